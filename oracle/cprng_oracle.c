@@ -1,0 +1,426 @@
+/*
+ * cprng_oracle.c -- CPU oracle for the chaotic-iteration PRNG hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, single-threaded
+ * definition that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product library never links, loads or calls it, and it shares no code,
+ * header, table or constant generator with the product library.
+ *
+ * Paper: Bahi, Couturier, Guyeux, Heam, "Efficient and Cryptographically
+ * Secure Generation of Chaotic Pseudorandom Numbers on GPU" (arXiv 1112.5239).
+ *
+ * What is computed (each function below cites the passage it follows):
+ *   - the chaotic-iteration step with vectorial negation, x^n = x^{n-1} xor S^n
+ *     (Section 4.2, Eq. "Oplus" and the general chaotic iterations that follow);
+ *   - strategy words S^n from Marsaglia xor-like generators (Algorithm 2 of
+ *     Section 4.1; the xorshift / xor128 / xorwow trio of Listing 1, Section 5);
+ *   - three variants:
+ *       V0 PLAIN  : one xor128 with 32-bit words as the strategy (Section 5,
+ *                   first idea; the object X of Section 8; Algorithm 4 with the
+ *                   neighbour exchange removed),
+ *       V1 NAIVE3 : Listing 1 per stream (Algorithm 3 of Section 6.1),
+ *       V2 SHMEM  : Algorithm 4 of Section 6.2 (xor128 per thread, mixed with
+ *                   two neighbours' previous words through a combination array);
+ *   - the in-kernel consumption mode (quarter-circle hit counts), a use of the
+ *     numbers in the spirit of the "versions without storage" of Section 7.
+ *
+ * Readings where the paper is silent or ambiguous (kept identical to the
+ * library's documented contract):
+ *   - seeding: SplitMix64 (Steele, Lea, Flood 2014) stands in for the ISAAC
+ *     initialiser of Section 6.1; stream s of base seed sigma starts its draw
+ *     counter at sigma*2^32 + s;
+ *   - Listing 1 uses 64-bit words (its text calls the three generators 64-bit);
+ *     a 32-bit-word variant (W=32) is kept as an option;
+ *   - the Listing 1 "xorshift" is the shift triple (13,17,5) of Algorithm 2;
+ *   - Algorithm 4 reads the neighbours' words of the previous step (all threads
+ *     of a group read, then all write), group size C = 32, combination arrays
+ *     drawn by Fisher-Yates from SplitMix64 as in orc_comb_tables();
+ *   - outputs are stream-major: out[s*n + i] (the printed index collides).
+ *
+ * Parity unpinned: the SplitMix64 multiplier constants (no known-answer value
+ * is printed in the paper); everything else is pinned by the test suite.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared (no fast-math).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+
+enum { ORC_V0 = 0, ORC_V1 = 1, ORC_V2 = 2 };
+
+/* ------------------------------------------------------------------------ */
+/* SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): a counter that advances by  */
+/* the odd integer nearest 2^64/phi, followed by a mixing finaliser.         */
+/* ------------------------------------------------------------------------ */
+#define ORC_SM64_GAMMA 0x9E3779B97F4A7C15ull
+
+uint64_t orc_sm64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static uint64_t sm64_draw(uint64_t *ctr)
+{
+    *ctr += ORC_SM64_GAMMA;
+    return orc_sm64_mix(*ctr);
+}
+
+/* n consecutive draws starting from counter value z (test helper). */
+void orc_sm64_draws(uint64_t z, uint64_t n, uint64_t *out)
+{
+    for (uint64_t i = 0; i < n; ++i) out[i] = sm64_draw(&z);
+}
+
+static uint64_t wmask(int W) { return W == 64 ? ~0ull : ((1ull << W) - 1ull); }
+
+/* ------------------------------------------------------------------------ */
+/* Strategy generators on W-bit words (W = 32 or 64).  Shifts discard the    */
+/* bits pushed out of the word; every operation is taken modulo 2^W.         */
+/* ------------------------------------------------------------------------ */
+
+/* One xorshift round with shift triple (a,b,c): Algorithm 2 (Section 4.1)
+ * is the case (13,17,5) on a 32-bit word.  Returns the new word. */
+uint64_t orc_xs_step(uint64_t *y, int a, int b, int c, int W)
+{
+    uint64_t m = wmask(W);
+    uint64_t z = *y & m;
+    z = z ^ ((z << a) & m);
+    z = z ^ (z >> b);
+    z = z ^ ((z << c) & m);
+    *y = z;
+    return z;
+}
+
+/* Marsaglia's xor128 (the generator named for Algorithm 4 in Section 6.2 and
+ * as the second generator of Listing 1).  s = {x,y,z,w}; returns new w. */
+uint64_t orc_x128_step(uint64_t s[4], int W)
+{
+    uint64_t m = wmask(W);
+    uint64_t t = s[0] ^ ((s[0] << 11) & m);
+    s[0] = s[1];
+    s[1] = s[2];
+    s[2] = s[3];
+    s[3] = (s[3] ^ (s[3] >> 19)) ^ (t ^ (t >> 8));
+    return s[3];
+}
+
+/* Marsaglia's xorwow (third generator of Listing 1).  s = {x,y,z,w,v,d};
+ * returns d + v after the Weyl increment of d. */
+uint64_t orc_xwow_step(uint64_t s[6], int W)
+{
+    uint64_t m = wmask(W);
+    uint64_t t = s[0] ^ (s[0] >> 2);
+    s[0] = s[1];
+    s[1] = s[2];
+    s[2] = s[3];
+    s[3] = s[4];
+    s[4] = (s[4] ^ ((s[4] << 4) & m)) ^ (t ^ ((t << 1) & m));
+    s[5] = (s[5] + 362437ull) & m;
+    return (s[5] + s[4]) & m;
+}
+
+/* n consecutive outputs of one generator from a given state (test helper).
+ * kind: 0 = xorshift(13,17,5), 1 = xor128, 2 = xorwow.  State is updated. */
+int orc_gen_outputs(int kind, int W, uint64_t *state, uint64_t n, uint64_t *out)
+{
+    if (W != 32 && W != 64) return ORC_EINVAL;
+    for (uint64_t i = 0; i < n; ++i) {
+        if (kind == 0)      out[i] = orc_xs_step(state, 13, 17, 5, W);
+        else if (kind == 1) out[i] = orc_x128_step(state, W);
+        else if (kind == 2) out[i] = orc_xwow_step(state, W);
+        else return ORC_EINVAL;
+    }
+    return ORC_OK;
+}
+
+/* Orbit length of Algorithm 2 from seed y0 on 32-bit words: steps until the
+ * word returns to y0, capped at limit.  *hit_zero is set if 0 is visited. */
+uint64_t orc_xs32_orbit(uint32_t y0, uint64_t limit, int *hit_zero)
+{
+    uint64_t y = y0, n = 0;
+    *hit_zero = 0;
+    do {
+        orc_xs_step(&y, 13, 17, 5, 32);
+        ++n;
+        if (y == 0) *hit_zero = 1;
+    } while (y != y0 && n < limit);
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The chaotic-iteration step (Section 4.2).  With f the vectorial negation,  */
+/* component k of x changes iff bit k of the strategy word S is 1, which is   */
+/* the bitwise exclusive or of Eq. (Oplus).                                   */
+/* ------------------------------------------------------------------------ */
+uint32_t orc_ci_step(uint32_t x, uint32_t S) { return x ^ S; }
+
+void orc_ci_step_batch(const uint32_t *x, const uint32_t *S, uint32_t *out, uint64_t n)
+{
+    for (uint64_t i = 0; i < n; ++i) out[i] = orc_ci_step(x[i], S[i]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-stream state, as 32-bit words (array of structures, stream by stream). */
+/*   V0: x128{x,y,z,w}, ci_x                                    (5 words)    */
+/*   V2: x128{x,y,z,w}, ci_x, t_prev                            (6 words)    */
+/*   V1: xs{lo,hi}, x128{x,y,z,w}{lo,hi}, xwow{x,y,z,w,v,d}{lo,hi}, ci_x     */
+/*                                                              (23 words)   */
+/* ------------------------------------------------------------------------ */
+int orc_state_words(int variant)
+{
+    switch (variant) {
+    case ORC_V0: return 5;
+    case ORC_V1: return 23;
+    case ORC_V2: return 6;
+    default: return ORC_EINVAL;
+    }
+}
+
+static uint64_t get64(const uint32_t *w, int k) { return (uint64_t)w[2 * k] | ((uint64_t)w[2 * k + 1] << 32); }
+static void put64(uint32_t *w, int k, uint64_t v) { w[2 * k] = (uint32_t)v; w[2 * k + 1] = (uint32_t)(v >> 32); }
+
+/* Seed streams first_stream .. first_stream+n_streams-1 of base seed sigma.
+ * Draw order: V0/V2 draw the four xor128 words (redrawn together until not
+ * all zero), then x, then (V2) the initial neighbour word.  V1 draws the
+ * xorshift word (until nonzero), the four xor128 words (until not all zero),
+ * the five xorwow words (until not all zero), the Weyl counter d, then x.
+ * W = 32 keeps the low 32 bits of each draw (rejection on the kept bits). */
+int orc_seed(int variant, int W, uint64_t sigma, uint64_t first_stream,
+             uint64_t n_streams, uint32_t *state)
+{
+    int nw = orc_state_words(variant);
+    if (nw < 0 || (W != 32 && W != 64)) return ORC_EINVAL;
+    uint64_t m = wmask(W);
+    for (uint64_t k = 0; k < n_streams; ++k) {
+        uint64_t ctr = (sigma << 32) + (first_stream + k);
+        uint32_t *st = state + k * (uint64_t)nw;
+        memset(st, 0, sizeof(uint32_t) * (size_t)nw);
+        if (variant == ORC_V0 || variant == ORC_V2) {
+            uint32_t a[4];
+            do {
+                for (int j = 0; j < 4; ++j) a[j] = (uint32_t)sm64_draw(&ctr);
+            } while ((a[0] | a[1] | a[2] | a[3]) == 0);
+            for (int j = 0; j < 4; ++j) st[j] = a[j];
+            st[4] = (uint32_t)sm64_draw(&ctr);
+            if (variant == ORC_V2) st[5] = (uint32_t)sm64_draw(&ctr);
+        } else {
+            uint64_t g1, g2[4], g3[6];
+            do { g1 = sm64_draw(&ctr) & m; } while (g1 == 0);
+            do {
+                for (int j = 0; j < 4; ++j) g2[j] = sm64_draw(&ctr) & m;
+            } while ((g2[0] | g2[1] | g2[2] | g2[3]) == 0);
+            do {
+                for (int j = 0; j < 5; ++j) g3[j] = sm64_draw(&ctr) & m;
+            } while ((g3[0] | g3[1] | g3[2] | g3[3] | g3[4]) == 0);
+            g3[5] = sm64_draw(&ctr) & m;
+            put64(st, 0, g1);
+            for (int j = 0; j < 4; ++j) put64(st, 1 + j, g2[j]);
+            for (int j = 0; j < 6; ++j) put64(st, 5 + j, g3[j]);
+            st[22] = (uint32_t)sm64_draw(&ctr);
+        }
+    }
+    return ORC_OK;
+}
+
+/* Combination arrays of Algorithm 4 (Section 6.2).  The paper gives neither C
+ * nor the arrays; the reading used here: two permutations of [0,C) drawn by
+ * Fisher-Yates (j = C-1 down to 1, swap with index draw mod (j+1)) from a
+ * SplitMix64 counter starting at 2^64-1, comb1 then comb2, redrawn (the same
+ * draw sequence continuing) until for every j: comb1[j] != j, comb2[j] != j
+ * and comb1[j] != comb2[j], so each thread mixes two distinct other threads. */
+int orc_comb_tables(uint32_t C, uint32_t *comb1, uint32_t *comb2)
+{
+    if (C < 3 || C > 4096) return ORC_EINVAL;
+    uint64_t ctr = ~0ull;
+    for (int attempt = 0; attempt < 1000000; ++attempt) {
+        uint32_t *arr[2] = {comb1, comb2};
+        for (int a = 0; a < 2; ++a) {
+            for (uint32_t j = 0; j < C; ++j) arr[a][j] = j;
+            for (uint32_t j = C - 1; j >= 1; --j) {
+                uint32_t k = (uint32_t)(sm64_draw(&ctr) % (uint64_t)(j + 1));
+                uint32_t tmp = arr[a][j];
+                arr[a][j] = arr[a][k];
+                arr[a][k] = tmp;
+            }
+        }
+        int ok = 1;
+        for (uint32_t j = 0; j < C; ++j)
+            if (comb1[j] == j || comb2[j] == j || comb1[j] == comb2[j]) ok = 0;
+        if (ok) return ORC_OK;
+    }
+    return ORC_EINVAL;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Generation.                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* V0: S = xor128 step on 32-bit words; x = x xor S; emit x (Eq. Oplus). */
+static void gen_v0_stream(uint32_t *st, uint64_t n, uint32_t *out, uint32_t *strat)
+{
+    uint64_t g[4] = {st[0], st[1], st[2], st[3]};
+    uint32_t x = st[4];
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t S = (uint32_t)orc_x128_step(g, 32);
+        x = orc_ci_step(x, S);
+        if (out) out[i] = x;
+        if (strat) strat[i] = S;
+    }
+    for (int j = 0; j < 4; ++j) st[j] = (uint32_t)g[j];
+    st[4] = x;
+}
+
+/* V1: Listing 1 per stream (Algorithm 3).  Each generator steps once per
+ * output; S is the xor of the low and high 32-bit halves of the three
+ * generator outputs, in the order the listing applies them. */
+static void gen_v1_stream(uint32_t *st, int W, uint64_t n, uint32_t *out, uint32_t *strat)
+{
+    uint64_t g1 = get64(st, 0), g2[4], g3[6];
+    for (int j = 0; j < 4; ++j) g2[j] = get64(st, 1 + j);
+    for (int j = 0; j < 6; ++j) g3[j] = get64(st, 5 + j);
+    uint32_t x = st[22];
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t t1 = orc_xs_step(&g1, 13, 17, 5, W);
+        uint64_t t2 = orc_x128_step(g2, W);
+        uint64_t t3 = orc_xwow_step(g3, W);
+        uint32_t S = 0;
+        S ^= (uint32_t)t1;
+        S ^= (uint32_t)(t2 >> 32);
+        S ^= (uint32_t)(t3 >> 32);
+        S ^= (uint32_t)t2;
+        S ^= (uint32_t)(t1 >> 32);
+        S ^= (uint32_t)t3;
+        x = orc_ci_step(x, S);
+        if (out) out[i] = x;
+        if (strat) strat[i] = S;
+    }
+    put64(st, 0, g1);
+    for (int j = 0; j < 4; ++j) put64(st, 1 + j, g2[j]);
+    for (int j = 0; j < 6; ++j) put64(st, 5 + j, g3[j]);
+    st[22] = x;
+}
+
+/* V2: Algorithm 4 on one group of C consecutive streams.  Thread j of the
+ * group reads the words that threads comb1[j] and comb2[j] of the same group
+ * produced at the previous step; every thread reads before any writes.
+ * out/strat are indexed [j*stride + i]. */
+static int gen_v2_group(uint32_t *st, uint32_t C, const uint32_t *comb1, const uint32_t *comb2,
+                        uint64_t n, uint32_t *out, uint32_t *strat, uint64_t stride)
+{
+    uint64_t (*g)[4] = malloc(sizeof(*g) * C);
+    uint32_t *tprev = malloc(sizeof(uint32_t) * C);
+    uint32_t *tnext = malloc(sizeof(uint32_t) * C);
+    uint32_t *u = malloc(sizeof(uint32_t) * C);
+    if (!g || !tprev || !tnext || !u) {
+        free(g); free(tprev); free(tnext); free(u);
+        return ORC_ENOMEM;
+    }
+    for (uint32_t j = 0; j < C; ++j) {
+        for (int k = 0; k < 4; ++k) g[j][k] = st[j * 6 + k];
+        tprev[j] = st[j * 6 + 5];
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+        for (uint32_t j = 0; j < C; ++j) u[j] = (uint32_t)orc_x128_step(g[j], 32);
+        for (uint32_t j = 0; j < C; ++j) tnext[j] = u[j] ^ tprev[comb1[j]] ^ tprev[comb2[j]];
+        for (uint32_t j = 0; j < C; ++j) {
+            tprev[j] = tnext[j];
+            uint32_t x = orc_ci_step(st[j * 6 + 4], tnext[j]);
+            st[j * 6 + 4] = x;
+            if (out) out[j * stride + i] = x;
+            if (strat) strat[j * stride + i] = tnext[j];
+        }
+    }
+    for (uint32_t j = 0; j < C; ++j) {
+        for (int k = 0; k < 4; ++k) st[j * 6 + k] = (uint32_t)g[j][k];
+        st[j * 6 + 5] = tprev[j];
+    }
+    free(g); free(tprev); free(tnext); free(u);
+    return ORC_OK;
+}
+
+/* Generate n outputs per stream for n_streams streams whose states are in
+ * `state` (updated in place, so a second call continues the streams).
+ * out (optional) and strat (optional, the strategy words S^n) are
+ * stream-major: [s*n + i].  V2 needs n_streams % C == 0 and the two
+ * combination arrays; W only matters for V1. */
+int orc_generate(int variant, int W, uint64_t n_streams, uint32_t *state, uint64_t n,
+                 uint32_t *out, uint32_t *strat, uint32_t C,
+                 const uint32_t *comb1, const uint32_t *comb2)
+{
+    int nw = orc_state_words(variant);
+    if (nw < 0 || (W != 32 && W != 64)) return ORC_EINVAL;
+    if (variant == ORC_V0) {
+        for (uint64_t s = 0; s < n_streams; ++s)
+            gen_v0_stream(state + s * 5, n, out ? out + s * n : NULL, strat ? strat + s * n : NULL);
+    } else if (variant == ORC_V1) {
+        for (uint64_t s = 0; s < n_streams; ++s)
+            gen_v1_stream(state + s * 23, W, n, out ? out + s * n : NULL, strat ? strat + s * n : NULL);
+    } else {
+        if (C == 0 || !comb1 || !comb2 || n_streams % C != 0) return ORC_EINVAL;
+        for (uint32_t j = 0; j < C; ++j)
+            if (comb1[j] >= C || comb2[j] >= C) return ORC_EINVAL;
+        for (uint64_t g0 = 0; g0 < n_streams; g0 += C) {
+            int rc = gen_v2_group(state + g0 * 6, C, comb1, comb2, n,
+                                  out ? out + g0 * n : NULL, strat ? strat + g0 * n : NULL, n);
+            if (rc) return rc;
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* In-kernel consumption: quarter-circle hit counts.                          */
+/* Outputs 2k and 2k+1 of a stream form a pair (r1, r2); each is turned into  */
+/* a float in [0,1) from its top 24 bits, u = (r >> 8) * 2^-24 (exact), and   */
+/* the pair is a hit iff fl(fl(u*u) + fl(v*v)) < 1 in IEEE binary32 with      */
+/* round-to-nearest-even and no fused multiply-add.                           */
+/* ------------------------------------------------------------------------ */
+static uint64_t count_hits(const uint32_t *r, uint64_t n)
+{
+    uint64_t hits = 0;
+    for (uint64_t k = 0; k + 1 < n; k += 2) {
+        float u = (float)(r[k] >> 8) * 0x1p-24f;
+        float v = (float)(r[k + 1] >> 8) * 0x1p-24f;
+        float uu = u * u;
+        float vv = v * v;
+        float s = uu + vv;
+        if (s < 1.0f) ++hits;
+    }
+    return hits;
+}
+
+/* counts[s] = hits among the n/2 pairs of stream s's next n outputs; the
+ * states advance by n exactly as orc_generate would.  n must be even. */
+int orc_consume_qc(int variant, int W, uint64_t n_streams, uint32_t *state, uint64_t n,
+                   uint64_t *counts, uint32_t C, const uint32_t *comb1, const uint32_t *comb2)
+{
+    int nw = orc_state_words(variant);
+    if (nw < 0 || (n & 1)) return ORC_EINVAL;
+    uint64_t group = (variant == ORC_V2) ? C : 1;
+    if (group == 0 || n_streams % group != 0) return ORC_EINVAL;
+    uint64_t words = group * n;
+    uint32_t *buf = malloc(sizeof(uint32_t) * (size_t)(words > 0 ? words : 1));
+    if (!buf) return ORC_ENOMEM;
+    for (uint64_t g0 = 0; g0 < n_streams; g0 += group) {
+        int rc = orc_generate(variant, W, group, state + g0 * (uint64_t)nw, n, buf, NULL, C, comb1, comb2);
+        if (rc) { free(buf); return rc; }
+        for (uint64_t j = 0; j < group; ++j) counts[g0 + j] = count_hits(buf + j * n, n);
+    }
+    free(buf);
+    return ORC_OK;
+}
+
+/* Float predicate of one pair, exposed for tests. */
+int orc_qc_hit(uint32_t r1, uint32_t r2)
+{
+    uint32_t r[2] = {r1, r2};
+    return (int)count_hits(r, 2);
+}
