@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X chaotic-iteration PRNG.
+
+One step = one cprng_generate call of the paper-shaped workload: the
+neighbour-exchange variant (Algorithm 4) on 2^20 streams x 1,024 uint32
+outputs (4 GiB written to HBM), states seeded from SplitMix64 with seed 1 and
+already resident on the device.  Prints ONE JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extra] [--no-cpu-baseline]
+    python bench.py --workload serving [--duration 60]
+
+Secondary measurements (same JSON line, "extra"): plain variants V0 and V1 at
+the same shape, batched uneven streams (4,096 streams, log-uniform lengths in
+[1e3, 1e7], one hipGraph launch), in-kernel consumption (2^36 numbers), and
+the store-only fill probe.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+VALU_INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CU x 64 lanes/clk x 2.4 GHz = 39.3 Tops/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    with open(os.path.join(ROOT, "paper_1112_5239_amd", "csrc", "cprng_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_tag):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def cpu_baseline_paper(budget_s=12.0):
+    """The oracle, single-threaded, on a bounded sample of the same workload."""
+    from oracle import oracle as O
+    comb = O.comb_tables(32)
+    batch = 8192
+    done = 0
+    t0 = time.perf_counter()
+    O.generate(2, O.seed(2, 1, 0, 32), 16, comb=comb)       # load / warm
+    t0 = time.perf_counter()
+    elapsed = 0.0
+    while elapsed < budget_s and done < (1 << 20):
+        st = O.seed(2, 1, done, batch)
+        t1 = time.perf_counter()
+        O.generate(2, st, 1024, comb=comb)
+        elapsed += time.perf_counter() - t1
+        done += batch
+    return {"value": done * 1024 / elapsed / 1e9, "unit": "Gnumbers/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} of the 2^20 streams x 1024 outputs (exchange variant, seed 1), "
+                      f"{elapsed:.1f} s of single-thread CPU time"}
+
+
+def run_paper(torch, G, L, args):
+    ns, n = 1 << 20, 1024
+    log(f"[bench] paper workload: V2, {ns} streams x {n}, seed 1")
+    g = G.Generator(ns, "v2", seed=1)
+    out = torch.empty((ns, n), dtype=torch.int32, device="cuda")
+    ms, wall = timed(torch, lambda: g.generate(n, out=out), args.steps, args.warmup)
+    numbers = ns * n
+    alg_bytes = numbers * 4 + ns * 6 * 4 * 2
+    achieved = alg_bytes / (ms / 1e3) / 1e9
+    g.close()
+    del out
+    return ms, wall, numbers, alg_bytes, achieved
+
+
+def run_plain(torch, G, variant, args):
+    ns, n = 1 << 20, 1024
+    words = {"v0": 5, "v1": 23}[variant]
+    g = G.Generator(ns, variant, seed=1)
+    out = torch.empty((ns, n), dtype=torch.int32, device="cuda")
+    ms, _ = timed(torch, lambda: g.generate(n, out=out), max(5, args.steps // 2), 2)
+    g.close()
+    del out
+    gn = ns * n / (ms / 1e3) / 1e9
+    byts = ns * n * 4 + ns * words * 8
+    return {"workload": f"{variant}: 2^20 streams x 1024, seed 1", "ms": round(ms, 4),
+            "gnumbers_per_s": round(gn, 2), "hbm_gbs": round(byts / (ms / 1e3) / 1e9, 1),
+            "frac_hbm_peak": round(byts / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def run_ragged(torch, G, args, ref_v0_gn):
+    from paper_1112_5239_amd import workloads
+    lengths = workloads.ragged_lengths()
+    ns = lengths.size
+    total = int(lengths.sum())
+    g = G.Generator(ns, "v0", seed=2)
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    if args.autotune:
+        g.autotune_ragged(lengths, out=out)
+    ms, _ = timed(torch, lambda: g.generate_ragged(lengths, out=out), max(5, args.steps // 4), 2)
+    g.close()
+    del out
+    gn = total / (ms / 1e3) / 1e9
+    return {"workload": f"4096 streams, log-uniform lengths [1e3,1e7] (total {total}), seed 2, "
+                        "one hipGraph launch", "ms": round(ms, 4), "gnumbers_per_s": round(gn, 2),
+            "hbm_gbs": round(total * 4 / (ms / 1e3) / 1e9, 1),
+            "frac_hbm_peak": round(total * 4 / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "ratio_to_plain_v0": round(gn / ref_v0_gn, 4) if ref_v0_gn else None}
+
+
+def run_consume(torch, G, args):
+    ns, n = 1 << 20, 1 << 16
+    res = {}
+    for variant, ops in (("v2", 15.5), ("v0", 13.5)):
+        g = G.Generator(ns, variant, seed=3)
+        counts = torch.empty(ns, dtype=torch.int64, device="cuda")
+        ms, _ = timed(torch, lambda: g.consume_qc(n, counts=counts), 3, 1)
+        g.close()
+        gn = ns * n / (ms / 1e3) / 1e9
+        res[variant] = {"ms": round(ms, 3), "gnumbers_per_s": round(gn, 1),
+                        "valu_ops_per_number": ops,
+                        "frac_valu_peak": round(gn * 1e9 * ops / (VALU_INT32_PEAK_TOPS * 1e12), 4)}
+    return {"workload": "2^36 uint32 (2^20 streams x 2^16) -> quarter-circle hit counts, seed 3", **res}
+
+
+def run_fill_probe(torch, L):
+    n_words = 1 << 30
+    buf = torch.empty(n_words, dtype=torch.int32, device="cuda")
+    ms, _ = timed(torch, lambda: L.cprng_probe_fill(buf, n_words, 7,
+                                                      torch.cuda.current_stream().cuda_stream), 10, 2)
+    del buf
+    return {"bytes": n_words * 4, "ms": round(ms, 4), "gbs": round(n_words * 4 / (ms / 1e3) / 1e9, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="paper", choices=["paper", "serving"])
+    ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the streams shard with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    from paper_1112_5239_amd import _lib as L
+    from paper_1112_5239_amd import generator as G
+    L.lib()
+
+    if args.workload == "serving":
+        from paper_1112_5239_amd import serving
+        res = serving.bench_line(args)
+        print(json.dumps(res), flush=True)
+        return
+
+    ms, wall, numbers, alg_bytes, achieved = run_paper(torch, G, L, args)
+    value = numbers / (ms / 1e3) / 1e9
+    log(f"[bench] paper: {ms:.4f} ms/step, {value:.1f} Gnumbers/s, {achieved:.0f} GB/s")
+    extra = {}
+    if not args.no_extra:
+        extra["v0_plain"] = run_plain(torch, G, "v0", args)
+        log(f"[bench] v0: {extra['v0_plain']}")
+        extra["v1_naive3"] = run_plain(torch, G, "v1", args)
+        log(f"[bench] v1: {extra['v1_naive3']}")
+        extra["ragged"] = run_ragged(torch, G, args, extra["v0_plain"]["gnumbers_per_s"])
+        log(f"[bench] ragged: {extra['ragged']}")
+        extra["consume"] = run_consume(torch, G, args)
+        log(f"[bench] consume: {extra['consume']}")
+        extra["fill_probe"] = run_fill_probe(torch, L)
+        log(f"[bench] fill probe: {extra['fill_probe']}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_paper()
+        log(f"[bench] cpu baseline: {cpu}")
+    line = {
+        "metric": "Gnumbers/s (uint32 to HBM) at 1 GPU, % HBM write peak; plain vs batched",
+        "value": round(value, 3),
+        "unit": "Gnumbers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "paper-shaped neighbour-exchange variant (Algorithm 4): 2^20 streams "
+                               "x 1024 uint32 outputs (4 GiB), SplitMix64 seed 1, group 32",
+                   "n_streams": 1 << 20, "n_per_stream": 1024, "variant": "v2"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profile("k_generate_v2_paper"),
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,247 @@
+/*
+ * cprng.h -- C ABI of the MI355X (gfx950) chaotic-iteration PRNG library.
+ *
+ * The library generates, for many independent streams at once, the
+ * pseudorandom numbers of the chaotic-iteration generator of Bahi, Couturier,
+ * Guyeux and Heam (arXiv 1112.5239): each stream keeps a 32-bit state x and
+ * applies x <- x xor S for a strategy word S drawn from Marsaglia xor-like
+ * generators (Section 4.2, Eq. "Oplus"; Section 5; Section 6).
+ *
+ * Conventions for every entry point:
+ *  - Return value: CPRNG_OK (0) or a negative cprng_status.  Nothing throws
+ *    across this boundary.  cprng_last_error() gives a human-readable detail
+ *    of the last failure on the calling thread.
+ *  - Pointers documented "device" are HIP device addresses (for example a
+ *    torch tensor's data_ptr()); "host" pointers are ordinary host memory.
+ *    The caller owns every buffer it passes; the handle owns only its own
+ *    device state and work lists.
+ *  - Calls that take a stream are asynchronous on that HIP stream (NULL = the
+ *    null stream).  A handle's state advances in stream order; calls on one
+ *    handle must be ordered on one stream and a handle is not thread-safe.
+ *  - Outputs are 32-bit unsigned integers.  Unless CPRNG_F_INTERLEAVED is
+ *    set, output i of stream s of one call is out[s * n_per_stream + i].
+ *  - Successive calls continue the streams: two calls of a and b outputs give
+ *    the same numbers as one call of a + b.
+ */
+#ifndef CPRNG_H
+#define CPRNG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* hipStream_t is a pointer to this opaque type in the HIP runtime. */
+typedef struct ihipStream_t *cprng_stream_t;
+
+typedef struct cprng cprng_t;
+
+/* Variant in the low byte of `variant`, flags above it. */
+enum cprng_variant {
+    /* Eq. (Oplus) with one xor128 (32-bit words) as the strategy (Section 5,
+     * first idea; the construction X of Section 8).  5 state words/stream. */
+    CPRNG_V0_PLAIN = 0,
+    /* Listing 1 / Algorithm 3 (Section 6.1): xorshift(13,17,5), xor128 and
+     * xorwow on 64-bit words; S is the xor of their six 32-bit halves.
+     * 23 state words/stream. */
+    CPRNG_V1_NAIVE3 = 1,
+    /* Algorithm 4 (Section 6.2): one xor128 per stream mixed with the previous
+     * words of two other streams of its group of C streams, chosen by two
+     * combination arrays.  6 state words/stream.  Needs n_streams % C == 0. */
+    CPRNG_V2_SHMEM = 2
+};
+
+enum cprng_flags {
+    /* Output i of stream s goes to out[i * n_streams + s]. */
+    CPRNG_F_INTERLEAVED = 1u << 8,
+    /* V1 only: the three generators use 32-bit words (high halves are 0). */
+    CPRNG_F_V1_W32 = 1u << 9
+};
+
+enum cprng_status {
+    CPRNG_OK = 0,
+    CPRNG_E_INVAL = -1,        /* bad argument (NULL pointer, size, variant) */
+    CPRNG_E_NOMEM = -2,        /* device or host allocation failed */
+    CPRNG_E_HIP = -3,          /* a HIP runtime call or launch failed */
+    CPRNG_E_UNSUPPORTED = -4   /* valid request that this build does not do */
+};
+
+/* Parameters of cprng_create_ex().  Zero-initialise, then set fields. */
+typedef struct cprng_params {
+    uint32_t struct_size;      /* sizeof(cprng_params_t) */
+    uint32_t variant;          /* cprng_variant | cprng_flags */
+    uint32_t n_streams;        /* >= 1 */
+    uint32_t group;            /* V2 group size C; 0 = 32.  Must divide 64. */
+    uint64_t seed;             /* base seed sigma */
+    const uint32_t *comb1;     /* host, `group` entries in [0,C); NULL = default */
+    const uint32_t *comb2;     /* host, `group` entries in [0,C); NULL = default */
+    int32_t device;            /* HIP device ordinal; -1 = current device */
+    uint32_t reserved;
+} cprng_params_t;
+
+/* ------------------------------------------------------------------------ */
+/* Lifecycle.                                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Create a generator of n_streams streams on the current HIP device.
+ * seeds: host, one uint64 base seed sigma.  Stream s is initialised from
+ * SplitMix64 draws whose counter starts at sigma*2^32 + s (the paper seeds
+ * per-thread parameters on the host with ISAAC, Section 6.1); generator
+ * words that would all be zero are redrawn.  V2 uses group size 32 and the
+ * library's default combination arrays.  The state lives in device memory
+ * owned by the handle.  Errors: E_INVAL (NULL, n_streams == 0, unknown
+ * variant, V2 with n_streams % 32 != 0), E_NOMEM, E_HIP. */
+int cprng_create(const uint64_t *seeds, uint32_t n_streams, uint32_t variant, cprng_t **out);
+
+/* As cprng_create with explicit group size, combination arrays and device.
+ * Combination arrays follow Algorithm 4: stream j of a group mixes the
+ * previous words of streams comb1[j mod C] and comb2[j mod C] of its group. */
+int cprng_create_ex(const cprng_params_t *params, cprng_t **out);
+
+/* Wait for the handle's pending work, free its device memory and the handle.
+ * NULL is a no-op. */
+void cprng_destroy(cprng_t *h);
+
+/* ------------------------------------------------------------------------ */
+/* Hot path.                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Generate n_per_stream outputs for every stream into out (device,
+ * n_streams * n_per_stream uint32, 4-byte aligned; 16-byte alignment and
+ * n_per_stream % 4 == 0 select the fast store path).  Each output is the new
+ * state x after one chaotic iteration x <- x xor S (Section 4.2), with S as
+ * the variant defines it; the state is written back at the end, as the GPU
+ * kernels of Section 6 do.  n_per_stream == 0 is a no-op.
+ * Errors: E_INVAL, E_HIP. */
+int cprng_generate(cprng_t *h, uint32_t *out, uint64_t n_per_stream, cprng_stream_t stream);
+
+/* In-kernel consumption (numbers used directly after generation, as in the
+ * storage-free runs of Section 7): advance every stream by n_per_stream
+ * outputs without storing them.  Outputs 2k and 2k+1 of a stream form a pair
+ * (r1, r2) mapped to binary32 u = (r1 >> 8) * 2^-24, v = (r2 >> 8) * 2^-24;
+ * the pair is a hit iff fl(fl(u*u) + fl(v*v)) < 1 (round to nearest even, no
+ * fused multiply-add).  counts (device, n_streams uint64) receives each
+ * stream's hit count for this call (overwritten).  n_per_stream must be even.
+ * Errors: E_INVAL, E_HIP. */
+int cprng_consume_qc(cprng_t *h, uint64_t *counts, uint64_t n_per_stream, cprng_stream_t stream);
+
+/* Batched uneven streams (V0 only).  Stream s writes its next lengths[s]
+ * outputs to out[offsets[s] .. offsets[s] + lengths[s]) (device, 4-byte
+ * aligned, no other alignment needed); offsets == NULL means the exclusive
+ * prefix sum of lengths.  lengths/offsets: host, n_streams entries each.
+ * Long streams are split into chunks that start from a jumped-ahead state:
+ * the strategy generator and the x chain are linear over GF(2), so the state
+ * after J steps is a polynomial in the one-step map (x^J modulo the minimal
+ * polynomial), and the x chain is the prefix-xor of the strategy words
+ * (construction X of Section 8).  The call runs as one hipGraph launch of a
+ * persistent kernel; the graph is built on the first call with a given
+ * (lengths, offsets, out) and replayed afterwards.  Results equal those of
+ * each stream generated alone.  Errors: E_INVAL, E_UNSUPPORTED (V1, V2,
+ * interleaved flag), E_NOMEM, E_HIP. */
+int cprng_generate_ragged(cprng_t *h, uint32_t *out, const uint64_t *lengths,
+                          const uint64_t *offsets, cprng_stream_t stream);
+
+/* One request of cprng_generate_requests(). */
+typedef struct cprng_request {
+    uint32_t stream;           /* stream id < n_streams */
+    uint32_t reserved;
+    uint64_t length;           /* outputs to produce (0 allowed) */
+    uint32_t *out;             /* device, 4-byte aligned, `length` uint32 */
+} cprng_request_t;
+
+/* Serve a batch of requests (V0 only): request r receives the next `length`
+ * outputs of its stream; several requests of one stream are served in array
+ * order, one after the other.  Streams without a request keep their state.
+ * reqs: host, count entries.  Same chunking and jump-ahead as
+ * cprng_generate_ragged, one kernel launch per call.  Errors: E_INVAL,
+ * E_UNSUPPORTED (V1, V2), E_NOMEM, E_HIP. */
+int cprng_generate_requests(cprng_t *h, const cprng_request_t *reqs, uint32_t count,
+                            cprng_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* State (checkpoint / resume).                                              */
+/* ------------------------------------------------------------------------ */
+
+/* 32-bit words of state per stream: V0 5 {x128 x,y,z,w, x}, V2 6 {x128
+ * x,y,z,w, x, previous mixed word}, V1 23 {xorshift lo,hi; xor128 x,y,z,w
+ * as lo,hi; xorwow x,y,z,w,v,d as lo,hi; x}.  Returns < 0 on a bad handle. */
+int cprng_state_words(const cprng_t *h);
+
+/* Copy all states to / from host memory, stream after stream, each stream's
+ * words in the order above (host, n_streams * state_words uint32).  These
+ * calls synchronise the device.  set_state rejects generator words that are
+ * all zero (E_INVAL).  Errors: E_INVAL, E_HIP. */
+int cprng_get_state(cprng_t *h, uint32_t *host_words, size_t n_words);
+int cprng_set_state(cprng_t *h, const uint32_t *host_words, size_t n_words);
+
+/* ------------------------------------------------------------------------ */
+/* Introspection and tuning.                                                 */
+/* ------------------------------------------------------------------------ */
+
+uint32_t cprng_n_streams(const cprng_t *h);
+uint32_t cprng_variant(const cprng_t *h);
+
+/* Library's default V2 combination arrays for group size C (3 <= C <= 64,
+ * C dividing 64): two permutations of [0,C) with comb1[j] != j,
+ * comb2[j] != j and comb1[j] != comb2[j].  comb1/comb2: host, C entries. */
+int cprng_default_combs(uint32_t C, uint32_t *comb1, uint32_t *comb2);
+
+/* Kernel configuration used by the hot-path entry points.  Zero fields mean
+ * "autotuned / default".  store: 0 auto, 1 per-lane direct, 2 LDS-transposed,
+ * 3 direct non-temporal, 4 LDS-transposed non-temporal. */
+typedef struct cprng_tuning {
+    uint32_t block;            /* threads per block (64..1024, multiple of 64) */
+    uint32_t unroll;           /* outputs per lane per round: 4, 8, 16 or 32 */
+    uint32_t store;            /* store mode, see above */
+    uint32_t chunk;            /* ragged/requests: outputs per chunk (multiple of 64) */
+    uint32_t waves_per_cu;     /* ragged/requests: persistent waves per CU */
+    uint32_t reserved[3];
+} cprng_tuning_t;
+
+int cprng_set_tuning(cprng_t *h, const cprng_tuning_t *t);
+int cprng_get_tuning(const cprng_t *h, cprng_tuning_t *t);
+
+/* Time each candidate configuration of cprng_generate for n_per_stream on
+ * this handle (the streams advance while tuning), keep the fastest, and
+ * record it in the JSON cache file named by $CPRNG_TUNE_CACHE if set.
+ * scratch: device buffer big enough for one generate call.  Errors: E_INVAL,
+ * E_HIP. */
+int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n_per_stream, cprng_stream_t stream);
+
+/* Same for cprng_generate_ragged with the given lengths (chunk length and
+ * persistent wave count).  Errors as cprng_generate_ragged. */
+int cprng_autotune_ragged(cprng_t *h, uint32_t *out, const uint64_t *lengths,
+                          const uint64_t *offsets, cprng_stream_t stream);
+
+/* Average device time in milliseconds of the last kernel launched by the
+ * most recent hot-path call on this handle, when timing is enabled with
+ * cprng_enable_timing(h, 1) (events recorded on the call's stream around the
+ * kernel).  Returns < 0 if unavailable. */
+int cprng_enable_timing(cprng_t *h, int on);
+double cprng_last_kernel_ms(cprng_t *h);
+
+/* ------------------------------------------------------------------------ */
+/* Measurement probes (not part of the generator).                           */
+/* ------------------------------------------------------------------------ */
+
+/* Fill dst (device, n_words uint32, 16-byte aligned) with `value` using
+ * coalesced 16-byte stores: the store-only bandwidth reference. */
+int cprng_probe_fill(uint32_t *dst, uint64_t n_words, uint32_t value, cprng_stream_t stream);
+
+/* Copy n_words uint32 from src to dst (device, 16-byte aligned): the copy
+ * kernel used to calibrate hardware byte counters. */
+int cprng_probe_copy(uint32_t *dst, const uint32_t *src, uint64_t n_words, cprng_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Errors.                                                                   */
+/* ------------------------------------------------------------------------ */
+const char *cprng_strerror(int status);
+const char *cprng_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPRNG_H */

@@ -1,0 +1,244 @@
+"""ctypes binding of libcprng.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and raises
+CprngError when the call returns a negative status.  There is no fallback:
+if the HIP library is not built, loading fails with an error.
+"""
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libcprng.so")
+
+V0_PLAIN, V1_NAIVE3, V2_SHMEM = 0, 1, 2
+F_INTERLEAVED = 1 << 8
+F_V1_W32 = 1 << 9
+
+OK, E_INVAL, E_NOMEM, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4
+
+STORE_AUTO, STORE_DIRECT, STORE_LDS, STORE_DIRECT_NT, STORE_LDS_NT = 0, 1, 2, 3, 4
+
+
+class CprngError(RuntimeError):
+    def __init__(self, status, where, detail):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("variant", C.c_uint32), ("n_streams", C.c_uint32),
+                ("group", C.c_uint32), ("seed", C.c_uint64), ("comb1", C.POINTER(C.c_uint32)),
+                ("comb2", C.POINTER(C.c_uint32)), ("device", C.c_int32), ("reserved", C.c_uint32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("stream", C.c_uint32), ("reserved", C.c_uint32), ("length", C.c_uint64),
+                ("out", C.c_void_p)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("block", C.c_uint32), ("unroll", C.c_uint32), ("store", C.c_uint32),
+                ("chunk", C.c_uint32), ("waves_per_cu", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+
+
+EXPORTED = [
+    "cprng_create", "cprng_create_ex", "cprng_destroy", "cprng_generate", "cprng_consume_qc",
+    "cprng_generate_ragged", "cprng_generate_requests", "cprng_state_words", "cprng_get_state",
+    "cprng_set_state", "cprng_n_streams", "cprng_variant", "cprng_default_combs",
+    "cprng_set_tuning", "cprng_get_tuning", "cprng_autotune", "cprng_autotune_ragged",
+    "cprng_enable_timing", "cprng_last_kernel_ms", "cprng_probe_fill", "cprng_probe_copy",
+    "cprng_strerror", "cprng_last_error",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libcprng.so (raises OSError if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError(f"{LIB_PATH} is not built; run paper_1112_5239_amd/build.py "
+                      "(the HIP library has no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
+    sig = {
+        "cprng_create": (i32, [vp, u32, u32, vp]),
+        "cprng_create_ex": (i32, [C.POINTER(Params), vp]),
+        "cprng_destroy": (None, [vp]),
+        "cprng_generate": (i32, [vp, vp, u64, vp]),
+        "cprng_consume_qc": (i32, [vp, vp, u64, vp]),
+        "cprng_generate_ragged": (i32, [vp, vp, vp, vp, vp]),
+        "cprng_generate_requests": (i32, [vp, C.POINTER(Request), u32, vp]),
+        "cprng_state_words": (i32, [vp]),
+        "cprng_get_state": (i32, [vp, vp, C.c_size_t]),
+        "cprng_set_state": (i32, [vp, vp, C.c_size_t]),
+        "cprng_n_streams": (u32, [vp]),
+        "cprng_variant": (u32, [vp]),
+        "cprng_default_combs": (i32, [u32, vp, vp]),
+        "cprng_set_tuning": (i32, [vp, C.POINTER(Tuning)]),
+        "cprng_get_tuning": (i32, [vp, C.POINTER(Tuning)]),
+        "cprng_autotune": (i32, [vp, vp, u64, vp]),
+        "cprng_autotune_ragged": (i32, [vp, vp, vp, vp, vp]),
+        "cprng_enable_timing": (i32, [vp, i32]),
+        "cprng_last_kernel_ms": (C.c_double, [vp]),
+        "cprng_probe_fill": (i32, [vp, u64, u32, vp]),
+        "cprng_probe_copy": (i32, [vp, vp, u64, vp]),
+        "cprng_strerror": (C.c_char_p, [i32]),
+        "cprng_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc, where):
+    if rc < 0:
+        L = lib()
+        raise CprngError(rc, where, f"{L.cprng_strerror(rc).decode()}: {L.cprng_last_error().decode()}")
+    return rc
+
+
+def _addr(x):
+    """Device or host address of a torch tensor, numpy array, int or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if hasattr(x, "ctypes"):
+        return x.ctypes.data
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def cprng_create(seed: int, n_streams: int, variant: int) -> int:
+    h = C.c_void_p()
+    s = (C.c_uint64 * 1)(seed)
+    _check(lib().cprng_create(C.cast(s, C.c_void_p), n_streams, variant, C.byref(h)), "cprng_create")
+    return h.value
+
+
+def cprng_create_ex(variant: int, n_streams: int, seed: int, group: int = 0, comb1=None, comb2=None,
+                    device: int = -1) -> int:
+    p = Params()
+    p.struct_size = C.sizeof(Params)
+    p.variant = variant
+    p.n_streams = n_streams
+    p.group = group
+    p.seed = seed
+    p.device = device
+    keep = []
+    if comb1 is not None:
+        a1 = (C.c_uint32 * len(comb1))(*[int(v) for v in comb1])
+        a2 = (C.c_uint32 * len(comb2))(*[int(v) for v in comb2])
+        keep += [a1, a2]
+        p.comb1 = C.cast(a1, C.POINTER(C.c_uint32))
+        p.comb2 = C.cast(a2, C.POINTER(C.c_uint32))
+    h = C.c_void_p()
+    _check(lib().cprng_create_ex(C.byref(p), C.byref(h)), "cprng_create_ex")
+    return h.value
+
+
+def cprng_destroy(h: int) -> None:
+    lib().cprng_destroy(h)
+
+
+def cprng_generate(h: int, out, n_per_stream: int, stream=None) -> None:
+    _check(lib().cprng_generate(h, _addr(out), n_per_stream, _addr(stream)), "cprng_generate")
+
+
+def cprng_consume_qc(h: int, counts, n_per_stream: int, stream=None) -> None:
+    _check(lib().cprng_consume_qc(h, _addr(counts), n_per_stream, _addr(stream)), "cprng_consume_qc")
+
+
+def cprng_generate_ragged(h: int, out, lengths, offsets=None, stream=None) -> None:
+    """lengths/offsets: host uint64 numpy arrays of n_streams entries."""
+    _check(lib().cprng_generate_ragged(h, _addr(out), _addr(lengths), _addr(offsets), _addr(stream)),
+           "cprng_generate_ragged")
+
+
+def cprng_generate_requests(h: int, reqs, stream=None) -> None:
+    """reqs: sequence of (stream_id, length, out) with out a device address or tensor."""
+    arr = (Request * max(1, len(reqs)))()
+    for i, (s, n, o) in enumerate(reqs):
+        arr[i].stream = s
+        arr[i].length = n
+        arr[i].out = _addr(o)
+    _check(lib().cprng_generate_requests(h, arr, len(reqs), _addr(stream)), "cprng_generate_requests")
+
+
+def cprng_state_words(h: int) -> int:
+    return _check(lib().cprng_state_words(h), "cprng_state_words")
+
+
+def cprng_get_state(h: int, host_words) -> None:
+    _check(lib().cprng_get_state(h, _addr(host_words), host_words.size), "cprng_get_state")
+
+
+def cprng_set_state(h: int, host_words) -> None:
+    _check(lib().cprng_set_state(h, _addr(host_words), host_words.size), "cprng_set_state")
+
+
+def cprng_n_streams(h: int) -> int:
+    return int(lib().cprng_n_streams(h))
+
+
+def cprng_variant(h: int) -> int:
+    return int(lib().cprng_variant(h))
+
+
+def cprng_default_combs(Cg: int):
+    a1 = (C.c_uint32 * Cg)()
+    a2 = (C.c_uint32 * Cg)()
+    _check(lib().cprng_default_combs(Cg, C.cast(a1, C.c_void_p), C.cast(a2, C.c_void_p)), "cprng_default_combs")
+    return list(a1), list(a2)
+
+
+def cprng_set_tuning(h: int, block=0, unroll=0, store=0, chunk=0, waves_per_cu=0) -> None:
+    t = Tuning(block, unroll, store, chunk, waves_per_cu)
+    _check(lib().cprng_set_tuning(h, C.byref(t)), "cprng_set_tuning")
+
+
+def cprng_get_tuning(h: int) -> dict:
+    t = Tuning()
+    _check(lib().cprng_get_tuning(h, C.byref(t)), "cprng_get_tuning")
+    return {"block": t.block, "unroll": t.unroll, "store": t.store, "chunk": t.chunk,
+            "waves_per_cu": t.waves_per_cu}
+
+
+def cprng_autotune(h: int, scratch, n_per_stream: int, stream=None) -> None:
+    _check(lib().cprng_autotune(h, _addr(scratch), n_per_stream, _addr(stream)), "cprng_autotune")
+
+
+def cprng_autotune_ragged(h: int, out, lengths, offsets=None, stream=None) -> None:
+    _check(lib().cprng_autotune_ragged(h, _addr(out), _addr(lengths), _addr(offsets), _addr(stream)),
+           "cprng_autotune_ragged")
+
+
+def cprng_enable_timing(h: int, on: bool) -> None:
+    _check(lib().cprng_enable_timing(h, 1 if on else 0), "cprng_enable_timing")
+
+
+def cprng_last_kernel_ms(h: int) -> float:
+    return float(lib().cprng_last_kernel_ms(h))
+
+
+def cprng_probe_fill(dst, n_words: int, value: int, stream=None) -> None:
+    _check(lib().cprng_probe_fill(_addr(dst), n_words, value, _addr(stream)), "cprng_probe_fill")
+
+
+def cprng_probe_copy(dst, src, n_words: int, stream=None) -> None:
+    _check(lib().cprng_probe_copy(_addr(dst), _addr(src), n_words, _addr(stream)), "cprng_probe_copy")
+
+
+def cprng_strerror(status: int) -> str:
+    return lib().cprng_strerror(status).decode()
+
+
+def cprng_last_error() -> str:
+    return lib().cprng_last_error().decode()

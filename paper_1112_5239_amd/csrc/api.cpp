@@ -1,0 +1,393 @@
+// api.cpp -- C ABI of the chaotic-iteration PRNG library (lifecycle, plain
+// generation, consumption, state, tuning, timing, probes).
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "host.h"
+#include "tune.h"
+
+using namespace cprng_impl;
+
+namespace cprng_impl {
+
+static thread_local std::string g_last_error;
+
+int set_error(int status, const std::string &detail)
+{
+    g_last_error = detail;
+    return status;
+}
+
+int hip_error(hipError_t e, const char *what)
+{
+    return set_error(CPRNG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace cprng_impl
+
+#define HIP_TRY(call, what)                                    \
+    do {                                                       \
+        hipError_t _e = (call);                                \
+        if (_e != hipSuccess) return hip_error(_e, what);      \
+    } while (0)
+
+namespace {
+
+// Make the handle's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+bool is_pow2(uint32_t v) { return v && !(v & (v - 1)); }
+
+void fill_args(const cprng_t *h, GenArgs &a)
+{
+    std::memset(&a, 0, sizeof a);
+    a.state = h->d_state;
+    a.ns = h->ns;
+    a.group = h->group ? h->group : 1;
+    std::memcpy(a.comb1, h->comb1, 64);
+    std::memcpy(a.comb2, h->comb2, 64);
+}
+
+int begin_timing(cprng_t *h, hipStream_t st)
+{
+    if (!h->timing) return CPRNG_OK;
+    HIP_TRY(hipEventRecord(h->ev0, st), "hipEventRecord");
+    return CPRNG_OK;
+}
+
+int end_timing(cprng_t *h, hipStream_t st)
+{
+    if (!h->timing) return CPRNG_OK;
+    HIP_TRY(hipEventRecord(h->ev1, st), "hipEventRecord");
+    h->ev_pending = true;
+    return CPRNG_OK;
+}
+
+int create_impl(const cprng_params_t *p, cprng_t **out)
+{
+    if (!p || !out) return set_error(CPRNG_E_INVAL, "NULL params or output handle");
+    *out = nullptr;
+    if (p->struct_size < sizeof(cprng_params_t))
+        return set_error(CPRNG_E_INVAL, "cprng_params_t.struct_size too small");
+    const uint32_t var = p->variant & 0xffu;
+    const uint32_t flags = p->variant & ~0xffu;
+    if (words_per_stream((int)var) < 0) return set_error(CPRNG_E_INVAL, "unknown variant");
+    if (flags & ~(uint32_t)(CPRNG_F_INTERLEAVED | CPRNG_F_V1_W32))
+        return set_error(CPRNG_E_INVAL, "unknown flag bits");
+    if ((flags & CPRNG_F_V1_W32) && var != CPRNG_V1_NAIVE3)
+        return set_error(CPRNG_E_INVAL, "CPRNG_F_V1_W32 applies to the V1 variant only");
+    if (p->n_streams == 0) return set_error(CPRNG_E_INVAL, "n_streams must be >= 1");
+
+    std::unique_ptr<cprng> h(new cprng());
+    h->variant = var;
+    h->flags = flags;
+    h->ns = p->n_streams;
+    h->words = (uint32_t)words_per_stream((int)var);
+
+    if (var == CPRNG_V2_SHMEM) {
+        const uint32_t C = p->group ? p->group : 32u;
+        if (!is_pow2(C) || C > 64)
+            return set_error(CPRNG_E_UNSUPPORTED, "V2 group size must be a power of two <= 64 (a group lies in one wave)");
+        if (p->n_streams % C != 0) return set_error(CPRNG_E_INVAL, "V2 needs n_streams % group == 0");
+        uint32_t c1[64], c2[64];
+        if (p->comb1 || p->comb2) {
+            if (!p->comb1 || !p->comb2) return set_error(CPRNG_E_INVAL, "give both comb1 and comb2");
+            for (uint32_t j = 0; j < C; ++j) {
+                if (p->comb1[j] >= C || p->comb2[j] >= C)
+                    return set_error(CPRNG_E_INVAL, "combination entry out of range");
+                c1[j] = p->comb1[j];
+                c2[j] = p->comb2[j];
+            }
+        } else if (!default_combs(C, c1, c2)) {
+            return set_error(CPRNG_E_INVAL, "no default combination arrays for this group size (need C >= 3)");
+        }
+        h->group = C;
+        for (uint32_t j = 0; j < 64; ++j) {
+            h->comb1[j] = (uint8_t)c1[j % C];
+            h->comb2[j] = (uint8_t)c2[j % C];
+        }
+    }
+
+    int dev = p->device;
+    if (dev < 0) HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    h->device = dev;
+    DeviceGuard g(dev);
+    if (!g.ok) return set_error(CPRNG_E_HIP, "hipSetDevice failed");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    h->n_cu = (uint32_t)prop.multiProcessorCount;
+
+    // Seed on the host, pack SoA, upload.
+    const uint64_t nwords = (uint64_t)h->ns * h->words;
+    std::vector<uint32_t> aos(nwords), soa(nwords);
+    seed_streams((int)var, (flags & CPRNG_F_V1_W32) != 0, p->seed, 0, h->ns, aos.data());
+    for (uint64_t s = 0; s < h->ns; ++s)
+        for (uint32_t k = 0; k < h->words; ++k) soa[k * (uint64_t)h->ns + s] = aos[s * h->words + k];
+    if (hipMalloc(&h->d_state, nwords * sizeof(uint32_t)) != hipSuccess)
+        return set_error(CPRNG_E_NOMEM, "hipMalloc of the stream states failed");
+    HIP_TRY(hipMemcpy(h->d_state, soa.data(), nwords * sizeof(uint32_t), hipMemcpyHostToDevice),
+            "hipMemcpy state");
+    HIP_TRY(hipEventCreate(&h->ev0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&h->ev1), "hipEventCreate");
+    *out = h.release();
+    return CPRNG_OK;
+}
+
+LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
+{
+    if (!h->tuned_loaded) {
+        tune_cache_load(h);
+        h->tuned_loaded = true;
+    }
+    LaunchCfg c = default_cfg(h->variant, (h->flags & CPRNG_F_V1_W32) != 0, consume);
+    TuneEntry e;
+    if (!consume && tune_cache_lookup(h, n, &e)) {
+        c.block = e.block;
+        c.unroll = e.unroll;
+        c.store = e.store;
+    }
+    if (h->tuning.block) c.block = h->tuning.block;
+    if (h->tuning.unroll) c.unroll = h->tuning.unroll;
+    if (h->tuning.store && !consume) c.store = h->tuning.store;
+    return c;
+}
+
+}  // namespace
+
+namespace cprng_impl {
+
+int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchCfg c)
+{
+    GenArgs a;
+    fill_args(h, a);
+    a.out = out;
+    a.n = n;
+    if (h->flags & CPRNG_F_INTERLEAVED) {
+        c.store = ST_INTERLEAVED;
+    } else {
+        const bool aligned = ((uintptr_t)out % 16u) == 0 && (n % 4u) == 0;
+        if (!aligned) c.store = ST_GENERIC;
+    }
+    int rc = begin_timing(h, st);
+    if (rc) return rc;
+    HIP_TRY(launch_generate(a, (int)h->variant, (h->flags & CPRNG_F_V1_W32) != 0, c, st),
+            "generate kernel launch");
+    return end_timing(h, st);
+}
+
+}  // namespace cprng_impl
+
+extern "C" {
+
+int cprng_create(const uint64_t *seeds, uint32_t n_streams, uint32_t variant, cprng_t **out)
+{
+    if (!seeds) return set_error(CPRNG_E_INVAL, "seeds is NULL");
+    cprng_params_t p;
+    std::memset(&p, 0, sizeof p);
+    p.struct_size = sizeof p;
+    p.variant = variant;
+    p.n_streams = n_streams;
+    p.seed = seeds[0];
+    p.device = -1;
+    return create_impl(&p, out);
+}
+
+int cprng_create_ex(const cprng_params_t *params, cprng_t **out) { return create_impl(params, out); }
+
+void cprng_destroy(cprng_t *h)
+{
+    if (!h) return;
+    DeviceGuard g(h->device);
+    (void)hipDeviceSynchronize();
+    destroy_plans(h);
+    if (h->d_state) (void)hipFree(h->d_state);
+    if (h->d_state_next) (void)hipFree(h->d_state_next);
+    if (h->d_counter) (void)hipFree(h->d_counter);
+    if (h->d_req_segs) (void)hipFree(h->d_req_segs);
+    if (h->d_req_polys) (void)hipFree(h->d_req_polys);
+    if (h->d_req_ids) (void)hipFree(h->d_req_ids);
+    for (auto &kv : h->d_req_poly_tables) (void)hipFree(kv.second);
+    if (h->h_stage) (void)hipHostFree(h->h_stage);
+    if (h->ev_stage) (void)hipEventDestroy(h->ev_stage);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    delete h;
+}
+
+int cprng_generate(cprng_t *h, uint32_t *out, uint64_t n_per_stream, cprng_stream_t stream)
+{
+    if (!h) return set_error(CPRNG_E_INVAL, "NULL handle");
+    if (n_per_stream == 0) return CPRNG_OK;
+    if (!out) return set_error(CPRNG_E_INVAL, "out is NULL");
+    if ((uintptr_t)out % 4u) return set_error(CPRNG_E_INVAL, "out must be 4-byte aligned");
+    DeviceGuard g(h->device);
+    if (!g.ok) return set_error(CPRNG_E_HIP, "hipSetDevice failed");
+    const LaunchCfg c = resolve_cfg(h, n_per_stream, false);
+    return generate_with(h, out, n_per_stream, (hipStream_t)stream, c);
+}
+
+int cprng_consume_qc(cprng_t *h, uint64_t *counts, uint64_t n_per_stream, cprng_stream_t stream)
+{
+    if (!h) return set_error(CPRNG_E_INVAL, "NULL handle");
+    if (!counts) return set_error(CPRNG_E_INVAL, "counts is NULL");
+    if (n_per_stream % 2u) return set_error(CPRNG_E_INVAL, "n_per_stream must be even (pairs)");
+    if ((uintptr_t)counts % 8u) return set_error(CPRNG_E_INVAL, "counts must be 8-byte aligned");
+    DeviceGuard g(h->device);
+    if (!g.ok) return set_error(CPRNG_E_HIP, "hipSetDevice failed");
+    GenArgs a;
+    fill_args(h, a);
+    a.counts = counts;
+    a.n = n_per_stream;
+    const LaunchCfg c = resolve_cfg(h, n_per_stream, true);
+    int rc = begin_timing(h, (hipStream_t)stream);
+    if (rc) return rc;
+    HIP_TRY(launch_consume(a, (int)h->variant, (h->flags & CPRNG_F_V1_W32) != 0, c, (hipStream_t)stream),
+            "consume kernel launch");
+    return end_timing(h, (hipStream_t)stream);
+}
+
+int cprng_state_words(const cprng_t *h)
+{
+    if (!h) return set_error(CPRNG_E_INVAL, "NULL handle");
+    return (int)h->words;
+}
+
+uint32_t cprng_n_streams(const cprng_t *h) { return h ? h->ns : 0u; }
+uint32_t cprng_variant(const cprng_t *h) { return h ? (h->variant | h->flags) : 0u; }
+
+int cprng_get_state(cprng_t *h, uint32_t *host_words, size_t n_words)
+{
+    if (!h || !host_words) return set_error(CPRNG_E_INVAL, "NULL argument");
+    const uint64_t nw = (uint64_t)h->ns * h->words;
+    if (n_words != nw) return set_error(CPRNG_E_INVAL, "n_words must be n_streams * state_words");
+    DeviceGuard g(h->device);
+    std::vector<uint32_t> soa(nw);
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    HIP_TRY(hipMemcpy(soa.data(), h->d_state, nw * sizeof(uint32_t), hipMemcpyDeviceToHost), "hipMemcpy state");
+    for (uint64_t s = 0; s < h->ns; ++s)
+        for (uint32_t k = 0; k < h->words; ++k) host_words[s * h->words + k] = soa[k * (uint64_t)h->ns + s];
+    return CPRNG_OK;
+}
+
+int cprng_set_state(cprng_t *h, const uint32_t *host_words, size_t n_words)
+{
+    if (!h || !host_words) return set_error(CPRNG_E_INVAL, "NULL argument");
+    const uint64_t nw = (uint64_t)h->ns * h->words;
+    if (n_words != nw) return set_error(CPRNG_E_INVAL, "n_words must be n_streams * state_words");
+    const bool w32 = (h->flags & CPRNG_F_V1_W32) != 0;
+    for (uint64_t s = 0; s < h->ns; ++s) {
+        const uint32_t *w = host_words + s * h->words;
+        if (h->variant == CPRNG_V1_NAIVE3) {
+            if ((w[0] | w[1]) == 0) return set_error(CPRNG_E_INVAL, "xorshift word is zero");
+            uint32_t or2 = 0, or3 = 0;
+            for (int k = 2; k < 10; ++k) or2 |= w[k];
+            for (int k = 10; k < 20; ++k) or3 |= w[k];
+            if (!or2 || !or3) return set_error(CPRNG_E_INVAL, "xor128 or xorwow words all zero");
+            if (w32)
+                for (int k = 1; k < 22; k += 2)
+                    if (w[k]) return set_error(CPRNG_E_INVAL, "32-bit-word V1 state has a nonzero high half");
+        } else if ((w[0] | w[1] | w[2] | w[3]) == 0) {
+            return set_error(CPRNG_E_INVAL, "xor128 words all zero");
+        }
+    }
+    DeviceGuard g(h->device);
+    std::vector<uint32_t> soa(nw);
+    for (uint64_t s = 0; s < h->ns; ++s)
+        for (uint32_t k = 0; k < h->words; ++k) soa[k * (uint64_t)h->ns + s] = host_words[s * h->words + k];
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    HIP_TRY(hipMemcpy(h->d_state, soa.data(), nw * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy state");
+    return CPRNG_OK;
+}
+
+int cprng_default_combs(uint32_t C, uint32_t *comb1, uint32_t *comb2)
+{
+    if (!comb1 || !comb2) return set_error(CPRNG_E_INVAL, "NULL argument");
+    if (C < 3 || C > 64 || !is_pow2(C)) return set_error(CPRNG_E_INVAL, "C must be a power of two in [4, 64]");
+    if (!default_combs(C, comb1, comb2)) return set_error(CPRNG_E_INVAL, "no combination arrays found");
+    return CPRNG_OK;
+}
+
+int cprng_set_tuning(cprng_t *h, const cprng_tuning_t *t)
+{
+    if (!h || !t) return set_error(CPRNG_E_INVAL, "NULL argument");
+    if (t->block && (t->block % 64 || t->block > 256)) return set_error(CPRNG_E_INVAL, "block must be 64, 128, 192 or 256");
+    if (t->unroll && t->unroll != 8 && t->unroll != 16 && t->unroll != 32)
+        return set_error(CPRNG_E_INVAL, "unroll must be 8, 16 or 32");
+    if (t->store > 4) return set_error(CPRNG_E_INVAL, "store mode must be 0..4");
+    if (t->chunk && (t->chunk % 64 || t->chunk > (1u << 24))) return set_error(CPRNG_E_INVAL, "chunk must be a multiple of 64, <= 2^24");
+    if (t->waves_per_cu > 32) return set_error(CPRNG_E_INVAL, "waves_per_cu must be <= 32");
+    h->tuning = *t;
+    return CPRNG_OK;
+}
+
+int cprng_get_tuning(const cprng_t *h, cprng_tuning_t *t)
+{
+    if (!h || !t) return set_error(CPRNG_E_INVAL, "NULL argument");
+    *t = h->tuning;
+    return CPRNG_OK;
+}
+
+int cprng_enable_timing(cprng_t *h, int on)
+{
+    if (!h) return set_error(CPRNG_E_INVAL, "NULL handle");
+    h->timing = on != 0;
+    h->ev_pending = false;
+    return CPRNG_OK;
+}
+
+double cprng_last_kernel_ms(cprng_t *h)
+{
+    if (!h || !h->ev_pending) return -1.0;
+    DeviceGuard g(h->device);
+    if (hipEventSynchronize(h->ev1) != hipSuccess) return -1.0;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev0, h->ev1) != hipSuccess) return -1.0;
+    return (double)ms;
+}
+
+int cprng_probe_fill(uint32_t *dst, uint64_t n_words, uint32_t value, cprng_stream_t stream)
+{
+    if (!dst || (uintptr_t)dst % 16u) return set_error(CPRNG_E_INVAL, "dst must be 16-byte aligned");
+    HIP_TRY(launch_fill(dst, n_words, value, (hipStream_t)stream), "fill kernel launch");
+    return CPRNG_OK;
+}
+
+int cprng_probe_copy(uint32_t *dst, const uint32_t *src, uint64_t n_words, cprng_stream_t stream)
+{
+    if (!dst || !src || (uintptr_t)dst % 16u || (uintptr_t)src % 16u)
+        return set_error(CPRNG_E_INVAL, "dst and src must be 16-byte aligned");
+    HIP_TRY(launch_copy(dst, src, n_words, (hipStream_t)stream), "copy kernel launch");
+    return CPRNG_OK;
+}
+
+const char *cprng_strerror(int status)
+{
+    switch (status) {
+    case CPRNG_OK: return "ok";
+    case CPRNG_E_INVAL: return "invalid argument";
+    case CPRNG_E_NOMEM: return "out of memory";
+    case CPRNG_E_HIP: return "HIP runtime error";
+    case CPRNG_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char *cprng_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,659 @@
+// cprng_kernels.hip -- gfx950 kernels of the chaotic-iteration PRNG.
+//
+// Every kernel keeps one stream per lane with its whole generator state in
+// VGPRs, applies the chaotic iteration x <- x xor S (Section 4.2, Eq. Oplus)
+// once per output and writes the state back at the end, as the GPU kernels of
+// Section 6 (Algorithms 3 and 4) do.  The work is integer ALU plus stores:
+// there is no dense contraction, so no MFMA.  The hot path is bound by HBM
+// writes (generate) or by the VALU (consume, and the three-generator
+// variant).
+//
+// Neighbour exchange (Algorithm 4): the paper's shared-memory array is
+// replaced by ds_bpermute_b32, which reads another lane's register.  All 64
+// lanes are read in one instruction before any lane updates its word, which
+// is exactly "every thread reads the previous step's words" -- race-free with
+// no barrier, as long as a group of C streams lies within one wave (C | 64).
+
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace cprng_impl {
+namespace {
+
+// ------------------------------------------------------------------------
+// Strategy generators.
+// ------------------------------------------------------------------------
+struct X128 {
+    uint32_t x, y, z, w;
+};
+
+// Marsaglia xor128 on 32-bit words (the xor-like generator of Algorithm 4).
+__device__ __forceinline__ uint32_t x128_next(X128 &g)
+{
+    uint32_t t = g.x ^ (g.x << 11);
+    g.x = g.y;
+    g.y = g.z;
+    g.z = g.w;
+    g.w = (g.w ^ (g.w >> 19)) ^ (t ^ (t >> 8));
+    return g.w;
+}
+
+// The three generators of Listing 1 on words of type T (uint64_t: the
+// listing's 64-bit generators; uint32_t: the 32-bit-word option).
+template <typename T>
+struct Naive3 {
+    T a;                     // xorshift (13,17,5), Algorithm 2's triple
+    T b0, b1, b2, b3;        // xor128
+    T c0, c1, c2, c3, c4, d; // xorwow (d: Weyl counter)
+};
+
+template <typename T>
+__device__ __forceinline__ uint32_t naive3_strategy(Naive3<T> &g)
+{
+    T a = g.a;
+    a ^= a << 13;
+    a ^= a >> 17;
+    a ^= a << 5;
+    g.a = a;
+
+    T t = g.b0 ^ (g.b0 << 11);
+    g.b0 = g.b1;
+    g.b1 = g.b2;
+    g.b2 = g.b3;
+    g.b3 = (g.b3 ^ (g.b3 >> 19)) ^ (t ^ (t >> 8));
+
+    T u = g.c0 ^ (g.c0 >> 2);
+    g.c0 = g.c1;
+    g.c1 = g.c2;
+    g.c2 = g.c3;
+    g.c3 = g.c4;
+    g.c4 = (g.c4 ^ (g.c4 << 4)) ^ (u ^ (u << 1));
+    g.d += (T)362437u;
+
+    // S = xor of the low and high halves of the three outputs.
+    T f = a ^ g.b3 ^ (T)(g.d + g.c4);
+    if constexpr (sizeof(T) == 8)
+        return (uint32_t)f ^ (uint32_t)(f >> 32);
+    else
+        return (uint32_t)f;
+}
+
+// ------------------------------------------------------------------------
+// Per-variant stream state held in registers.  SoA in memory: word k of
+// stream s is state[k * ns + s].
+// ------------------------------------------------------------------------
+template <int VAR, typename T>
+struct Stream;
+
+template <typename T>
+struct Stream<0, T> {                       // V0 PLAIN
+    X128 g;
+    uint32_t x;
+    __device__ void load(const GenArgs &a, uint32_t s)
+    {
+        const uint32_t *p = a.state + s;
+        const uint64_t ns = a.ns;
+        g.x = p[0]; g.y = p[ns]; g.z = p[2 * ns]; g.w = p[3 * ns];
+        x = p[4 * ns];
+    }
+    __device__ void save(const GenArgs &a, uint32_t s) const
+    {
+        uint32_t *p = a.state + s;
+        const uint64_t ns = a.ns;
+        p[0] = g.x; p[ns] = g.y; p[2 * ns] = g.z; p[3 * ns] = g.w;
+        p[4 * ns] = x;
+    }
+    __device__ void init_exchange(const GenArgs &, uint32_t) {}
+    __device__ __forceinline__ uint32_t next()
+    {
+        x ^= x128_next(g);
+        return x;
+    }
+};
+
+template <typename T>
+struct Stream<2, T> {                       // V2 SHMEM (Algorithm 4)
+    X128 g;
+    uint32_t x, t;                          // t: this stream's previous mixed word
+    int addr1, addr2;                       // byte addresses of the two source lanes
+    __device__ void load(const GenArgs &a, uint32_t s)
+    {
+        const uint32_t *p = a.state + s;
+        const uint64_t ns = a.ns;
+        g.x = p[0]; g.y = p[ns]; g.z = p[2 * ns]; g.w = p[3 * ns];
+        x = p[4 * ns];
+        t = p[5 * ns];
+    }
+    __device__ void save(const GenArgs &a, uint32_t s) const
+    {
+        uint32_t *p = a.state + s;
+        const uint64_t ns = a.ns;
+        p[0] = g.x; p[ns] = g.y; p[2 * ns] = g.z; p[3 * ns] = g.w;
+        p[4 * ns] = x;
+        p[5 * ns] = t;
+    }
+    __device__ void init_exchange(const GenArgs &a, uint32_t lane)
+    {
+        // o = threadIdx - offset + comb[offset], offset = threadIdx mod C,
+        // within the wave (the group never straddles a wave since C | 64).
+        const uint32_t off = lane & (a.group - 1);
+        const uint32_t gbase = lane - off;
+        addr1 = (int)((gbase + a.comb1[off]) << 2);
+        addr2 = (int)((gbase + a.comb2[off]) << 2);
+    }
+    __device__ __forceinline__ uint32_t next()
+    {
+        const uint32_t u = x128_next(g);
+        const uint32_t n1 = (uint32_t)__builtin_amdgcn_ds_bpermute(addr1, (int)t);
+        const uint32_t n2 = (uint32_t)__builtin_amdgcn_ds_bpermute(addr2, (int)t);
+        t = u ^ n1 ^ n2;
+        x ^= t;
+        return x;
+    }
+};
+
+template <typename T>
+struct Stream<1, T> {                       // V1 NAIVE3 (Listing 1, Algorithm 3)
+    Naive3<T> g;
+    uint32_t x;
+    __device__ static T ld(const uint32_t *p, uint64_t ns, int k)
+    {
+        if constexpr (sizeof(T) == 8)
+            return (T)p[(2 * k) * ns] | ((T)p[(2 * k + 1) * ns] << 32);
+        else
+            return (T)p[(2 * k) * ns];
+    }
+    __device__ static void st(uint32_t *p, uint64_t ns, int k, T v)
+    {
+        p[(2 * k) * ns] = (uint32_t)v;
+        if constexpr (sizeof(T) == 8)
+            p[(2 * k + 1) * ns] = (uint32_t)(v >> 32);
+        else
+            p[(2 * k + 1) * ns] = 0u;
+    }
+    __device__ void load(const GenArgs &a, uint32_t s)
+    {
+        const uint32_t *p = a.state + s;
+        const uint64_t ns = a.ns;
+        g.a = ld(p, ns, 0);
+        g.b0 = ld(p, ns, 1); g.b1 = ld(p, ns, 2); g.b2 = ld(p, ns, 3); g.b3 = ld(p, ns, 4);
+        g.c0 = ld(p, ns, 5); g.c1 = ld(p, ns, 6); g.c2 = ld(p, ns, 7); g.c3 = ld(p, ns, 8);
+        g.c4 = ld(p, ns, 9); g.d = ld(p, ns, 10);
+        x = p[22 * ns];
+    }
+    __device__ void save(const GenArgs &a, uint32_t s) const
+    {
+        uint32_t *p = a.state + s;
+        const uint64_t ns = a.ns;
+        st(p, ns, 0, g.a);
+        st(p, ns, 1, g.b0); st(p, ns, 2, g.b1); st(p, ns, 3, g.b2); st(p, ns, 4, g.b3);
+        st(p, ns, 5, g.c0); st(p, ns, 6, g.c1); st(p, ns, 7, g.c2); st(p, ns, 8, g.c3);
+        st(p, ns, 9, g.c4); st(p, ns, 10, g.d);
+        p[22 * ns] = x;
+    }
+    __device__ void init_exchange(const GenArgs &, uint32_t) {}
+    __device__ __forceinline__ uint32_t next()
+    {
+        x ^= naive3_strategy(g);
+        return x;
+    }
+};
+
+// ------------------------------------------------------------------------
+// Stores.
+// ------------------------------------------------------------------------
+template <bool NT>
+__device__ __forceinline__ void store4(uint32_t *p, uint32_t a, uint32_t b, uint32_t c, uint32_t d)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 v = {a, b, c, d};
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+    else
+        *reinterpret_cast<u32x4 *>(p) = v;
+}
+
+__device__ __forceinline__ void load4(const uint32_t *p, uint32_t &a, uint32_t &b, uint32_t &c, uint32_t &d)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 v = *reinterpret_cast<const u32x4 *>(p);
+    a = v.x; b = v.y; c = v.z; d = v.w;
+}
+
+// ------------------------------------------------------------------------
+// Plain generate kernel: one lane per stream, K outputs per lane per round.
+//   ST_DIRECT(_NT): lane stores its K outputs as K/4 aligned 16-byte quads.
+//   ST_LDS(_NT)   : the wave's 64 x K tile goes through LDS so that each
+//                   store instruction writes K/4 consecutive quads of 64/(K/4)
+//                   streams (whole 128-byte lines when K >= 32).
+//   ST_INTERLEAVED: out[i * ns + s]; 64 lanes write 256 contiguous bytes.
+//   ST_GENERIC    : out[s * n + i] one dword at a time (any n, any alignment).
+// Fast modes need n % 4 == 0 and a 16-byte aligned `out` (host checks).
+// ------------------------------------------------------------------------
+template <int VAR, typename T, int K, int MODE>
+__global__ __launch_bounds__(256) void k_generate(GenArgs a)
+{
+    constexpr bool LDS = (MODE == ST_LDS || MODE == ST_LDS_NT);
+    constexpr bool NT = (MODE == ST_DIRECT_NT || MODE == ST_LDS_NT);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t wave_base = s - lane;
+    const bool active = s < a.ns;
+    const uint64_t n = a.n;
+
+    Stream<VAR, T> st;
+    if constexpr (!LDS) {
+        if (!active) return;
+        st.load(a, s);
+        st.init_exchange(a, lane);
+        if constexpr (MODE == ST_INTERLEAVED) {
+            uint64_t i = 0;
+            for (; i + K <= n; i += K) {
+                uint32_t v[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) v[j] = st.next();
+#pragma unroll
+                for (int j = 0; j < K; ++j) a.out[(i + j) * a.ns + s] = v[j];
+            }
+            for (; i < n; ++i) a.out[i * a.ns + s] = st.next();
+        } else if constexpr (MODE == ST_GENERIC) {
+            uint32_t *o = a.out + (uint64_t)s * n;
+            uint64_t i = 0;
+            for (; i + K <= n; i += K) {
+                uint32_t v[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) v[j] = st.next();
+#pragma unroll
+                for (int j = 0; j < K; ++j) o[i + j] = v[j];
+            }
+            for (; i < n; ++i) o[i] = st.next();
+        } else {
+            uint32_t *o = a.out + (uint64_t)s * n;
+            uint64_t i = 0;
+            for (; i + K <= n; i += K) {
+                uint32_t v[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) v[j] = st.next();
+#pragma unroll
+                for (int q = 0; q < K / 4; ++q)
+                    store4<NT>(o + i + 4 * q, v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+            }
+            for (; i < n; i += 4) {          // n % 4 == 0
+                uint32_t v0 = st.next(), v1 = st.next(), v2 = st.next(), v3 = st.next();
+                store4<NT>(o + i, v0, v1, v2, v3);
+            }
+        }
+        st.save(a, s);
+    } else {
+        // All lanes stay for the cooperative stores; inactive lanes (a partial
+        // last wave) run on a zero state and their rows are never stored.  For
+        // V2 the inactive lanes are whole groups, so no active lane reads them.
+        HIP_DYNAMIC_SHARED(uint32_t, lds);
+        constexpr int RS = K + 4;            // row stride (words): 16-byte aligned rows
+        constexpr int QPR = K / 4;           // quads per row
+        uint32_t *tile = lds + (threadIdx.x >> 6) * (64 * RS);
+        if (active) {
+            st.load(a, s);
+        } else {
+            st = Stream<VAR, T>{};
+        }
+        st.init_exchange(a, lane);
+        uint64_t i = 0;
+        for (; i + K <= n; i += K) {
+            uint32_t v[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) v[j] = st.next();
+#pragma unroll
+            for (int q = 0; q < QPR; ++q)
+                store4<false>(tile + lane * RS + 4 * q, v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < QPR; ++j) {
+                const uint32_t Q = j * 64 + lane;
+                const uint32_t r = Q / QPR;
+                const uint32_t q = Q % QPR;
+                uint32_t x0, x1, x2, x3;
+                load4(tile + r * RS + 4 * q, x0, x1, x2, x3);
+                if (wave_base + r < a.ns)
+                    store4<NT>(a.out + (uint64_t)(wave_base + r) * n + i + 4 * q, x0, x1, x2, x3);
+            }
+            __syncthreads();
+        }
+        if (active) {
+            uint32_t *o = a.out + (uint64_t)s * n;
+            for (; i < n; i += 4) {
+                uint32_t v0 = st.next(), v1 = st.next(), v2 = st.next(), v3 = st.next();
+                store4<NT>(o + i, v0, v1, v2, v3);
+            }
+        } else {
+            for (; i < n; ++i) (void)st.next();  // keep V2 exchanges in step
+        }
+        if (active) st.save(a, s);
+    }
+}
+
+// ------------------------------------------------------------------------
+// Consumption kernel: pairs of outputs -> binary32 point in [0,1)^2 -> hit
+// count of the unit quarter circle.  Products and the sum are rounded one by
+// one (contraction is off for this file).
+// ------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t qc_hit(uint32_t r1, uint32_t r2)
+{
+    const float u = (float)(r1 >> 8) * 0x1p-24f;
+    const float v = (float)(r2 >> 8) * 0x1p-24f;
+    const float uu = u * u;
+    const float vv = v * v;
+    const float sum = uu + vv;
+    return sum < 1.0f ? 1u : 0u;
+}
+
+template <int VAR, typename T, int K>
+__global__ __launch_bounds__(256) void k_consume(GenArgs a)
+{
+    static_assert(K % 2 == 0, "pairs");
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.ns) return;
+    Stream<VAR, T> st;
+    st.load(a, s);
+    st.init_exchange(a, lane);
+    const uint64_t n = a.n;
+    uint64_t total = 0;
+    uint64_t i = 0;
+    while (i < n) {
+        const uint64_t lim = (n - i > (1ull << 30)) ? i + (1ull << 30) : n;
+        uint32_t c = 0;
+        for (; i + K <= lim; i += K) {
+#pragma unroll
+            for (int j = 0; j < K; j += 2) {
+                const uint32_t r1 = st.next();
+                const uint32_t r2 = st.next();
+                c += qc_hit(r1, r2);
+            }
+        }
+        for (; i < lim; i += 2) {
+            const uint32_t r1 = st.next();
+            const uint32_t r2 = st.next();
+            c += qc_hit(r1, r2);
+        }
+        total += c;
+    }
+    a.counts[s] = total;
+    st.save(a, s);
+}
+
+// ------------------------------------------------------------------------
+// Segments of V0 streams (batched uneven streams, requests).  Each lane takes
+// one segment from a work queue (64 per wave and grab), jumps the stream's
+// 160-bit state (xor128 words and x) ahead by the segment's start position,
+// then generates and stores its outputs.
+//
+// Jump: the map v -> A'v (one xor128 step, then x ^= new w) is linear over
+// GF(2), so A'^J v = sum_k c_k A'^k v with sum_k c_k X^k = X^J mod q(X),
+// q the polynomial annihilating A' (degree <= 129).  The host supplies the
+// coefficients c_k; the lane walks k = 0..128, accumulating A'^k v where
+// c_k = 1.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void jump_v0(X128 &g, uint32_t &x, const uint32_t *poly)
+{
+    uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
+#pragma unroll 1
+    for (int w = 0; w < 5; ++w) {
+        const uint32_t pw = poly[w];
+        const int nb = (w < 4) ? 32 : 1;     // coefficients 0..128
+#pragma unroll 4
+        for (int b = 0; b < nb; ++b) {
+            const uint32_t m = 0u - ((pw >> b) & 1u);
+            a0 ^= g.x & m;
+            a1 ^= g.y & m;
+            a2 ^= g.z & m;
+            a3 ^= g.w & m;
+            a4 ^= x & m;
+            x ^= x128_next(g);
+        }
+    }
+    g.x = a0; g.y = a1; g.z = a2; g.w = a3;
+    x = a4;
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_segments(SegArgs a)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t ns = a.ns;
+    for (;;) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(a.counter, 64u);
+        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+        if (base >= a.nseg) break;
+        const uint32_t idx = base + lane;
+        if (idx < a.nseg) {
+            const SegDesc d = a.segs[idx];
+            const uint32_t *p = a.state + d.stream;
+            X128 g{p[0], p[ns], p[2 * ns], p[3 * ns]};
+            uint32_t x = p[4 * ns];
+            if (d.poly != 0)
+                jump_v0(g, x, d.poly < a.n_table ? a.polys + 5ull * d.poly
+                                                 : a.polys_extra + 5ull * (d.poly - a.n_table));
+            uint32_t *o = reinterpret_cast<uint32_t *>(d.out);
+            const uint32_t len = d.len;
+            uint32_t i = 0;
+            const uint32_t head = d.head < len ? d.head : len;
+            for (; i < head; ++i) {
+                x ^= x128_next(g);
+                o[i] = x;
+            }
+            for (; i + K <= len; i += K) {
+                uint32_t v[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    x ^= x128_next(g);
+                    v[j] = x;
+                }
+#pragma unroll
+                for (int q = 0; q < K / 4; ++q)
+                    store4<false>(o + i + 4 * q, v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+            }
+            for (; i + 4 <= len; i += 4) {
+                uint32_t v0, v1, v2, v3;
+                x ^= x128_next(g); v0 = x;
+                x ^= x128_next(g); v1 = x;
+                x ^= x128_next(g); v2 = x;
+                x ^= x128_next(g); v3 = x;
+                store4<false>(o + i, v0, v1, v2, v3);
+            }
+            for (; i < len; ++i) {
+                x ^= x128_next(g);
+                o[i] = x;
+            }
+            if (d.last) {
+                uint32_t *q = a.state_next + d.stream;
+                q[0] = g.x; q[ns] = g.y; q[2 * ns] = g.z; q[3 * ns] = g.w;
+                q[4 * ns] = x;
+            }
+        }
+    }
+}
+
+__global__ void k_commit(uint32_t *state, const uint32_t *state_next, const uint32_t *ids,
+                         uint32_t count, uint32_t ns)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint64_t id = ids[i];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) state[k * (uint64_t)ns + id] = state_next[k * (uint64_t)ns + id];
+}
+
+__global__ void k_zero_u32(uint32_t *p, uint32_t count)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0u;
+}
+
+// ------------------------------------------------------------------------
+// Probes: store-only fill and copy with 16-byte accesses (grid-stride).
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fill(uint32_t *dst, uint64_t nq, uint32_t value)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += stride)
+        store4<false>(dst + 4 * q, value, value, value, value);
+}
+
+__global__ __launch_bounds__(256) void k_copy(uint32_t *dst, const uint32_t *src, uint64_t nq)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += stride) {
+        uint32_t a0, a1, a2, a3;
+        load4(src + 4 * q, a0, a1, a2, a3);
+        store4<false>(dst + 4 * q, a0, a1, a2, a3);
+    }
+}
+
+__global__ void k_tail_words(uint32_t *dst, const uint32_t *src, uint64_t begin, uint64_t end, uint32_t value)
+{
+    const uint64_t i = begin + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i < end) dst[i] = src ? src[i] : value;
+}
+
+// ------------------------------------------------------------------------
+// Dispatch.
+// ------------------------------------------------------------------------
+template <int VAR, typename T, int K>
+hipError_t gen_by_mode(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
+{
+    const uint32_t grid = (a.ns + c.block - 1) / c.block;
+    size_t lds = 0;
+    switch (c.store) {
+    case ST_DIRECT:
+        hipLaunchKernelGGL((k_generate<VAR, T, K, ST_DIRECT>), dim3(grid), dim3(c.block), 0, st, a);
+        break;
+    case ST_DIRECT_NT:
+        hipLaunchKernelGGL((k_generate<VAR, T, K, ST_DIRECT_NT>), dim3(grid), dim3(c.block), 0, st, a);
+        break;
+    case ST_LDS:
+        lds = (size_t)(c.block / 64) * 64 * (K + 4) * sizeof(uint32_t);
+        hipLaunchKernelGGL((k_generate<VAR, T, K, ST_LDS>), dim3(grid), dim3(c.block), lds, st, a);
+        break;
+    case ST_LDS_NT:
+        lds = (size_t)(c.block / 64) * 64 * (K + 4) * sizeof(uint32_t);
+        hipLaunchKernelGGL((k_generate<VAR, T, K, ST_LDS_NT>), dim3(grid), dim3(c.block), lds, st, a);
+        break;
+    case ST_INTERLEAVED:
+        hipLaunchKernelGGL((k_generate<VAR, T, K, ST_INTERLEAVED>), dim3(grid), dim3(c.block), 0, st, a);
+        break;
+    case ST_GENERIC:
+        hipLaunchKernelGGL((k_generate<VAR, T, K, ST_GENERIC>), dim3(grid), dim3(c.block), 0, st, a);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int VAR, typename T>
+hipError_t gen_by_unroll(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
+{
+    switch (c.unroll) {
+    case 8: return gen_by_mode<VAR, T, 8>(a, c, st);
+    case 16: return gen_by_mode<VAR, T, 16>(a, c, st);
+    case 32: return gen_by_mode<VAR, T, 32>(a, c, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int VAR, typename T>
+hipError_t consume_by_unroll(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
+{
+    const uint32_t grid = (a.ns + c.block - 1) / c.block;
+    switch (c.unroll) {
+    case 8: hipLaunchKernelGGL((k_consume<VAR, T, 8>), dim3(grid), dim3(c.block), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_consume<VAR, T, 16>), dim3(grid), dim3(c.block), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_consume<VAR, T, 32>), dim3(grid), dim3(c.block), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_generate(const GenArgs &a, int variant, int w32, const LaunchCfg &c, hipStream_t st)
+{
+    if (c.block == 0 || c.block % 64 != 0 || c.block > 256) return hipErrorInvalidValue;
+    switch (variant) {
+    case 0: return gen_by_unroll<0, uint32_t>(a, c, st);
+    case 1: return w32 ? gen_by_unroll<1, uint32_t>(a, c, st) : gen_by_unroll<1, uint64_t>(a, c, st);
+    case 2: return gen_by_unroll<2, uint32_t>(a, c, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_consume(const GenArgs &a, int variant, int w32, const LaunchCfg &c, hipStream_t st)
+{
+    if (c.block == 0 || c.block % 64 != 0 || c.block > 256) return hipErrorInvalidValue;
+    switch (variant) {
+    case 0: return consume_by_unroll<0, uint32_t>(a, c, st);
+    case 1: return w32 ? consume_by_unroll<1, uint32_t>(a, c, st) : consume_by_unroll<1, uint64_t>(a, c, st);
+    case 2: return consume_by_unroll<2, uint32_t>(a, c, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_segments(const SegArgs &a, uint32_t grid, uint32_t block, uint32_t store, hipStream_t st)
+{
+    (void)store;
+    if (block == 0 || block % 64 != 0 || block > 256 || grid == 0) return hipErrorInvalidValue;
+    switch (a.unroll) {
+    case 8: hipLaunchKernelGGL((k_segments<8>), dim3(grid), dim3(block), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_segments<16>), dim3(grid), dim3(block), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_segments<32>), dim3(grid), dim3(block), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_commit(uint32_t *state, const uint32_t *state_next, const uint32_t *ids,
+                         uint32_t count, uint32_t ns, hipStream_t st)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_commit, dim3((count + 255) / 256), dim3(256), 0, st, state, state_next, ids, count, ns);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t *p, uint32_t count, hipStream_t st)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3((count + 255) / 256), dim3(256), 0, st, p, count);
+    return hipGetLastError();
+}
+
+static uint32_t probe_grid(uint64_t nq)
+{
+    uint64_t g = (nq + 255) / 256;
+    const uint64_t cap = 256ull * 64;          // plenty of waves for 256 CUs
+    if (g > cap) g = cap;
+    return (uint32_t)(g ? g : 1);
+}
+
+hipError_t launch_fill(uint32_t *dst, uint64_t n_words, uint32_t value, hipStream_t st)
+{
+    const uint64_t nq = n_words / 4;
+    if (nq) hipLaunchKernelGGL(k_fill, dim3(probe_grid(nq)), dim3(256), 0, st, dst, nq, value);
+    if (n_words % 4)
+        hipLaunchKernelGGL(k_tail_words, dim3(1), dim3(64), 0, st, dst, (const uint32_t *)nullptr,
+                           nq * 4, n_words, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(uint32_t *dst, const uint32_t *src, uint64_t n_words, hipStream_t st)
+{
+    const uint64_t nq = n_words / 4;
+    if (nq) hipLaunchKernelGGL(k_copy, dim3(probe_grid(nq)), dim3(256), 0, st, dst, src, nq);
+    if (n_words % 4)
+        hipLaunchKernelGGL(k_tail_words, dim3(1), dim3(64), 0, st, dst, src, nq * 4, n_words, 0u);
+    return hipGetLastError();
+}
+
+}  // namespace cprng_impl

@@ -1,0 +1,87 @@
+// host.h -- host-side pieces of the library: seeding, combination arrays,
+// GF(2) jump polynomials, error reporting and the handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "cprng.h"
+#include "internal.h"
+
+namespace cprng_impl {
+
+// ---- errors ---------------------------------------------------------------
+int set_error(int status, const std::string &detail);
+int hip_error(hipError_t e, const char *what);
+
+// ---- seeding (seed.cpp) ---------------------------------------------------
+// Words per stream of a variant (V0 5, V1 23, V2 6).
+int words_per_stream(int variant);
+// Fill AoS words (n_streams x words) for streams [first, first+count).
+void seed_streams(int variant, bool w32, uint64_t sigma, uint64_t first, uint64_t count,
+                  uint32_t *aos);
+// Default combination arrays for a group of C streams (C >= 3).
+bool default_combs(uint32_t C, uint32_t *comb1, uint32_t *comb2);
+
+// ---- GF(2) jump polynomials (gf2.cpp) ------------------------------------
+// Elements of GF(2)[X]/(q) with q the annihilating polynomial of the V0
+// one-step map on (xor128 words, x); deg q <= 129, so 3 64-bit words.
+struct JPoly {
+    uint64_t w[3];
+};
+// Initialise (idempotent, thread-safe): computes q and self-checks it.
+bool jump_init(std::string *why);
+JPoly jump_mul(const JPoly &a, const JPoly &b);
+JPoly jump_xpow(uint64_t J);          // X^J mod q
+JPoly jump_one();
+// Pack into the kernel's 5 x 32-bit coefficient words (coefficients 0..128).
+void jump_pack(const JPoly &p, uint32_t out[5]);
+
+// ---- ragged / request plans (segments.cpp) --------------------------------
+struct RaggedPlan;
+void destroy_plans(cprng_t *h);
+
+}  // namespace cprng_impl
+
+// The handle.
+struct cprng {
+    int device = 0;
+    uint32_t variant = 0;       // low byte
+    uint32_t flags = 0;         // cprng_flags
+    uint32_t ns = 0;
+    uint32_t words = 0;
+    uint32_t group = 0;         // V2
+    uint8_t comb1[64] = {0};
+    uint8_t comb2[64] = {0};
+    uint32_t *d_state = nullptr;        // SoA, words x ns
+    uint32_t *d_state_next = nullptr;   // V0 segment kernels: end states
+    uint32_t n_cu = 0;
+    cprng_tuning_t tuning{};            // user / autotuned (0 = default)
+    bool tuned_loaded = false;
+
+    // timing
+    bool timing = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool ev_pending = false;
+
+    // segment machinery (V0)
+    uint32_t *d_counter = nullptr;
+    std::vector<cprng_impl::RaggedPlan *> plans;
+    // requests: per-call buffers (grow-only)
+    cprng_impl::SegDesc *d_req_segs = nullptr;
+    size_t req_segs_cap = 0;
+    uint32_t *d_req_polys = nullptr;
+    size_t req_polys_cap = 0;
+    uint32_t *d_req_ids = nullptr;
+    size_t req_ids_cap = 0;
+    void *h_stage = nullptr;            // pinned staging for uploads
+    size_t h_stage_cap = 0;
+    hipEvent_t ev_stage = nullptr;
+    // cached X^(h + k*Lc) tables for requests: key Lc
+    std::unordered_map<uint32_t, std::vector<uint32_t>> req_poly_tables;
+    std::unordered_map<uint32_t, uint32_t *> d_req_poly_tables;
+};

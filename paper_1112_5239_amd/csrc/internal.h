@@ -1,0 +1,81 @@
+// internal.h -- shared declarations between the host runtime and the gfx950
+// kernels of the chaotic-iteration PRNG library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "cprng.h"
+
+namespace cprng_impl {
+
+// Store modes of the plain generate kernel.
+enum StoreMode : int {
+    ST_DIRECT = 1,        // each lane stores its own stream's 16-byte quads
+    ST_LDS = 2,           // tile transposed through LDS, full lines per store
+    ST_DIRECT_NT = 3,     // as ST_DIRECT with non-temporal stores
+    ST_LDS_NT = 4,        // as ST_LDS with non-temporal stores
+    ST_INTERLEAVED = 5,   // out[i * n_streams + s], one dword per lane
+    ST_GENERIC = 6        // any alignment / length: one dword per output
+};
+
+// Kernel arguments of the plain generate / consume kernels.
+struct GenArgs {
+    uint32_t *state;       // SoA: word k of stream s at state[k * ns + s]
+    uint32_t *out;         // outputs (generate)
+    uint64_t *counts;      // hit counts (consume)
+    uint64_t n;            // outputs per stream
+    uint32_t ns;           // number of streams
+    uint32_t group;        // V2 group size C (divides 64)
+    uint8_t comb1[64];     // V2: comb1[j mod C]
+    uint8_t comb2[64];
+};
+
+struct LaunchCfg {
+    uint32_t block;        // threads per block
+    uint32_t unroll;       // outputs per lane per round
+    uint32_t store;        // StoreMode
+};
+
+// variant: 0 V0, 1 V1 (w32 selects 32-bit words), 2 V2.
+hipError_t launch_generate(const GenArgs &a, int variant, int w32, const LaunchCfg &c,
+                           hipStream_t st);
+hipError_t launch_consume(const GenArgs &a, int variant, int w32, const LaunchCfg &c,
+                          hipStream_t st);
+
+// Chunk ("segment") of a stream for the batched uneven and request kernels.
+struct SegDesc {
+    uint64_t out;          // device address of the segment's first output
+    uint32_t stream;       // stream id
+    uint32_t len;          // outputs in this segment
+    uint32_t head;         // leading outputs stored one by one (0..3)
+    uint32_t poly;         // index of the jump polynomial (0 = no jump)
+    uint32_t last;         // 1: writes the stream's end state to state_next
+    uint32_t pad;
+};
+
+struct SegArgs {
+    const SegDesc *segs;
+    uint32_t nseg;
+    uint32_t ns;           // streams (SoA stride)
+    const uint32_t *polys; // 5 words per polynomial, bit k = coeff of x^k
+    const uint32_t *polys_extra; // polynomials with index >= n_table
+    uint32_t n_table;      // entries in polys
+    const uint32_t *state; // current states (read only during the launch)
+    uint32_t *state_next;  // end states of streams whose last segment ran
+    uint32_t *counter;     // work-queue counter (reset before each launch)
+    uint32_t unroll;       // outputs per lane per round
+};
+
+hipError_t launch_segments(const SegArgs &a, uint32_t grid, uint32_t block, uint32_t store,
+                           hipStream_t st);
+// state[k * ns + ids[i]] = state_next[k * ns + ids[i]] for k < 5.
+hipError_t launch_commit(uint32_t *state, const uint32_t *state_next, const uint32_t *ids,
+                         uint32_t count, uint32_t ns, hipStream_t st);
+hipError_t launch_zero_u32(uint32_t *p, uint32_t count, hipStream_t st);
+
+hipError_t launch_fill(uint32_t *dst, uint64_t n_words, uint32_t value, hipStream_t st);
+hipError_t launch_copy(uint32_t *dst, const uint32_t *src, uint64_t n_words, hipStream_t st);
+
+}  // namespace cprng_impl

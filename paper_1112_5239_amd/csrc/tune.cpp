@@ -1,0 +1,202 @@
+// tune.cpp -- launch-configuration autotuner with a JSON cache.
+//
+// Candidates are timed with HIP events on the caller's stream (median of a
+// few launches after one warm-up); the fastest is kept in a process-wide
+// table and, if $CPRNG_TUNE_CACHE names a file, written there as JSON:
+//   { "<key>": {"block": B, "unroll": U, "store": S, "chunk": C, "waves": W}, ... }
+// Keys name the device architecture, variant and a power-of-two bucket of
+// the shape, so one tuning serves every shape of the same class.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "tune.h"
+
+namespace cprng_impl {
+
+namespace {
+
+std::mutex g_mu;
+std::map<std::string, TuneEntry> g_table;
+bool g_loaded = false;
+
+int log2_bucket(uint64_t v)
+{
+    int b = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+std::string arch_name(int device)
+{
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return "unknown";
+    std::string a = p.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+const char *cache_path()
+{
+    const char *p = std::getenv("CPRNG_TUNE_CACHE");
+    return (p && *p) ? p : nullptr;
+}
+
+void load_file_locked()
+{
+    if (g_loaded) return;
+    g_loaded = true;
+    const char *path = cache_path();
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        char key[256];
+        TuneEntry e;
+        if (std::sscanf(line, " \"%255[^\"]\" : {\"block\": %u, \"unroll\": %u, \"store\": %u, \"chunk\": %u, \"waves\": %u}",
+                        key, &e.block, &e.unroll, &e.store, &e.chunk, &e.waves) == 6)
+            g_table[key] = e;
+    }
+    std::fclose(f);
+}
+
+void save_file_locked()
+{
+    const char *path = cache_path();
+    if (!path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto &kv : g_table) {
+        const TuneEntry &e = kv.second;
+        std::fprintf(f, "  \"%s\": {\"block\": %u, \"unroll\": %u, \"store\": %u, \"chunk\": %u, \"waves\": %u}%s\n",
+                     kv.first.c_str(), e.block, e.unroll, e.store, e.chunk, e.waves,
+                     ++i < g_table.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
+
+}  // namespace
+
+LaunchCfg default_cfg(uint32_t variant, bool w32, bool consume)
+{
+    (void)w32;
+    LaunchCfg c;
+    c.block = 256;
+    c.unroll = (variant == CPRNG_V1_NAIVE3) ? 16 : 32;
+    c.store = ST_DIRECT;
+    if (consume) c.unroll = 16;
+    return c;
+}
+
+std::string tune_key_generate(const cprng_t *h, uint64_t n)
+{
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s/gen/v%u%s/ns2^%d/n2^%d", arch_name(h->device).c_str(), h->variant,
+                  (h->flags & CPRNG_F_V1_W32) ? "w32" : "", log2_bucket(h->ns), log2_bucket(n));
+    return buf;
+}
+
+std::string tune_key_ragged(const cprng_t *h, uint64_t total, uint64_t max_len)
+{
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s/ragged/v%u/ns2^%d/total2^%d/max2^%d", arch_name(h->device).c_str(),
+                  h->variant, log2_bucket(h->ns), log2_bucket(total), log2_bucket(max_len));
+    return buf;
+}
+
+void tune_cache_load(cprng_t *)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_file_locked();
+}
+
+bool tune_cache_lookup_key(const std::string &key, TuneEntry *e)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_file_locked();
+    auto it = g_table.find(key);
+    if (it == g_table.end()) return false;
+    *e = it->second;
+    return true;
+}
+
+bool tune_cache_lookup(const cprng_t *h, uint64_t n, TuneEntry *e)
+{
+    return tune_cache_lookup_key(tune_key_generate(h, n), e);
+}
+
+void tune_cache_store(const std::string &key, const TuneEntry &e)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_file_locked();
+    g_table[key] = e;
+    save_file_locked();
+}
+
+}  // namespace cprng_impl
+
+using namespace cprng_impl;
+
+extern "C" int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n, cprng_stream_t stream)
+{
+    if (!h || !scratch || n == 0) return set_error(CPRNG_E_INVAL, "NULL handle/scratch or n == 0");
+    if (h->flags & CPRNG_F_INTERLEAVED) return set_error(CPRNG_E_UNSUPPORTED, "autotune covers the stream-major layout");
+    if ((uintptr_t)scratch % 16u || n % 4u)
+        return set_error(CPRNG_E_INVAL, "autotune needs a 16-byte aligned buffer and n % 4 == 0");
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return set_error(CPRNG_E_HIP, "hipEventCreate");
+    const uint32_t blocks[] = {64, 128, 256};
+    const uint32_t unrolls[] = {8, 16, 32};
+    const uint32_t stores[] = {ST_DIRECT, ST_LDS, ST_DIRECT_NT, ST_LDS_NT};
+    float best = 1e30f;
+    TuneEntry best_e;
+    const bool saved_timing = h->timing;
+    h->timing = false;
+    int rc = CPRNG_OK;
+    for (uint32_t b : blocks)
+        for (uint32_t u : unrolls)
+            for (uint32_t s : stores) {
+                if (h->variant == CPRNG_V1_NAIVE3 && u == 32) continue;
+                LaunchCfg c{b, u, s};
+                std::vector<float> t;
+                for (int r = 0; r < 4 && rc == CPRNG_OK; ++r) {
+                    if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
+                    if (rc == CPRNG_OK) rc = generate_with(h, scratch, n, st, c);
+                    if (rc == CPRNG_OK && hipEventRecord(e1, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
+                    if (rc == CPRNG_OK && hipEventSynchronize(e1) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventSynchronize");
+                    float ms = 0.f;
+                    if (rc == CPRNG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = set_error(CPRNG_E_HIP, "elapsed");
+                    if (r > 0) t.push_back(ms);
+                }
+                if (rc != CPRNG_OK) break;
+                std::sort(t.begin(), t.end());
+                const float med = t[t.size() / 2];
+                if (med < best) {
+                    best = med;
+                    best_e.block = b;
+                    best_e.unroll = u;
+                    best_e.store = s;
+                }
+            }
+    h->timing = saved_timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != CPRNG_OK) return rc;
+    tune_cache_store(tune_key_generate(h, n), best_e);
+    return CPRNG_OK;
+}

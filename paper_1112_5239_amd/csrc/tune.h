@@ -1,0 +1,24 @@
+// tune.h -- launch configuration defaults, the autotuner and its JSON cache.
+#pragma once
+
+#include <string>
+
+#include "host.h"
+
+namespace cprng_impl {
+
+struct TuneEntry {
+    uint32_t block = 0, unroll = 0, store = 0, chunk = 0, waves = 0;
+};
+
+LaunchCfg default_cfg(uint32_t variant, bool w32, bool consume);
+std::string tune_key_generate(const cprng_t *h, uint64_t n);
+std::string tune_key_ragged(const cprng_t *h, uint64_t total, uint64_t max_len);
+void tune_cache_load(cprng_t *h);
+bool tune_cache_lookup(const cprng_t *h, uint64_t n, TuneEntry *e);
+bool tune_cache_lookup_key(const std::string &key, TuneEntry *e);
+void tune_cache_store(const std::string &key, const TuneEntry &e);
+
+int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchCfg c);
+
+}  // namespace cprng_impl

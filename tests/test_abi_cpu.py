@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+The library must load, export every function include/cprng.h declares, and
+reject invalid arguments that are checked before any device work.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cprng.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(cprng_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1112_5239_amd import _lib
+    return _lib
+
+
+def test_library_exports_every_declared_symbol(L):
+    lib = L.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 20
+    missing = [n for n in declared if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(L.EXPORTED) == declared
+
+
+def test_status_strings(L):
+    assert L.cprng_strerror(0) == "ok"
+    assert L.cprng_strerror(-1) == "invalid argument"
+    assert L.cprng_strerror(-4) == "unsupported"
+
+
+def test_invalid_arguments_rejected_before_device_work(L):
+    with pytest.raises(L.CprngError) as e:
+        L.cprng_create(0, 0, 0)                      # n_streams == 0
+    assert e.value.status == L.E_INVAL
+    with pytest.raises(L.CprngError) as e:
+        L.cprng_create(0, 64, 7)                     # unknown variant
+    assert e.value.status == L.E_INVAL
+    with pytest.raises(L.CprngError) as e:
+        L.cprng_create(0, 100, L.V2_SHMEM)           # 100 % 32 != 0
+    assert e.value.status == L.E_INVAL
+    with pytest.raises(L.CprngError) as e:
+        L.cprng_create_ex(L.V2_SHMEM, 96, 0, group=3)  # group not a power of two
+    assert e.value.status == L.E_UNSUPPORTED
+    with pytest.raises(L.CprngError) as e:
+        L.cprng_create(0, 64, L.V0_PLAIN | L.F_V1_W32)  # W32 flag on V0
+    assert e.value.status == L.E_INVAL
+    with pytest.raises(L.CprngError) as e:
+        L.cprng_create_ex(L.V2_SHMEM, 64, 0, group=4, comb1=[1, 2, 3, 9], comb2=[2, 3, 0, 1])
+    assert e.value.status == L.E_INVAL
+    lib = L.lib()
+    assert lib.cprng_generate(None, None, 4, None) == L.E_INVAL
+    assert lib.cprng_consume_qc(None, None, 4, None) == L.E_INVAL
+    assert lib.cprng_state_words(None) == L.E_INVAL
+    assert lib.cprng_last_kernel_ms(None) < 0
+    lib.cprng_destroy(None)                          # no-op
+
+
+def test_default_combs_match_the_oracle_reading(L, orc):
+    # Two independent implementations of the same reading of Algorithm 4's
+    # unspecified combination arrays must agree.
+    for Cg in (4, 8, 16, 32, 64):
+        c1, c2 = L.cprng_default_combs(Cg)
+        o1, o2 = orc.comb_tables(Cg)
+        assert c1 == o1.tolist() and c2 == o2.tolist()
+    with pytest.raises(L.CprngError):
+        L.cprng_default_combs(2)
+
+
+def test_header_is_plain_c(tmp_path):
+    # The boundary header compiles as C99 on its own (no HIP or torch types).
+    src = tmp_path / "t.c"
+    src.write_text('#include "cprng.h"\nint main(void){cprng_params_t p; (void)p; return 0;}\n')
+    import subprocess
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                        str(src), "-o", str(tmp_path / "t")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr

@@ -1,0 +1,244 @@
+"""GPU parity: the HIP kernels (through the C ABI) against the CPU oracle.
+
+Integer outputs are compared bit for bit.  Sizes span several tiles of every
+kernel plus ragged tails; the full-size paper-shaped case is checked on the
+first 64 streams plus a seeded 1% sample of streams expanded to whole
+exchange groups.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def G(torch):
+    from paper_1112_5239_amd import generator
+    return generator
+
+
+def _oracle_states(orc, variant, sigma, ns, W=64):
+    return orc.seed(variant, sigma, 0, ns, W=W)
+
+
+def _gen_check(orc, G, variant_name, variant, ns, n, sigma=0, w32=False, calls=1, tuning=None,
+               comb=None, group=0):
+    W = 32 if w32 else 64
+    g = G.Generator(ns, variant_name, seed=sigma, w32=w32, comb=comb, group=group)
+    try:
+        if tuning:
+            g.set_tuning(**tuning)
+        st = _oracle_states(orc, variant, sigma, ns, W)
+        assert np.array_equal(g.get_state(), st), "seeding differs"
+        combs = None
+        if variant == 2:
+            combs = comb if comb is not None else orc.comb_tables(group or 32)
+        for _ in range(calls):
+            got = G.as_u32(g.generate(n))
+            want, _ = orc.generate(variant, st, n, W=W, comb=combs)
+            assert got.shape == want.shape
+            bad = np.argwhere(got != want)
+            assert bad.size == 0, f"first mismatch at {bad[:3].tolist()}"
+        assert np.array_equal(g.get_state(), st), "end state differs"
+    finally:
+        g.close()
+
+
+# ---------------------------------------------------------------------------
+# Plain generator, 1,024 streams x 1,024 outputs, seed 0 (V0 and V1).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("store", [1, 2, 3, 4])
+@pytest.mark.parametrize("unroll", [8, 16, 32])
+def test_v0_plain_1024x1024_all_store_modes(orc, G, store, unroll):
+    _gen_check(orc, G, "v0", 0, 1024, 1024, sigma=0, tuning=dict(store=store, unroll=unroll, block=256))
+
+
+@pytest.mark.parametrize("w32", [False, True])
+def test_v1_naive3_1024x1024(orc, G, w32):
+    _gen_check(orc, G, "v1", 1, 1024, 1024, sigma=0, w32=w32)
+
+
+@pytest.mark.parametrize("store", [1, 2])
+def test_v1_naive3_store_modes_and_blocks(orc, G, store):
+    for block in (64, 128):
+        _gen_check(orc, G, "v1", 1, 640, 96, sigma=5, tuning=dict(store=store, unroll=16, block=block))
+
+
+# ---------------------------------------------------------------------------
+# Neighbour-exchange variant (Algorithm 4).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("store", [1, 2, 3, 4])
+def test_v2_shmem_4096x1024(orc, G, store):
+    _gen_check(orc, G, "v2", 2, 4096, 1024, sigma=1, tuning=dict(store=store, unroll=32, block=256))
+
+
+@pytest.mark.parametrize("group", [4, 8, 16, 64])
+def test_v2_other_group_sizes_default_combs(orc, G, group):
+    _gen_check(orc, G, "v2", 2, 512, 200, sigma=3, group=group)
+
+
+def test_v2_custom_combs_and_partial_wave(orc, G):
+    # 96 streams = one full wave plus half a wave; explicit combination arrays.
+    rng = np.random.default_rng(17)
+    c1 = rng.permutation(32).astype(np.uint32)
+    c2 = rng.permutation(32).astype(np.uint32)
+    for store in (1, 2):
+        _gen_check(orc, G, "v2", 2, 96, 64, sigma=9, comb=(c1, c2), group=32,
+                   tuning=dict(store=store, unroll=16, block=128))
+
+
+# ---------------------------------------------------------------------------
+# Tails, alignment, continuation, interleaved layout.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("variant_name,variant", [("v0", 0), ("v1", 1), ("v2", 2)])
+@pytest.mark.parametrize("n", [1, 3, 4, 37, 100, 1029])
+def test_ragged_tail_lengths(orc, G, variant_name, variant, n):
+    ns = 160 if variant == 2 else 131           # partial last wave
+    _gen_check(orc, G, variant_name, variant, ns, n, sigma=2)
+
+
+@pytest.mark.parametrize("variant_name,variant", [("v0", 0), ("v1", 1), ("v2", 2)])
+def test_continuation_across_calls(orc, G, variant_name, variant):
+    _gen_check(orc, G, variant_name, variant, 256, 64, sigma=4, calls=3)
+
+
+def test_misaligned_output_pointer(orc, G, torch):
+    g = G.Generator(100, "v0", seed=6)
+    try:
+        buf = torch.zeros(100 * 64 + 1, dtype=torch.int32, device="cuda")
+        g.generate(64, out=buf[1:])               # 4-byte but not 16-byte aligned
+        want, _ = orc.generate(0, _oracle_states(orc, 0, 6, 100), 64)
+        assert np.array_equal(G.as_u32(buf[1:]).reshape(100, 64), want)
+        assert G.as_u32(buf[:1])[0] == 0
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("variant_name,variant", [("v0", 0), ("v2", 2), ("v1", 1)])
+def test_interleaved_layout(orc, G, variant_name, variant):
+    ns, n = 192, 50
+    g = G.Generator(ns, variant_name, seed=8, interleaved=True)
+    try:
+        got = G.as_u32(g.generate(n))
+        assert got.shape == (n, ns)
+        want, _ = orc.generate(variant, _oracle_states(orc, variant, 8, ns), n)
+        assert np.array_equal(got.T, want)
+    finally:
+        g.close()
+
+
+def test_checkpoint_resume(orc, G):
+    g = G.Generator(256, "v2", seed=10)
+    try:
+        g.generate(100)
+        snap = g.get_state()
+        a = G.as_u32(g.generate(77))
+        g.close()
+        g = G.Generator(256, "v2", seed=999)
+        g.set_state(snap)
+        b = G.as_u32(g.generate(77))
+        assert np.array_equal(a, b)
+        bad = snap.copy()
+        bad[3, :4] = 0
+        with pytest.raises(Exception):
+            g.set_state(bad)
+    finally:
+        g.close()
+
+
+# ---------------------------------------------------------------------------
+# Paper-shaped run: 2^20 streams x 1,024 outputs (4 GiB), exchange variant,
+# seed 1.  First 64 streams in full plus a seeded 1% sample of streams
+# expanded to their whole groups of 32.
+# ---------------------------------------------------------------------------
+def _sample_groups(ns, frac=0.01, group=32, seed=20111223):
+    rng = np.random.default_rng(seed)
+    picks = rng.choice(ns, size=int(ns * frac), replace=False)
+    groups = np.unique(picks // group)
+    return np.unique(np.concatenate([np.arange(64) // group, groups]))
+
+
+def test_v2_paper_shape_sampled(orc, G, torch):
+    ns, n = 1 << 20, 1024
+    g = G.Generator(ns, "v2", seed=1)
+    try:
+        out = g.generate(n)
+        torch.cuda.synchronize()
+        groups = _sample_groups(ns)
+        combs = orc.comb_tables(32)
+        idx = torch.from_numpy(np.concatenate([np.arange(gr * 32, gr * 32 + 32) for gr in groups])).cuda()
+        got = G.as_u32(out.index_select(0, idx))
+        for k, gr in enumerate(groups):
+            st = orc.seed(2, 1, gr * 32, 32)
+            want, _ = orc.generate(2, st, n, comb=combs)
+            assert np.array_equal(got[k * 32:(k + 1) * 32], want), f"group {gr}"
+        assert len(groups) > 300
+        del out
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("variant_name,variant", [("v0", 0), ("v1", 1)])
+def test_plain_paper_shape_sampled(orc, G, torch, variant_name, variant):
+    ns, n = 1 << 20, 1024
+    g = G.Generator(ns, variant_name, seed=1)
+    try:
+        out = g.generate(n)
+        rng = np.random.default_rng(7)
+        streams = np.unique(np.concatenate([np.arange(64), rng.choice(ns, 2000, replace=False),
+                                            [ns - 1]]))
+        got = G.as_u32(out.index_select(0, torch.from_numpy(streams).cuda()))
+        for k, s in enumerate(streams):
+            st = orc.seed(variant, 1, int(s), 1)
+            want, _ = orc.generate(variant, st, n)
+            assert np.array_equal(got[k], want[0]), f"stream {s}"
+        del out
+    finally:
+        g.close()
+
+
+# ---------------------------------------------------------------------------
+# In-kernel consumption: per-stream counts bit-exact.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("variant_name,variant", [("v0", 0), ("v2", 2), ("v1", 1)])
+def test_consume_counts_small(orc, G, variant_name, variant):
+    ns, n = 256, 4096
+    g = G.Generator(ns, variant_name, seed=3)
+    try:
+        st = _oracle_states(orc, variant, 3, ns)
+        for _ in range(2):
+            got = g.consume_qc(n).cpu().numpy().astype(np.uint64)
+            want = orc.consume_qc(variant, st, n)
+            assert np.array_equal(got, want)
+        assert np.array_equal(g.get_state(), st)
+    finally:
+        g.close()
+
+
+def test_consume_paper_scale_sampled(orc, G, torch):
+    # 2^36 numbers: 2^20 streams x 2^16, exchange variant, seed 3.
+    ns, n = 1 << 20, 1 << 16
+    g = G.Generator(ns, "v2", seed=3)
+    try:
+        counts = g.consume_qc(n).cpu().numpy().astype(np.uint64)
+        groups = _sample_groups(ns, frac=0.0001)
+        combs = orc.comb_tables(32)
+        for gr in groups:
+            st = orc.seed(2, 3, gr * 32, 32)
+            want = orc.consume_qc(2, st, n, comb=combs)
+            assert np.array_equal(counts[gr * 32:(gr + 1) * 32], want), f"group {gr}"
+        total = int(counts.sum())
+        pairs = ns * n // 2
+        pi_est = 4 * total / pairs
+        sigma = 4 * np.sqrt((np.pi / 4) * (1 - np.pi / 4) / pairs)
+        assert abs(pi_est - np.pi) < 6 * sigma
+    finally:
+        g.close()
