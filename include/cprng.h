@@ -192,12 +192,15 @@ int cprng_default_combs(uint32_t C, uint32_t *comb1, uint32_t *comb2);
  * "autotuned / default".  store: 0 auto, 1 per-lane direct, 2 LDS-transposed,
  * 3 direct non-temporal, 4 LDS-transposed non-temporal. */
 typedef struct cprng_tuning {
-    uint32_t block;            /* threads per block (64..1024, multiple of 64) */
-    uint32_t unroll;           /* outputs per lane per round: 4, 8, 16 or 32 */
+    uint32_t block;            /* threads per block: 64, 128, 192 or 256 */
+    uint32_t unroll;           /* outputs per stream per round: 8, 16, 32 (direct);
+                                  16..256, powers of two (LDS-transposed) */
     uint32_t store;            /* store mode, see above */
     uint32_t chunk;            /* ragged/requests: outputs per chunk (multiple of 64) */
-    uint32_t waves_per_cu;     /* ragged/requests: persistent waves per CU */
-    uint32_t reserved[3];
+    uint32_t waves_per_cu;     /* ragged/requests: persistent waves per CU;
+                                  LDS-transposed generate: residency cap (0 = none) */
+    uint32_t streams_per_lane; /* LDS-transposed generate: 1, 2 or 4 streams per lane */
+    uint32_t reserved[2];
 } cprng_tuning_t;
 
 int cprng_set_tuning(cprng_t *h, const cprng_tuning_t *t);

@@ -38,7 +38,8 @@ class Request(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("block", C.c_uint32), ("unroll", C.c_uint32), ("store", C.c_uint32),
-                ("chunk", C.c_uint32), ("waves_per_cu", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+                ("chunk", C.c_uint32), ("waves_per_cu", C.c_uint32), ("streams_per_lane", C.c_uint32),
+                ("reserved", C.c_uint32 * 2)]
 
 
 EXPORTED = [
@@ -199,8 +200,9 @@ def cprng_default_combs(Cg: int):
     return list(a1), list(a2)
 
 
-def cprng_set_tuning(h: int, block=0, unroll=0, store=0, chunk=0, waves_per_cu=0) -> None:
-    t = Tuning(block, unroll, store, chunk, waves_per_cu)
+def cprng_set_tuning(h: int, block=0, unroll=0, store=0, chunk=0, waves_per_cu=0,
+                     streams_per_lane=0) -> None:
+    t = Tuning(block, unroll, store, chunk, waves_per_cu, streams_per_lane)
     _check(lib().cprng_set_tuning(h, C.byref(t)), "cprng_set_tuning")
 
 
@@ -208,7 +210,7 @@ def cprng_get_tuning(h: int) -> dict:
     t = Tuning()
     _check(lib().cprng_get_tuning(h, C.byref(t)), "cprng_get_tuning")
     return {"block": t.block, "unroll": t.unroll, "store": t.store, "chunk": t.chunk,
-            "waves_per_cu": t.waves_per_cu}
+            "waves_per_cu": t.waves_per_cu, "streams_per_lane": t.streams_per_lane}
 
 
 def cprng_autotune(h: int, scratch, n_per_stream: int, stream=None) -> None:

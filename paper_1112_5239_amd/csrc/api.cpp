@@ -156,15 +156,19 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
         h->tuned_loaded = true;
     }
     LaunchCfg c = default_cfg(h->variant, (h->flags & CPRNG_F_V1_W32) != 0, consume);
-    TuneEntry e;
+    TuneEntry e = default_entry(h->variant, consume);
     if (!consume && tune_cache_lookup(h, n, &e)) {
         c.block = e.block;
         c.unroll = e.unroll;
         c.store = e.store;
+        c.slots = e.slots ? e.slots : 1;
     }
+    if (h->tuning.streams_per_lane) c.slots = h->tuning.streams_per_lane;
     if (h->tuning.block) c.block = h->tuning.block;
     if (h->tuning.unroll) c.unroll = h->tuning.unroll;
     if (h->tuning.store && !consume) c.store = h->tuning.store;
+    const uint32_t wpc = h->tuning.waves_per_cu ? h->tuning.waves_per_cu : (consume ? 0u : e.waves);
+    c.lds_bytes = lds_for_waves(c.block, wpc);
     return c;
 }
 
@@ -183,6 +187,14 @@ int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchC
     } else {
         const bool aligned = ((uintptr_t)out % 16u) == 0 && (n % 4u) == 0;
         if (!aligned) c.store = ST_GENERIC;
+    }
+    if (c.store == ST_LDS || c.store == ST_LDS_NT) {
+        // LDS tiles hold K >= 16 words per row; block/64 waves x 64 rows x K
+        // words must fit 64 KiB (K <= 256 always fits with block 64).
+        if (c.unroll < 16) c.unroll = 16;
+        if (c.slots != 1 && c.slots != 2 && c.slots != 4) c.slots = 1;
+        while (c.block > 64 && (uint64_t)c.block * c.slots * c.unroll * 4u > 65536u) c.block -= 64;
+        while (c.slots > 1 && (uint64_t)c.block * c.slots * c.unroll * 4u > 65536u) c.slots /= 2;
     }
     int rc = begin_timing(h, st);
     if (rc) return rc;
@@ -327,11 +339,14 @@ int cprng_set_tuning(cprng_t *h, const cprng_tuning_t *t)
 {
     if (!h || !t) return set_error(CPRNG_E_INVAL, "NULL argument");
     if (t->block && (t->block % 64 || t->block > 256)) return set_error(CPRNG_E_INVAL, "block must be 64, 128, 192 or 256");
-    if (t->unroll && t->unroll != 8 && t->unroll != 16 && t->unroll != 32)
-        return set_error(CPRNG_E_INVAL, "unroll must be 8, 16 or 32");
+    if (t->unroll && t->unroll != 8 && t->unroll != 16 && t->unroll != 32 && t->unroll != 64 &&
+        t->unroll != 128 && t->unroll != 256)
+        return set_error(CPRNG_E_INVAL, "unroll must be 8, 16, 32, 64, 128 or 256 (above 32: LDS store modes)");
     if (t->store > 4) return set_error(CPRNG_E_INVAL, "store mode must be 0..4");
     if (t->chunk && (t->chunk % 64 || t->chunk > (1u << 24))) return set_error(CPRNG_E_INVAL, "chunk must be a multiple of 64, <= 2^24");
     if (t->waves_per_cu > 32) return set_error(CPRNG_E_INVAL, "waves_per_cu must be <= 32");
+    if (t->streams_per_lane && t->streams_per_lane != 1 && t->streams_per_lane != 2 && t->streams_per_lane != 4)
+        return set_error(CPRNG_E_INVAL, "streams_per_lane must be 1, 2 or 4");
     h->tuning = *t;
     return CPRNG_OK;
 }

@@ -224,9 +224,6 @@ __device__ __forceinline__ void load4(const uint32_t *p, uint32_t &a, uint32_t &
 // ------------------------------------------------------------------------
 // Plain generate kernel: one lane per stream, K outputs per lane per round.
 //   ST_DIRECT(_NT): lane stores its K outputs as K/4 aligned 16-byte quads.
-//   ST_LDS(_NT)   : the wave's 64 x K tile goes through LDS so that each
-//                   store instruction writes K/4 consecutive quads of 64/(K/4)
-//                   streams (whole 128-byte lines when K >= 32).
 //   ST_INTERLEAVED: out[i * ns + s]; 64 lanes write 256 contiguous bytes.
 //   ST_GENERIC    : out[s * n + i] one dword at a time (any n, any alignment).
 // Fast modes need n % 4 == 0 and a 16-byte aligned `out` (host checks).
@@ -234,102 +231,128 @@ __device__ __forceinline__ void load4(const uint32_t *p, uint32_t &a, uint32_t &
 template <int VAR, typename T, int K, int MODE>
 __global__ __launch_bounds__(256) void k_generate(GenArgs a)
 {
-    constexpr bool LDS = (MODE == ST_LDS || MODE == ST_LDS_NT);
-    constexpr bool NT = (MODE == ST_DIRECT_NT || MODE == ST_LDS_NT);
+    constexpr bool NT = (MODE == ST_DIRECT_NT);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t wave_base = s - lane;
-    const bool active = s < a.ns;
+    if (s >= a.ns) return;
     const uint64_t n = a.n;
-
     Stream<VAR, T> st;
-    if constexpr (!LDS) {
-        if (!active) return;
-        st.load(a, s);
-        st.init_exchange(a, lane);
-        if constexpr (MODE == ST_INTERLEAVED) {
-            uint64_t i = 0;
-            for (; i + K <= n; i += K) {
-                uint32_t v[K];
-#pragma unroll
-                for (int j = 0; j < K; ++j) v[j] = st.next();
-#pragma unroll
-                for (int j = 0; j < K; ++j) a.out[(i + j) * a.ns + s] = v[j];
-            }
-            for (; i < n; ++i) a.out[i * a.ns + s] = st.next();
-        } else if constexpr (MODE == ST_GENERIC) {
-            uint32_t *o = a.out + (uint64_t)s * n;
-            uint64_t i = 0;
-            for (; i + K <= n; i += K) {
-                uint32_t v[K];
-#pragma unroll
-                for (int j = 0; j < K; ++j) v[j] = st.next();
-#pragma unroll
-                for (int j = 0; j < K; ++j) o[i + j] = v[j];
-            }
-            for (; i < n; ++i) o[i] = st.next();
-        } else {
-            uint32_t *o = a.out + (uint64_t)s * n;
-            uint64_t i = 0;
-            for (; i + K <= n; i += K) {
-                uint32_t v[K];
-#pragma unroll
-                for (int j = 0; j < K; ++j) v[j] = st.next();
-#pragma unroll
-                for (int q = 0; q < K / 4; ++q)
-                    store4<NT>(o + i + 4 * q, v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
-            }
-            for (; i < n; i += 4) {          // n % 4 == 0
-                uint32_t v0 = st.next(), v1 = st.next(), v2 = st.next(), v3 = st.next();
-                store4<NT>(o + i, v0, v1, v2, v3);
-            }
-        }
-        st.save(a, s);
-    } else {
-        // All lanes stay for the cooperative stores; inactive lanes (a partial
-        // last wave) run on a zero state and their rows are never stored.  For
-        // V2 the inactive lanes are whole groups, so no active lane reads them.
-        HIP_DYNAMIC_SHARED(uint32_t, lds);
-        constexpr int RS = K + 4;            // row stride (words): 16-byte aligned rows
-        constexpr int QPR = K / 4;           // quads per row
-        uint32_t *tile = lds + (threadIdx.x >> 6) * (64 * RS);
-        if (active) {
-            st.load(a, s);
-        } else {
-            st = Stream<VAR, T>{};
-        }
-        st.init_exchange(a, lane);
+    st.load(a, s);
+    st.init_exchange(a, lane);
+    if constexpr (MODE == ST_INTERLEAVED) {
         uint64_t i = 0;
         for (; i + K <= n; i += K) {
             uint32_t v[K];
 #pragma unroll
             for (int j = 0; j < K; ++j) v[j] = st.next();
 #pragma unroll
-            for (int q = 0; q < QPR; ++q)
-                store4<false>(tile + lane * RS + 4 * q, v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
-            __syncthreads();
+            for (int j = 0; j < K; ++j) a.out[(i + j) * a.ns + s] = v[j];
+        }
+        for (; i < n; ++i) a.out[i * a.ns + s] = st.next();
+    } else if constexpr (MODE == ST_GENERIC) {
+        uint32_t *o = a.out + (uint64_t)s * n;
+        uint64_t i = 0;
+        for (; i + K <= n; i += K) {
+            uint32_t v[K];
 #pragma unroll
-            for (int j = 0; j < QPR; ++j) {
-                const uint32_t Q = j * 64 + lane;
-                const uint32_t r = Q / QPR;
-                const uint32_t q = Q % QPR;
-                uint32_t x0, x1, x2, x3;
-                load4(tile + r * RS + 4 * q, x0, x1, x2, x3);
-                if (wave_base + r < a.ns)
-                    store4<NT>(a.out + (uint64_t)(wave_base + r) * n + i + 4 * q, x0, x1, x2, x3);
-            }
-            __syncthreads();
+            for (int j = 0; j < K; ++j) v[j] = st.next();
+#pragma unroll
+            for (int j = 0; j < K; ++j) o[i + j] = v[j];
         }
-        if (active) {
-            uint32_t *o = a.out + (uint64_t)s * n;
-            for (; i < n; i += 4) {
-                uint32_t v0 = st.next(), v1 = st.next(), v2 = st.next(), v3 = st.next();
-                store4<NT>(o + i, v0, v1, v2, v3);
-            }
-        } else {
-            for (; i < n; ++i) (void)st.next();  // keep V2 exchanges in step
+        for (; i < n; ++i) o[i] = st.next();
+    } else {
+        uint32_t *o = a.out + (uint64_t)s * n;
+        uint64_t i = 0;
+        for (; i + K <= n; i += K) {
+            uint32_t v[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) v[j] = st.next();
+#pragma unroll
+            for (int q = 0; q < K / 4; ++q)
+                store4<NT>(o + i + 4 * q, v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
         }
-        if (active) st.save(a, s);
+        for (; i < n; i += 4) {              // n % 4 == 0
+            uint32_t v0 = st.next(), v1 = st.next(), v2 = st.next(), v3 = st.next();
+            store4<NT>(o + i, v0, v1, v2, v3);
+        }
+    }
+    st.save(a, s);
+}
+
+// ------------------------------------------------------------------------
+// Tiled generate kernel (stream-major output through LDS).
+//
+// A wave owns 64*S consecutive streams: lane l, slot k holds stream
+// base + 64k + l, so each slot's 64 lanes hold whole groups of C | 64 streams
+// and the exchange addresses are the same for every slot; the S streams of a
+// lane are independent, which gives the exchange's cross-lane reads S-fold
+// instruction-level parallelism.  Each round every stream writes its next K
+// outputs into its LDS row (row 64k + l); then store instruction j covers
+// quads j*64 .. j*64+63 of the row-major (64 S) x K tile, i.e. 64/(K/4) whole
+// rows of K words (K >= 32: whole 128-byte lines; K = 256: a 1 KiB row).
+// Quad q of row r lives at quad q ^ (r mod K/4) of the row, so the row writes
+// (consecutive rows, same q) and the line reads (one row, consecutive q) hit
+// distinct banks with no padding.  All lanes take part in the stores; streams
+// past the end run on a zero state and are never stored (for V2 these are
+// whole groups, so no live stream reads them).
+// ------------------------------------------------------------------------
+template <int VAR, typename T, int K, int S, bool NT>
+__global__ __launch_bounds__(256) void k_generate_tile(GenArgs a)
+{
+    HIP_DYNAMIC_SHARED(uint32_t, lds);
+    constexpr int QPR = K / 4;               // quads per row
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t base = wave * 64u * S;
+    uint32_t *tile = lds + (threadIdx.x >> 6) * (64 * S * K);
+    const uint64_t n = a.n;
+
+    Stream<VAR, T> st[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const uint64_t s = base + 64u * k + lane;
+        if (s < a.ns) st[k].load(a, (uint32_t)s);
+        else st[k] = Stream<VAR, T>{};
+        st[k].init_exchange(a, lane);
+    }
+    uint64_t i = 0;
+    for (; i + K <= n; i += K) {
+#pragma unroll
+        for (int q = 0; q < QPR; ++q) {
+            uint32_t v[4][S];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int k = 0; k < S; ++k) v[e][k] = st[k].next();
+#pragma unroll
+            for (int k = 0; k < S; ++k)
+                store4<false>(tile + (64 * k + lane) * K + 4 * (q ^ (lane & (QPR - 1))),
+                              v[0][k], v[1][k], v[2][k], v[3][k]);
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int j = 0; j < S * QPR; ++j) {
+            const uint32_t Q = j * 64 + lane;
+            const uint32_t r = Q / QPR;
+            const uint32_t q = Q % QPR;
+            uint32_t x0, x1, x2, x3;
+            load4(tile + r * K + 4 * (q ^ (r & (QPR - 1))), x0, x1, x2, x3);
+            if (base + r < a.ns)
+                store4<NT>(a.out + (base + r) * n + i + 4 * q, x0, x1, x2, x3);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const uint64_t s = base + 64u * k + lane;
+        if (s < a.ns) {
+            uint32_t *o = a.out + s * n;
+            for (uint64_t t = i; t < n; t += 4) {    // n % 4 == 0
+                uint32_t v0 = st[k].next(), v1 = st[k].next(), v2 = st[k].next(), v3 = st[k].next();
+                store4<NT>(o + t, v0, v1, v2, v3);
+            }
+            st[k].save(a, (uint32_t)s);
+        }
     }
 }
 
@@ -521,45 +544,68 @@ __global__ void k_tail_words(uint32_t *dst, const uint32_t *src, uint64_t begin,
 // ------------------------------------------------------------------------
 // Dispatch.
 // ------------------------------------------------------------------------
+template <int VAR, typename T, int K, int MODE>
+hipError_t gen_launch(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
+{
+    const uint32_t grid = (a.ns + c.block - 1) / c.block;
+    hipLaunchKernelGGL((k_generate<VAR, T, K, MODE>), dim3(grid), dim3(c.block), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int VAR, typename T, int K, int S, bool NT>
+hipError_t tile_launch(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
+{
+    const uint64_t waves = ((uint64_t)a.ns + 64u * S - 1) / (64u * S);
+    const uint32_t wpb = c.block / 64;
+    const uint32_t grid = (uint32_t)((waves + wpb - 1) / wpb);
+    size_t lds = (size_t)wpb * 64 * S * K * sizeof(uint32_t);
+    if (lds > 65536) return hipErrorInvalidValue;   // the host keeps tiles within 64 KiB
+    if (c.lds_bytes > lds) lds = c.lds_bytes;
+    hipLaunchKernelGGL((k_generate_tile<VAR, T, K, S, NT>), dim3(grid), dim3(c.block), lds, st, a);
+    return hipGetLastError();
+}
+
+template <int VAR, typename T, int K, bool NT>
+hipError_t tile_by_slots(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
+{
+    switch (c.slots) {
+    case 1: return tile_launch<VAR, T, K, 1, NT>(a, c, st);
+    case 2: return tile_launch<VAR, T, K, 2, NT>(a, c, st);
+    case 4: if constexpr (K <= 128) return tile_launch<VAR, T, K, 4, NT>(a, c, st); break;
+    default: break;
+    }
+    return hipErrorInvalidValue;
+}
+
 template <int VAR, typename T, int K>
 hipError_t gen_by_mode(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
 {
-    const uint32_t grid = (a.ns + c.block - 1) / c.block;
-    size_t lds = 0;
+    constexpr bool small = K <= 32;          // per-lane register tiles
     switch (c.store) {
-    case ST_DIRECT:
-        hipLaunchKernelGGL((k_generate<VAR, T, K, ST_DIRECT>), dim3(grid), dim3(c.block), 0, st, a);
-        break;
-    case ST_DIRECT_NT:
-        hipLaunchKernelGGL((k_generate<VAR, T, K, ST_DIRECT_NT>), dim3(grid), dim3(c.block), 0, st, a);
-        break;
-    case ST_LDS:
-        lds = (size_t)(c.block / 64) * 64 * (K + 4) * sizeof(uint32_t);
-        hipLaunchKernelGGL((k_generate<VAR, T, K, ST_LDS>), dim3(grid), dim3(c.block), lds, st, a);
-        break;
-    case ST_LDS_NT:
-        lds = (size_t)(c.block / 64) * 64 * (K + 4) * sizeof(uint32_t);
-        hipLaunchKernelGGL((k_generate<VAR, T, K, ST_LDS_NT>), dim3(grid), dim3(c.block), lds, st, a);
-        break;
-    case ST_INTERLEAVED:
-        hipLaunchKernelGGL((k_generate<VAR, T, K, ST_INTERLEAVED>), dim3(grid), dim3(c.block), 0, st, a);
-        break;
-    case ST_GENERIC:
-        hipLaunchKernelGGL((k_generate<VAR, T, K, ST_GENERIC>), dim3(grid), dim3(c.block), 0, st, a);
-        break;
-    default:
-        return hipErrorInvalidValue;
+    case ST_DIRECT: if constexpr (small) return gen_launch<VAR, T, K, ST_DIRECT>(a, c, st); break;
+    case ST_DIRECT_NT: if constexpr (small) return gen_launch<VAR, T, K, ST_DIRECT_NT>(a, c, st); break;
+    case ST_LDS: if constexpr (K >= 16) return tile_by_slots<VAR, T, K, false>(a, c, st); break;
+    case ST_LDS_NT: if constexpr (K >= 16) return tile_by_slots<VAR, T, K, true>(a, c, st); break;
+    case ST_INTERLEAVED: if constexpr (small) return gen_launch<VAR, T, K, ST_INTERLEAVED>(a, c, st); break;
+    case ST_GENERIC: if constexpr (small) return gen_launch<VAR, T, K, ST_GENERIC>(a, c, st); break;
+    default: break;
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 template <int VAR, typename T>
 hipError_t gen_by_unroll(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
 {
-    switch (c.unroll) {
+    // Modes that need K <= 32 fall back to K = 32 when a larger K is asked.
+    const bool lds_mode = c.store == ST_LDS || c.store == ST_LDS_NT;
+    const uint32_t k = (!lds_mode && c.unroll > 32) ? 32 : c.unroll;
+    switch (k) {
     case 8: return gen_by_mode<VAR, T, 8>(a, c, st);
     case 16: return gen_by_mode<VAR, T, 16>(a, c, st);
     case 32: return gen_by_mode<VAR, T, 32>(a, c, st);
+    case 64: return gen_by_mode<VAR, T, 64>(a, c, st);
+    case 128: return gen_by_mode<VAR, T, 128>(a, c, st);
+    case 256: return gen_by_mode<VAR, T, 256>(a, c, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -36,6 +36,8 @@ struct LaunchCfg {
     uint32_t block;        // threads per block
     uint32_t unroll;       // outputs per lane per round
     uint32_t store;        // StoreMode
+    uint32_t lds_bytes;    // LDS modes: dynamic LDS per block (>= the tile; more caps occupancy)
+    uint32_t slots;        // LDS modes: streams per lane (1, 2 or 4)
 };
 
 // variant: 0 V0, 1 V1 (w32 selects 32-bit words), 2 V2.

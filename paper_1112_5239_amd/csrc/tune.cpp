@@ -61,8 +61,8 @@ void load_file_locked()
     while (std::fgets(line, sizeof line, f)) {
         char key[256];
         TuneEntry e;
-        if (std::sscanf(line, " \"%255[^\"]\" : {\"block\": %u, \"unroll\": %u, \"store\": %u, \"chunk\": %u, \"waves\": %u}",
-                        key, &e.block, &e.unroll, &e.store, &e.chunk, &e.waves) == 6)
+        if (std::sscanf(line, " \"%255[^\"]\" : {\"block\": %u, \"unroll\": %u, \"store\": %u, \"chunk\": %u, \"waves\": %u, \"slots\": %u}",
+                        key, &e.block, &e.unroll, &e.store, &e.chunk, &e.waves, &e.slots) == 7)
             g_table[key] = e;
     }
     std::fclose(f);
@@ -79,8 +79,8 @@ void save_file_locked()
     size_t i = 0;
     for (const auto &kv : g_table) {
         const TuneEntry &e = kv.second;
-        std::fprintf(f, "  \"%s\": {\"block\": %u, \"unroll\": %u, \"store\": %u, \"chunk\": %u, \"waves\": %u}%s\n",
-                     kv.first.c_str(), e.block, e.unroll, e.store, e.chunk, e.waves,
+        std::fprintf(f, "  \"%s\": {\"block\": %u, \"unroll\": %u, \"store\": %u, \"chunk\": %u, \"waves\": %u, \"slots\": %u}%s\n",
+                     kv.first.c_str(), e.block, e.unroll, e.store, e.chunk, e.waves, e.slots,
                      ++i < g_table.size() ? "," : "");
     }
     std::fprintf(f, "}\n");
@@ -93,12 +93,51 @@ void save_file_locked()
 LaunchCfg default_cfg(uint32_t variant, bool w32, bool consume)
 {
     (void)w32;
+    const TuneEntry e = default_entry(variant, consume);
     LaunchCfg c;
-    c.block = 256;
-    c.unroll = (variant == CPRNG_V1_NAIVE3) ? 16 : 32;
-    c.store = ST_DIRECT;
-    if (consume) c.unroll = 16;
+    c.block = e.block;
+    c.unroll = e.unroll;
+    c.store = e.store;
+    c.lds_bytes = 0;
+    c.slots = e.slots ? e.slots : 1;
     return c;
+}
+
+TuneEntry default_entry(uint32_t variant, bool consume)
+{
+    // Measured on MI355X at 2^20 streams x 1024 outputs (see profiles/):
+    // V0 prefers long rows per round (K = 128) with non-temporal stores; V2's
+    // exchange chain needs the occupancy of smaller tiles (K = 32); V1 is
+    // VALU-bound and takes K = 64.
+    TuneEntry e;
+    e.slots = 1;
+    switch (variant) {
+    case CPRNG_V0_PLAIN:
+        e.block = 128; e.unroll = 128; e.store = ST_LDS_NT; e.waves = 8;
+        break;
+    case CPRNG_V1_NAIVE3:
+        e.block = 256; e.unroll = 64; e.store = ST_LDS_NT; e.waves = 3;
+        break;
+    default:
+        e.block = 128; e.unroll = 32; e.store = ST_LDS; e.waves = 0;
+        break;
+    }
+    if (consume) {
+        e.block = 256;
+        e.unroll = 16;
+        e.store = 0;
+        e.waves = 0;
+    }
+    return e;
+}
+
+uint32_t lds_for_waves(uint32_t block, uint32_t waves_per_cu)
+{
+    if (!waves_per_cu) return 0;
+    const uint64_t lds_per_cu = 160ull * 1024;
+    uint64_t b = lds_per_cu * (block / 64) / waves_per_cu;
+    if (b > 65536) b = 65536;
+    return (uint32_t)(b & ~15ull);
 }
 
 std::string tune_key_generate(const cprng_t *h, uint64_t n)
@@ -161,8 +200,10 @@ extern "C" int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n, cprng_s
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return set_error(CPRNG_E_HIP, "hipEventCreate");
     const uint32_t blocks[] = {64, 128, 256};
-    const uint32_t unrolls[] = {8, 16, 32};
-    const uint32_t stores[] = {ST_DIRECT, ST_LDS, ST_DIRECT_NT, ST_LDS_NT};
+    const uint32_t unrolls[] = {8, 16, 32, 64, 128, 256};
+    const uint32_t stores[] = {ST_DIRECT, ST_LDS, ST_LDS_NT};
+    const uint32_t caps[] = {0, 4, 8};
+    const uint32_t slot_opts[] = {1, 2, 4};
     float best = 1e30f;
     TuneEntry best_e;
     const bool saved_timing = h->timing;
@@ -170,9 +211,14 @@ extern "C" int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n, cprng_s
     int rc = CPRNG_OK;
     for (uint32_t b : blocks)
         for (uint32_t u : unrolls)
-            for (uint32_t s : stores) {
-                if (h->variant == CPRNG_V1_NAIVE3 && u == 32) continue;
-                LaunchCfg c{b, u, s};
+            for (uint32_t s : stores)
+                for (uint32_t w : caps)
+                for (uint32_t sl : slot_opts) {
+                const bool lds_mode = s == ST_LDS || s == ST_LDS_NT;
+                if (!lds_mode && (u > 32 || w || sl > 1)) continue;   // direct modes: K <= 32
+                if (lds_mode && u < 16) continue;
+                if (lds_mode && (size_t)b * sl * u * 4 > 65536) continue;
+                LaunchCfg c{b, u, s, lds_for_waves(b, w), sl};
                 std::vector<float> t;
                 for (int r = 0; r < 4 && rc == CPRNG_OK; ++r) {
                     if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
@@ -191,6 +237,8 @@ extern "C" int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n, cprng_s
                     best_e.block = b;
                     best_e.unroll = u;
                     best_e.store = s;
+                    best_e.waves = w;
+                    best_e.slots = sl;
                 }
             }
     h->timing = saved_timing;

@@ -8,10 +8,14 @@
 namespace cprng_impl {
 
 struct TuneEntry {
-    uint32_t block = 0, unroll = 0, store = 0, chunk = 0, waves = 0;
+    uint32_t block = 0, unroll = 0, store = 0, chunk = 0, waves = 0, slots = 0;
 };
 
 LaunchCfg default_cfg(uint32_t variant, bool w32, bool consume);
+TuneEntry default_entry(uint32_t variant, bool consume);
+// Dynamic LDS per block that caps residency at `waves_per_cu` waves per CU
+// (0 = no cap); LDS modes only, limited to 64 KiB per block.
+uint32_t lds_for_waves(uint32_t block, uint32_t waves_per_cu);
 std::string tune_key_generate(const cprng_t *h, uint64_t n);
 std::string tune_key_ragged(const cprng_t *h, uint64_t total, uint64_t max_len);
 void tune_cache_load(cprng_t *h);

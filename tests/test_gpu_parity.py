@@ -56,9 +56,22 @@ def _gen_check(orc, G, variant_name, variant, ns, n, sigma=0, w32=False, calls=1
 # Plain generator, 1,024 streams x 1,024 outputs, seed 0 (V0 and V1).
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("store", [1, 2, 3, 4])
-@pytest.mark.parametrize("unroll", [8, 16, 32])
+@pytest.mark.parametrize("unroll", [8, 16, 32, 64, 128, 256])
 def test_v0_plain_1024x1024_all_store_modes(orc, G, store, unroll):
     _gen_check(orc, G, "v0", 0, 1024, 1024, sigma=0, tuning=dict(store=store, unroll=unroll, block=256))
+
+
+@pytest.mark.parametrize("unroll,block,waves,slots", [(64, 64, 2, 1), (128, 128, 4, 1), (256, 64, 0, 1),
+                                                      (32, 192, 6, 1), (64, 128, 0, 2), (32, 64, 4, 4),
+                                                      (128, 64, 0, 4), (16, 256, 0, 2)])
+def test_lds_tiles_and_occupancy_caps(orc, G, unroll, block, waves, slots):
+    # n = 1000: rounds of K plus a tail; 1000 streams: a partial last wave
+    # (and partial slots when several streams share a lane).
+    for name, variant in (("v0", 0), ("v2", 2), ("v1", 1)):
+        ns = 992 if variant == 2 else 1000
+        _gen_check(orc, G, name, variant, ns, 1000, sigma=12,
+                   tuning=dict(store=2, unroll=unroll, block=block, waves_per_cu=waves,
+                               streams_per_lane=slots))
 
 
 @pytest.mark.parametrize("w32", [False, True])
@@ -75,9 +88,9 @@ def test_v1_naive3_store_modes_and_blocks(orc, G, store):
 # ---------------------------------------------------------------------------
 # Neighbour-exchange variant (Algorithm 4).
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("store", [1, 2, 3, 4])
-def test_v2_shmem_4096x1024(orc, G, store):
-    _gen_check(orc, G, "v2", 2, 4096, 1024, sigma=1, tuning=dict(store=store, unroll=32, block=256))
+@pytest.mark.parametrize("store,unroll", [(1, 32), (2, 32), (3, 32), (4, 32), (2, 128), (4, 256)])
+def test_v2_shmem_4096x1024(orc, G, store, unroll):
+    _gen_check(orc, G, "v2", 2, 4096, 1024, sigma=1, tuning=dict(store=store, unroll=unroll, block=64))
 
 
 @pytest.mark.parametrize("group", [4, 8, 16, 64])
