@@ -179,6 +179,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB copy kernel (hardware byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -200,6 +202,15 @@ def main():
         return
 
     ms, wall, numbers, alg_bytes, achieved = run_paper(torch, G, L, args)
+    if args.copy_probe:
+        n_words = 1 << 28
+        src = torch.zeros(n_words, dtype=torch.int32, device="cuda")
+        dst = torch.empty(n_words, dtype=torch.int32, device="cuda")
+        for _ in range(2):
+            L.cprng_probe_copy(dst, src, n_words, torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] copy probe: 2 x 1 GiB copies (k_copy)")
     value = numbers / (ms / 1e3) / 1e9
     log(f"[bench] paper: {ms:.4f} ms/step, {value:.1f} Gnumbers/s, {achieved:.0f} GB/s")
     extra = {}

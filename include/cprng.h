@@ -226,6 +226,84 @@ int cprng_enable_timing(cprng_t *h, int on);
 double cprng_last_kernel_ms(cprng_t *h);
 
 /* ------------------------------------------------------------------------ */
+/* Serving loop (continuous batching over a V0 handle's resident streams).   */
+/*                                                                           */
+/* Each client is one stream of the handle, whose state stays in device      */
+/* memory.  A request (client, length) receives that client's next `length`  */
+/* outputs, in the order the client's requests were submitted.  Results live */
+/* in a device arena of `budget_bytes` owned by the server: a request is     */
+/* admitted when its result fits in the free part of the arena (and the      */
+/* client has no request on the GPU), and its memory returns to the budget   */
+/* when the caller releases the result.  Admitted requests are launched in   */
+/* batches (cprng_generate_requests) on up to `n_gpu_streams` HIP streams,   */
+/* so a batch can start while earlier ones still run; a client appears in at */
+/* most one batch in flight.  Results are identical whatever the mix of      */
+/* requests they were served with.  Not thread-safe: one thread drives it.   */
+/* ------------------------------------------------------------------------ */
+typedef struct cprng_server cprng_server_t;
+
+typedef struct cprng_server_params {
+    uint32_t struct_size;      /* sizeof(cprng_server_params_t) */
+    uint32_t n_gpu_streams;    /* concurrent batches (HIP streams, 1..16); 0 = 2 */
+    uint64_t budget_bytes;     /* result arena = admission budget; 0 = 64 GiB */
+    uint32_t max_batch;        /* requests per batch; 0 = 1024 */
+    uint32_t reserved;
+} cprng_server_params_t;
+
+typedef struct cprng_completion {
+    uint64_t tag;              /* caller's tag from cprng_server_submit */
+    uint32_t client;           /* stream id */
+    int32_t status;            /* CPRNG_OK, or the error of the batch */
+    uint64_t length;           /* outputs */
+    uint32_t *out;             /* device, in the arena; valid until released */
+    uint64_t t_submit_ns;      /* cprng_now_ns() clock: submitted (as given), */
+    uint64_t t_admit_ns;       /* admitted and launched, */
+    uint64_t t_done_ns;        /* completion observed by cprng_server_poll */
+} cprng_completion_t;
+
+/* Steady monotonic clock in nanoseconds (the clock of cprng_completion_t). */
+uint64_t cprng_now_ns(void);
+
+/* Create a server over h (V0 only; h must outlive the server).  Allocates the
+ * arena.  Errors: E_INVAL, E_UNSUPPORTED (not V0), E_NOMEM, E_HIP. */
+int cprng_server_create(cprng_t *h, const cprng_server_params_t *params, cprng_server_t **out);
+
+/* Queue a request of `length` outputs (1 .. budget/4) for `client`; t_submit_ns
+ * is its arrival time on cprng_now_ns()'s clock (0 = now).  Never blocks.
+ * Errors: E_INVAL (client out of range, length 0 or larger than the budget). */
+int cprng_server_submit(cprng_server_t *s, uint32_t client, uint64_t length, uint64_t tag,
+                        uint64_t t_submit_ns);
+
+/* Make progress without blocking: collect finished batches, admit waiting
+ * requests in arrival order (a request that does not fit lets later ones of
+ * other clients pass, unless it has waited more than 20 ms), launch batches
+ * on free HIP streams, and return up to max_done completions (host array).
+ * *n_done receives their number.  Errors: E_INVAL, E_HIP. */
+int cprng_server_poll(cprng_server_t *s, cprng_completion_t *done, uint32_t max_done, uint32_t *n_done);
+
+/* Return a completed result's memory to the budget.  Errors: E_INVAL. */
+int cprng_server_release(cprng_server_t *s, uint32_t *out);
+
+/* Requests waiting for admission, requests on the GPU, arena bytes in use
+ * (admitted and not yet released).  Any pointer may be NULL. */
+int cprng_server_stats(const cprng_server_t *s, uint64_t *waiting, uint64_t *in_flight,
+                       uint64_t *bytes_in_use);
+
+/* Drive the server through a trace in real time: request i (client[i],
+ * length[i]) arrives at start + arrival_ns[i] (non-decreasing); the call
+ * submits each request at its arrival time, polls until every request has
+ * completed, and writes request i's completion to results[i] (host, count
+ * entries; tag = i).  With release_results != 0 each result is released as
+ * soon as it completes (its `out` is then no longer valid).
+ * Errors: E_INVAL, E_HIP. */
+int cprng_server_replay(cprng_server_t *s, const uint64_t *arrival_ns, const uint32_t *client,
+                        const uint64_t *length, uint32_t count, int release_results,
+                        cprng_completion_t *results);
+
+/* Wait for the server's batches and free it.  NULL is a no-op. */
+void cprng_server_destroy(cprng_server_t *s);
+
+/* ------------------------------------------------------------------------ */
 /* Measurement probes (not part of the generator).                           */
 /* ------------------------------------------------------------------------ */
 

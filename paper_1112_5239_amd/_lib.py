@@ -36,6 +36,17 @@ class Request(C.Structure):
                 ("out", C.c_void_p)]
 
 
+class ServerParams(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("n_gpu_streams", C.c_uint32), ("budget_bytes", C.c_uint64),
+                ("max_batch", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("client", C.c_uint32), ("status", C.c_int32), ("length", C.c_uint64),
+                ("out", C.c_void_p), ("t_submit_ns", C.c_uint64), ("t_admit_ns", C.c_uint64),
+                ("t_done_ns", C.c_uint64)]
+
+
 class Tuning(C.Structure):
     _fields_ = [("block", C.c_uint32), ("unroll", C.c_uint32), ("store", C.c_uint32),
                 ("chunk", C.c_uint32), ("waves_per_cu", C.c_uint32), ("streams_per_lane", C.c_uint32),
@@ -48,7 +59,9 @@ EXPORTED = [
     "cprng_set_state", "cprng_n_streams", "cprng_variant", "cprng_default_combs",
     "cprng_set_tuning", "cprng_get_tuning", "cprng_autotune", "cprng_autotune_ragged",
     "cprng_enable_timing", "cprng_last_kernel_ms", "cprng_probe_fill", "cprng_probe_copy",
-    "cprng_strerror", "cprng_last_error",
+    "cprng_strerror", "cprng_last_error", "cprng_now_ns", "cprng_server_create", "cprng_server_submit",
+    "cprng_server_poll", "cprng_server_release", "cprng_server_stats", "cprng_server_replay",
+    "cprng_server_destroy",
 ]
 
 _lib = None
@@ -88,6 +101,14 @@ def lib():
         "cprng_probe_copy": (i32, [vp, vp, u64, vp]),
         "cprng_strerror": (C.c_char_p, [i32]),
         "cprng_last_error": (C.c_char_p, []),
+        "cprng_now_ns": (u64, []),
+        "cprng_server_create": (i32, [vp, C.POINTER(ServerParams), vp]),
+        "cprng_server_submit": (i32, [vp, u32, u64, u64, u64]),
+        "cprng_server_poll": (i32, [vp, C.POINTER(Completion), u32, C.POINTER(u32)]),
+        "cprng_server_release": (i32, [vp, vp]),
+        "cprng_server_stats": (i32, [vp, C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)]),
+        "cprng_server_replay": (i32, [vp, vp, vp, vp, u32, i32, C.POINTER(Completion)]),
+        "cprng_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -244,3 +265,52 @@ def cprng_strerror(status: int) -> str:
 
 def cprng_last_error() -> str:
     return lib().cprng_last_error().decode()
+
+
+# ---------------------------------------------------------------------------
+# Serving loop.
+# ---------------------------------------------------------------------------
+def cprng_now_ns() -> int:
+    return int(lib().cprng_now_ns())
+
+
+def cprng_server_create(h: int, n_gpu_streams: int = 0, budget_bytes: int = 0, max_batch: int = 0) -> int:
+    p = ServerParams(C.sizeof(ServerParams), n_gpu_streams, budget_bytes, max_batch, 0)
+    s = C.c_void_p()
+    _check(lib().cprng_server_create(h, C.byref(p), C.byref(s)), "cprng_server_create")
+    return s.value
+
+
+def cprng_server_submit(s: int, client: int, length: int, tag: int, t_submit_ns: int = 0) -> None:
+    _check(lib().cprng_server_submit(s, client, length, tag, t_submit_ns), "cprng_server_submit")
+
+
+def cprng_server_poll(s: int, max_done: int = 256):
+    buf = (Completion * max_done)()
+    n = C.c_uint32(0)
+    _check(lib().cprng_server_poll(s, buf, max_done, C.byref(n)), "cprng_server_poll")
+    return [buf[i] for i in range(n.value)]
+
+
+def cprng_server_release(s: int, out: int) -> None:
+    _check(lib().cprng_server_release(s, out), "cprng_server_release")
+
+
+def cprng_server_stats(s: int):
+    w, f, b = C.c_uint64(0), C.c_uint64(0), C.c_uint64(0)
+    _check(lib().cprng_server_stats(s, C.byref(w), C.byref(f), C.byref(b)), "cprng_server_stats")
+    return {"waiting": w.value, "in_flight": f.value, "bytes_in_use": b.value}
+
+
+def cprng_server_replay(s: int, arrival_ns, client, length, release_results: bool):
+    """arrival_ns/length: uint64 numpy arrays, client: uint32 numpy array.
+    Returns a ctypes array of Completion, indexed by request."""
+    n = len(arrival_ns)
+    res = (Completion * max(1, n))()
+    _check(lib().cprng_server_replay(s, _addr(arrival_ns), _addr(client), _addr(length), n,
+                                     1 if release_results else 0, res), "cprng_server_replay")
+    return res
+
+
+def cprng_server_destroy(s: int) -> None:
+    lib().cprng_server_destroy(s)

@@ -22,10 +22,10 @@ LIB = os.path.join(PKG, "libcprng.so")
 ARCH = os.environ.get("CPRNG_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
-DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-ffp-contract=off",
-          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics"]
-HOST = ["-D__HIP_PLATFORM_AMD__=1"]
+NO_PACKED_FP32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-ffp-contract=off"] + NO_PACKED_FP32
+# Host sources include the HIP runtime headers; hipcc compiles them in HIP mode.
+HOST = ["-D__HIP_PLATFORM_AMD__=1", f"--offload-arch={ARCH}"] + NO_PACKED_FP32
 
 
 def _hipcc():

@@ -231,12 +231,7 @@ void cprng_destroy(cprng_t *h)
     if (h->d_state) (void)hipFree(h->d_state);
     if (h->d_state_next) (void)hipFree(h->d_state_next);
     if (h->d_counter) (void)hipFree(h->d_counter);
-    if (h->d_req_segs) (void)hipFree(h->d_req_segs);
-    if (h->d_req_polys) (void)hipFree(h->d_req_polys);
-    if (h->d_req_ids) (void)hipFree(h->d_req_ids);
-    for (auto &kv : h->d_req_poly_tables) (void)hipFree(kv.second);
-    if (h->h_stage) (void)hipHostFree(h->h_stage);
-    if (h->ev_stage) (void)hipEventDestroy(h->ev_stage);
+    destroy_req_slots(h);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;

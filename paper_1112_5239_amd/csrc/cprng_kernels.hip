@@ -440,6 +440,47 @@ __device__ __forceinline__ void jump_v0(X128 &g, uint32_t &x, const uint32_t *po
     x = a4;
 }
 
+// Segment idx -> its run, position, length, head and jump polynomial.
+struct Seg {
+    uint32_t *out;         // first output of the segment
+    uint32_t len, head, stream, last;
+    const uint32_t *poly;  // nullptr: no jump (segment 0)
+    uint64_t pos;          // start position within the run
+};
+
+__device__ __forceinline__ Seg decode_segment(const SegArgs &a, uint32_t idx)
+{
+    // Binary search for the run with first_seg <= idx < next run's first_seg.
+    uint32_t lo = 0, hi = a.nrun;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.runs[mid].first_seg <= idx) lo = mid;
+        else hi = mid;
+    }
+    const RunDesc r = a.runs[lo];
+    const uint32_t k = idx - r.first_seg;
+    Seg s;
+    s.stream = r.stream;
+    const uint64_t seg0 = (uint64_t)r.head + a.chunk;
+    uint64_t len;
+    if (k == 0) {
+        s.pos = 0;
+        len = r.len < seg0 ? r.len : seg0;
+        s.head = r.head;
+        s.poly = nullptr;
+    } else {
+        s.pos = seg0 + (uint64_t)(k - 1) * a.chunk;
+        const uint64_t left = r.len - s.pos;
+        len = left < a.chunk ? left : a.chunk;
+        s.head = 0;
+        s.poly = a.polys + 5ull * ((uint64_t)r.head * a.kcap + k);
+    }
+    s.len = (uint32_t)len;
+    s.out = reinterpret_cast<uint32_t *>(r.out) + s.pos;
+    s.last = (r.last && s.pos + len == r.len) ? 1u : 0u;
+    return s;
+}
+
 template <int K>
 __global__ __launch_bounds__(256) void k_segments(SegArgs a)
 {
@@ -452,14 +493,12 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a)
         if (base >= a.nseg) break;
         const uint32_t idx = base + lane;
         if (idx < a.nseg) {
-            const SegDesc d = a.segs[idx];
+            const Seg d = decode_segment(a, idx);
             const uint32_t *p = a.state + d.stream;
             X128 g{p[0], p[ns], p[2 * ns], p[3 * ns]};
             uint32_t x = p[4 * ns];
-            if (d.poly != 0)
-                jump_v0(g, x, d.poly < a.n_table ? a.polys + 5ull * d.poly
-                                                 : a.polys_extra + 5ull * (d.poly - a.n_table));
-            uint32_t *o = reinterpret_cast<uint32_t *>(d.out);
+            if (d.poly) jump_v0(g, x, d.poly);
+            uint32_t *o = d.out;
             const uint32_t len = d.len;
             uint32_t i = 0;
             const uint32_t head = d.head < len ? d.head : len;
@@ -495,6 +534,103 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a)
                 q[0] = g.x; q[ns] = g.y; q[2 * ns] = g.z; q[3 * ns] = g.w;
                 q[4 * ns] = x;
             }
+        }
+    }
+}
+
+// Tiled variant of k_segments: one wave per workgroup (each wave runs its
+// own number of rounds, so barriers must stay wave-local).  Each round every
+// lane writes its segment's next K outputs to its LDS row; the wave then
+// stores the 64 x K tile with whole-line 16-byte stores, using each row's
+// destination and count (a row's last partial quad is stored word by word).
+// Rows start 16-byte aligned after the segment's head (0..3 outputs stored
+// singly before the first round).
+template <int K, bool NT>
+__global__ __launch_bounds__(64) void k_segments_tile(SegArgs a)
+{
+    HIP_DYNAMIC_SHARED(uint32_t, lds);
+    constexpr int QPR = K / 4;
+    uint32_t *tile = lds;                    // 64 rows x K words, quad-swizzled
+    uint32_t *meta = lds + 64 * K;           // per row: address lo, hi, count
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t ns = a.ns;
+    for (;;) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(a.counter, 64u);
+        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+        if (base >= a.nseg) break;
+        const uint32_t idx = base + lane;
+        X128 g{0u, 0u, 0u, 0u};
+        uint32_t x = 0, rem = 0, stream = 0, last = 0;
+        uint32_t *o = nullptr;
+        if (idx < a.nseg) {
+            const Seg d = decode_segment(a, idx);
+            const uint32_t *p = a.state + d.stream;
+            g = X128{p[0], p[ns], p[2 * ns], p[3 * ns]};
+            x = p[4 * ns];
+            if (d.poly) jump_v0(g, x, d.poly);
+            o = d.out;
+            const uint32_t head = d.head < d.len ? d.head : d.len;
+            for (uint32_t i = 0; i < head; ++i) {
+                x ^= x128_next(g);
+                o[i] = x;
+            }
+            o += head;
+            rem = d.len - head;
+            stream = d.stream;
+            last = d.last;
+        }
+        while (__ballot(rem > 0u) != 0ull) {
+            const uint32_t cnt = rem < (uint32_t)K ? rem : (uint32_t)K;
+            uint32_t *row = tile + lane * K;
+            if (cnt == (uint32_t)K) {
+#pragma unroll
+                for (int q = 0; q < QPR; ++q) {
+                    uint32_t v0, v1, v2, v3;
+                    x ^= x128_next(g); v0 = x;
+                    x ^= x128_next(g); v1 = x;
+                    x ^= x128_next(g); v2 = x;
+                    x ^= x128_next(g); v3 = x;
+                    store4<false>(row + 4 * (q ^ (lane & (QPR - 1))), v0, v1, v2, v3);
+                }
+            } else {
+                for (uint32_t j = 0; j < cnt; ++j) {
+                    x ^= x128_next(g);
+                    row[4 * ((j >> 2) ^ (lane & (QPR - 1))) + (j & 3u)] = x;
+                }
+            }
+            const uint64_t oa = (uint64_t)(uintptr_t)o;
+            meta[lane * 4 + 0] = (uint32_t)oa;
+            meta[lane * 4 + 1] = (uint32_t)(oa >> 32);
+            meta[lane * 4 + 2] = cnt;
+            __syncthreads();
+#pragma unroll 8
+            for (int j = 0; j < QPR; ++j) {
+                const uint32_t Q = j * 64 + lane;
+                const uint32_t r = Q / QPR;
+                const uint32_t q = Q % QPR;
+                const uint32_t cr = meta[r * 4 + 2];
+                if (4 * q < cr) {
+                    uint32_t *dst = reinterpret_cast<uint32_t *>(
+                        (uintptr_t)(((uint64_t)meta[r * 4 + 1] << 32) | meta[r * 4 + 0])) + 4 * q;
+                    const uint32_t *src = tile + r * K + 4 * (q ^ (r & (QPR - 1)));
+                    if (4 * q + 4 <= cr) {
+                        uint32_t x0, x1, x2, x3;
+                        load4(src, x0, x1, x2, x3);
+                        store4<NT>(dst, x0, x1, x2, x3);
+                    } else {
+                        for (uint32_t e = 0; e < cr - 4 * q; ++e) dst[e] = src[e];
+                    }
+                }
+            }
+            __syncthreads();
+            o += cnt;
+            rem -= cnt;
+        }
+        if (last) {
+            uint32_t *q = a.state_next + stream;
+            q[0] = g.x; q[ns] = g.y; q[2 * ns] = g.z; q[3 * ns] = g.w;
+            q[4 * ns] = x;
         }
     }
 }
@@ -649,8 +785,26 @@ hipError_t launch_consume(const GenArgs &a, int variant, int w32, const LaunchCf
 
 hipError_t launch_segments(const SegArgs &a, uint32_t grid, uint32_t block, uint32_t store, hipStream_t st)
 {
-    (void)store;
-    if (block == 0 || block % 64 != 0 || block > 256 || grid == 0) return hipErrorInvalidValue;
+    if (grid == 0) return hipErrorInvalidValue;
+    if (store == ST_LDS || store == ST_LDS_NT) {
+        const bool nt = store == ST_LDS_NT;
+        const size_t lds = (size_t)64 * a.unroll * 4 + 64 * 16;
+#define SEG_TILE(K)                                                                              \
+    do {                                                                                         \
+        if (nt) hipLaunchKernelGGL((k_segments_tile<K, true>), dim3(grid), dim3(64), lds, st, a);  \
+        else hipLaunchKernelGGL((k_segments_tile<K, false>), dim3(grid), dim3(64), lds, st, a);    \
+    } while (0)
+        switch (a.unroll) {
+        case 32: SEG_TILE(32); break;
+        case 64: SEG_TILE(64); break;
+        case 128: SEG_TILE(128); break;
+        case 256: return hipErrorInvalidValue;          // 64 KiB tile + metadata exceeds 64 KiB
+        default: return hipErrorInvalidValue;
+        }
+#undef SEG_TILE
+        return hipGetLastError();
+    }
+    if (block == 0 || block % 64 != 0 || block > 256) return hipErrorInvalidValue;
     switch (a.unroll) {
     case 8: hipLaunchKernelGGL((k_segments<8>), dim3(grid), dim3(block), 0, st, a); break;
     case 16: hipLaunchKernelGGL((k_segments<16>), dim3(grid), dim3(block), 0, st, a); break;

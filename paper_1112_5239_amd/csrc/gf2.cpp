@@ -13,6 +13,8 @@
 // A' in block form [[A,0],[eA,I]] gives q(A') = 0 for q = p(X)(X+1), since
 // sum_k q_k A'^k has blocks q(A) = 0 and (A+I)^{-1}A(q(A) + q(1)I) = 0.  The
 // result is checked by simulation before use.
+#include <array>
+#include <map>
 #include <mutex>
 
 #include "host.h"
@@ -198,6 +200,34 @@ void jump_pack(const JPoly &p, uint32_t out[5])
     out[2] = (uint32_t)p.w[1];
     out[3] = (uint32_t)(p.w[1] >> 32);
     out[4] = (uint32_t)(p.w[2] & 1u);   // coefficient of X^128
+}
+
+}  // namespace cprng_impl
+
+namespace cprng_impl {
+
+namespace {
+std::mutex g_tab_mu;
+// Per chunk length: X^(h + k*chunk) mod q for h = 0..3, k = 0, 1, 2, ...
+std::map<uint32_t, std::array<std::vector<JPoly>, 4>> g_tables;
+}  // namespace
+
+void jump_table(uint32_t chunk, uint32_t kcap, std::vector<uint32_t> &out)
+{
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    auto &rows = g_tables[chunk];
+    if (rows[0].size() < kcap) {
+        const JPoly step = jump_xpow(chunk);
+        for (uint32_t h = 0; h < 4; ++h) {
+            std::vector<JPoly> &r = rows[h];
+            if (r.empty()) r.push_back(jump_xpow(h));
+            r.reserve(kcap);
+            while (r.size() < kcap) r.push_back(jump_mul(r.back(), step));
+        }
+    }
+    out.assign((size_t)4 * kcap * 5, 0u);
+    for (uint32_t h = 0; h < 4; ++h)
+        for (uint32_t k = 0; k < kcap; ++k) jump_pack(rows[h][k], &out[((size_t)h * kcap + k) * 5]);
 }
 
 }  // namespace cprng_impl

@@ -40,10 +40,28 @@ JPoly jump_xpow(uint64_t J);          // X^J mod q
 JPoly jump_one();
 // Pack into the kernel's 5 x 32-bit coefficient words (coefficients 0..128).
 void jump_pack(const JPoly &p, uint32_t out[5]);
+// Packed table of X^(h + k*chunk) mod q, h = 0..3, k = 0..kcap-1, at index
+// h*kcap + k (5 words each).  Cached per process and extended on demand.
+void jump_table(uint32_t chunk, uint32_t kcap, std::vector<uint32_t> &out);
+// Make sure request batches of runs up to max_len outputs find their jump
+// table on the device without rebuilding it (segments.cpp).
+int prepare_request_tables(cprng_t *h, uint64_t max_len);
 
 // ---- ragged / request plans (segments.cpp) --------------------------------
 struct RaggedPlan;
 void destroy_plans(cprng_t *h);
+
+// Work buffers of request batches on one HIP stream (batches on different
+// streams may overlap on the device, so each stream has its own).
+struct ReqSlot {
+    hipStream_t stream = nullptr;
+    uint32_t *d_counter = nullptr;      // work-queue counter
+    void *d_buf = nullptr;              // run descriptors and commit ids
+    void *h_stage = nullptr;            // pinned staging of d_buf
+    size_t buf_cap = 0;
+    hipEvent_t ev_stage = nullptr;      // the previous upload has completed
+};
+void destroy_req_slots(cprng_t *h);
 
 }  // namespace cprng_impl
 
@@ -71,17 +89,9 @@ struct cprng {
     // segment machinery (V0)
     uint32_t *d_counter = nullptr;
     std::vector<cprng_impl::RaggedPlan *> plans;
-    // requests: per-call buffers (grow-only)
-    cprng_impl::SegDesc *d_req_segs = nullptr;
-    size_t req_segs_cap = 0;
-    uint32_t *d_req_polys = nullptr;
-    size_t req_polys_cap = 0;
-    uint32_t *d_req_ids = nullptr;
-    size_t req_ids_cap = 0;
-    void *h_stage = nullptr;            // pinned staging for uploads
-    size_t h_stage_cap = 0;
-    hipEvent_t ev_stage = nullptr;
-    // cached X^(h + k*Lc) tables for requests: key Lc
-    std::unordered_map<uint32_t, std::vector<uint32_t>> req_poly_tables;
+    // requests: work buffers per HIP stream (grow-only)
+    std::vector<cprng_impl::ReqSlot *> req_slots;
+    // jump tables X^(h + k*chunk) for requests, per chunk length
+    std::unordered_map<uint32_t, uint32_t> req_poly_kcap;
     std::unordered_map<uint32_t, uint32_t *> d_req_poly_tables;
 };

@@ -46,26 +46,32 @@ hipError_t launch_generate(const GenArgs &a, int variant, int w32, const LaunchC
 hipError_t launch_consume(const GenArgs &a, int variant, int w32, const LaunchCfg &c,
                           hipStream_t st);
 
-// Chunk ("segment") of a stream for the batched uneven and request kernels.
-struct SegDesc {
-    uint64_t out;          // device address of the segment's first output
+// A run of consecutive outputs of one stream (a batched stream or a request)
+// for the chunked kernels.  The run is cut into chunks ("segments"):
+// segment 0 covers positions [0, min(len, head + chunk)), segment k >= 1
+// covers [head + k*chunk, min(len, head + (k+1)*chunk)); `head` (0..3) makes
+// every segment after the first start on a 16-byte boundary.  Segment k starts
+// from the stream's state jumped ahead by its start position, with the jump
+// polynomial X^(head + k*chunk) at table index head*kcap + k (k >= 1).
+struct RunDesc {
+    uint64_t out;          // device address of the run's first output
+    uint64_t len;          // outputs in the run (> 0)
     uint32_t stream;       // stream id
-    uint32_t len;          // outputs in this segment
-    uint32_t head;         // leading outputs stored one by one (0..3)
-    uint32_t poly;         // index of the jump polynomial (0 = no jump)
-    uint32_t last;         // 1: writes the stream's end state to state_next
-    uint32_t pad;
+    uint32_t head;         // 0..3
+    uint32_t first_seg;    // global index of the run's segment 0
+    uint32_t last;         // 1: the run ends the stream's work of this launch
 };
 
 struct SegArgs {
-    const SegDesc *segs;
-    uint32_t nseg;
+    const RunDesc *runs;   // sorted by first_seg
+    uint32_t nrun;
+    uint32_t nseg;         // total segments
+    uint32_t chunk;        // outputs per segment (multiple of 64)
+    uint32_t kcap;         // jump table: kcap entries per head value
+    const uint32_t *polys; // 4*kcap polynomials, 5 words each, bit k = coeff of X^k
     uint32_t ns;           // streams (SoA stride)
-    const uint32_t *polys; // 5 words per polynomial, bit k = coeff of x^k
-    const uint32_t *polys_extra; // polynomials with index >= n_table
-    uint32_t n_table;      // entries in polys
     const uint32_t *state; // current states (read only during the launch)
-    uint32_t *state_next;  // end states of streams whose last segment ran
+    uint32_t *state_next;  // end states of runs with `last`
     uint32_t *counter;     // work-queue counter (reset before each launch)
     uint32_t unroll;       // outputs per lane per round
 };

@@ -1,17 +1,20 @@
 // segments.cpp -- batched uneven streams and request batches (plain variant).
 //
-// A stream's run of L outputs is cut into chunks ("segments") so that long
-// runs use many lanes.  Segment k of a run starts at position P_k (P_0 = 0,
-// P_k = h + k*chunk, h = outputs needed to reach a 16-byte-aligned address),
-// from the state A'^{P_k} v obtained with a jump polynomial X^{P_k} mod q (see
-// gf2.cpp).  The lane that owns the run's final segment writes the end state
-// to state_next; a small commit kernel copies those states back after the
-// segment kernel, so no lane reads a state another lane of the same launch is
-// rewriting.
+// A run of L outputs of one stream is cut into chunks ("segments") so that
+// long runs use many lanes (see RunDesc in internal.h).  Segment k >= 1 of a
+// run starts at position h + k*chunk from the state A'^(h + k*chunk) v, whose
+// jump polynomial X^(h + k*chunk) mod q (gf2.cpp) comes from a table indexed
+// by (h, k); the kernel decodes its segment from the run descriptors, so the
+// host work per launch is proportional to the number of runs.  The lane that
+// owns a run's final segment writes the stream's end state to state_next; a
+// commit kernel copies those states back after the segment kernel, so no lane
+// reads a state that another lane of the same launch rewrites.
 //
-// Batched uneven streams run as one hipGraph (queue reset, persistent segment
-// kernel, commit) that is built once per (lengths, offsets, out, tuning) and
-// replayed.  Request batches are built per call and launched directly.
+// Batched uneven streams run as one hipGraph (queue-reset kernel, persistent
+// segment kernel, commit kernel) built once per (lengths, offsets, out,
+// tuning) and replayed.  Request batches are built per call; requests of one
+// stream are served in order by consecutive launches on the call's stream,
+// each launch holding at most one run per stream.
 #include <algorithm>
 #include <cstring>
 #include <memory>
@@ -26,13 +29,11 @@ namespace cprng_impl {
 struct RaggedPlan {
     std::vector<uint64_t> lengths, offsets;
     uint32_t *out = nullptr;
-    uint32_t chunk = 0, unroll = 0, waves = 0, block = 0;
-    SegDesc *d_segs = nullptr;
-    uint32_t nseg = 0;
+    uint32_t chunk = 0, unroll = 0, waves = 0, block = 0, store = 0;
+    RunDesc *d_runs = nullptr;
+    uint32_t nrun = 0, nseg = 0, kcap = 0;
     uint32_t *d_polys = nullptr;
-    uint32_t npolys = 0;
     uint32_t *d_ids = nullptr;
-    uint32_t nids = 0;
     uint32_t grid = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -48,69 +49,47 @@ void free_plan(RaggedPlan *p)
     if (!p) return;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    if (p->d_segs) (void)hipFree(p->d_segs);
+    if (p->d_runs) (void)hipFree(p->d_runs);
     if (p->d_polys) (void)hipFree(p->d_polys);
     if (p->d_ids) (void)hipFree(p->d_ids);
     delete p;
 }
 
-// Table of X^(h + k*chunk) mod q for h in 0..3, k in 0..kcap-1 (index
-// h*kcap + k); entry 0 is X^0 = 1, the "no jump" polynomial.
-void build_table(uint32_t chunk, uint32_t kcap, std::vector<uint32_t> &tab)
+uint32_t head_of(uint64_t addr) { return (uint32_t)((4u - (uint32_t)((addr / 4u) % 4u)) % 4u); }
+
+uint64_t segments_of(uint64_t len, uint32_t head, uint32_t chunk)
 {
-    tab.assign((size_t)4 * kcap * 5, 0u);
-    const JPoly step = jump_xpow(chunk);
-    for (uint32_t h = 0; h < 4; ++h) {
-        JPoly p = jump_xpow(h);
-        for (uint32_t k = 0; k < kcap; ++k) {
-            jump_pack(p, &tab[((size_t)h * kcap + k) * 5]);
-            p = jump_mul(p, step);
-        }
-    }
+    const uint64_t seg0 = (uint64_t)head + chunk;
+    return len <= seg0 ? 1 : 1 + (len - seg0 + chunk - 1) / chunk;
 }
 
-uint32_t head_of(uint64_t addr)
+uint32_t kcap_for(uint64_t max_segments)
 {
-    return (uint32_t)((4u - (uint32_t)((addr / 4u) % 4u)) % 4u);
+    uint32_t cap = 64;
+    while (cap < max_segments + 1) cap *= 2;
+    return cap;
 }
 
-// Cut one run into segments.  `skip` > 0 (not the first run of the stream in
-// this call) takes its jump polynomials from `extra`.
-struct Cutter {
-    uint32_t chunk = 0, kcap = 0;
-    std::vector<SegDesc> segs;
-    std::vector<uint32_t> extra;       // packed polynomials, index n_table + i
-    uint32_t n_table = 0;
-    bool need_bigger_table = false;
-
-    void run(uint32_t stream, uint64_t addr, uint64_t len, uint64_t skip)
+// Runs of one launch, with their segment numbering.
+struct RunList {
+    std::vector<RunDesc> runs;
+    uint64_t nseg = 0, max_seg = 0;
+    // Returns false if the launch would exceed 2^31 segments.
+    bool add(uint32_t stream, uint64_t addr, uint64_t len, uint32_t chunk, uint32_t last)
     {
-        const uint32_t h = head_of(addr);
-        uint64_t pos = 0;
-        uint32_t k = 0;
-        while (pos < len) {
-            const uint64_t cap = (k == 0) ? (uint64_t)h + chunk : chunk;
-            const uint64_t sl = std::min<uint64_t>(cap, len - pos);
-            SegDesc d;
-            std::memset(&d, 0, sizeof d);
-            d.out = addr + 4u * pos;
-            d.stream = stream;
-            d.len = (uint32_t)sl;
-            d.head = (k == 0) ? h : 0u;
-            const uint64_t dist = skip + pos;
-            if (skip == 0) {
-                if (k >= kcap) need_bigger_table = true;
-                d.poly = (k == 0) ? 0u : h * kcap + k;
-            } else {
-                uint32_t w[5];
-                jump_pack(jump_xpow(dist), w);
-                d.poly = n_table + (uint32_t)(extra.size() / 5);
-                extra.insert(extra.end(), w, w + 5);
-            }
-            segs.push_back(d);
-            pos += sl;
-            ++k;
-        }
+        RunDesc r;
+        std::memset(&r, 0, sizeof r);
+        r.out = addr;
+        r.len = len;
+        r.stream = stream;
+        r.head = head_of(addr);
+        r.first_seg = (uint32_t)nseg;
+        r.last = last;
+        const uint64_t k = segments_of(len, r.head, chunk);
+        nseg += k;
+        max_seg = std::max(max_seg, k);
+        runs.push_back(r);
+        return nseg < (1ull << 31);
     }
 };
 
@@ -129,40 +108,54 @@ int ensure_common(cprng_t *h)
     return CPRNG_OK;
 }
 
-uint32_t kcap_for(uint64_t max_len, uint32_t chunk)
-{
-    const uint64_t k = max_len / chunk + 2;
-    uint32_t cap = 64;
-    while (cap < k) cap *= 2;
-    return cap;
-}
-
 struct SegCfg {
-    uint32_t chunk, unroll, waves, block;
+    uint32_t chunk, unroll, waves, block, store;
 };
+
+// Tiled stores (one wave per workgroup) take K in {32, 64, 128}; per-lane
+// stores take K in {8, 16, 32} and any block size.
+void normalize(SegCfg &c)
+{
+    if (c.store == ST_LDS || c.store == ST_LDS_NT) {
+        c.block = 64;
+        if (c.unroll < 32) c.unroll = 32;
+        if (c.unroll > 128) c.unroll = 128;
+    } else {
+        c.store = ST_DIRECT;
+        if (c.unroll > 32) c.unroll = 32;
+        if (c.unroll < 8) c.unroll = 8;
+    }
+    if (c.waves == 0) c.waves = 4;
+}
 
 SegCfg resolve_seg_cfg(const cprng_t *h, uint64_t total, uint64_t max_len)
 {
-    SegCfg c{8192, 32, 8, 256};
+    // Default measured on MI355X for 4,096 streams of 1e3..1e7 outputs:
+    // per-lane stores, 2048-output chunks (a wave's 64 chunks then span
+    // 512 KiB of the output), one persistent wave per SIMD.
+    SegCfg c{2048, 16, 4, 256, ST_DIRECT};
     TuneEntry e;
     if (tune_cache_lookup_key(tune_key_ragged(h, total, max_len), &e)) {
         if (e.chunk) c.chunk = e.chunk;
         if (e.unroll) c.unroll = e.unroll;
         if (e.waves) c.waves = e.waves;
         if (e.block) c.block = e.block;
+        if (e.store) c.store = e.store;
     }
     if (h->tuning.chunk) c.chunk = h->tuning.chunk;
     if (h->tuning.waves_per_cu) c.waves = h->tuning.waves_per_cu;
     if (h->tuning.unroll) c.unroll = h->tuning.unroll;
     if (h->tuning.block) c.block = h->tuning.block;
+    if (h->tuning.store) c.store = h->tuning.store == ST_DIRECT_NT ? (uint32_t)ST_DIRECT : h->tuning.store;
+    normalize(c);
     return c;
 }
 
-uint32_t persistent_grid(const cprng_t *h, const SegCfg &c, uint32_t nseg)
+uint32_t persistent_grid(const cprng_t *h, const SegCfg &c, uint64_t nseg)
 {
     const uint32_t waves_per_block = c.block / 64;
     uint64_t grid = (uint64_t)h->n_cu * c.waves / waves_per_block;
-    const uint64_t needed = ((uint64_t)nseg + 63) / 64;          // one grab per wave
+    const uint64_t needed = (nseg + 63) / 64;          // one grab per wave
     const uint64_t needed_blocks = (needed + waves_per_block - 1) / waves_per_block;
     if (grid > needed_blocks) grid = needed_blocks;
     return (uint32_t)(grid ? grid : 1);
@@ -178,73 +171,75 @@ int upload(T **dptr, const std::vector<T> &v)
     return CPRNG_OK;
 }
 
+SegArgs seg_args(const cprng_t *h, const SegCfg &c, const RunDesc *runs, uint32_t nrun, uint64_t nseg,
+                 uint32_t kcap, const uint32_t *polys, uint32_t *counter)
+{
+    SegArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.runs = runs;
+    a.nrun = nrun;
+    a.nseg = (uint32_t)nseg;
+    a.chunk = c.chunk;
+    a.kcap = kcap;
+    a.polys = polys;
+    a.ns = h->ns;
+    a.state = h->d_state;
+    a.state_next = h->d_state_next;
+    a.counter = counter;
+    a.unroll = c.unroll;
+    return a;
+}
+
 int build_plan(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets,
                const SegCfg &c, RaggedPlan **res)
 {
     std::unique_ptr<RaggedPlan, void (*)(RaggedPlan *)> p(new RaggedPlan(), free_plan);
     p->lengths.assign(lengths, lengths + h->ns);
     p->offsets.resize(h->ns);
-    uint64_t acc = 0, max_len = 0;
+    uint64_t acc = 0;
     for (uint32_t s = 0; s < h->ns; ++s) {
         p->offsets[s] = offsets ? offsets[s] : acc;
         acc += lengths[s];
-        max_len = std::max(max_len, lengths[s]);
     }
     p->out = out;
     p->chunk = c.chunk;
     p->unroll = c.unroll;
     p->waves = c.waves;
     p->block = c.block;
+    p->store = c.store;
 
-    Cutter cut;
-    cut.chunk = c.chunk;
-    cut.kcap = kcap_for(max_len, c.chunk);
-    cut.n_table = 4 * cut.kcap;
+    // Longest runs first, so that the queue ends with short segments.
+    std::vector<uint32_t> order;
+    for (uint32_t s = 0; s < h->ns; ++s)
+        if (lengths[s]) order.push_back(s);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t b) { return lengths[a] > lengths[b]; });
+    RunList rl;
     std::vector<uint32_t> ids;
-    for (uint32_t s = 0; s < h->ns; ++s) {
-        const uint64_t L = p->lengths[s];
-        if (L == 0) continue;
-        const size_t first = cut.segs.size();
-        cut.run(s, (uint64_t)(uintptr_t)out + 4u * p->offsets[s], L, 0);
-        cut.segs.back().last = 1;
-        (void)first;
+    for (uint32_t s : order) {
+        if (!rl.add(s, (uint64_t)(uintptr_t)out + 4u * p->offsets[s], lengths[s], c.chunk, 1))
+            return set_error(CPRNG_E_INVAL, "too many segments (raise the chunk length)");
         ids.push_back(s);
     }
-    if (cut.need_bigger_table) return set_error(CPRNG_E_INVAL, "internal: jump table too small");
-    // Longest segments first so that short tails fill the end of the queue.
-    std::stable_sort(cut.segs.begin(), cut.segs.end(),
-                     [](const SegDesc &a, const SegDesc &b) { return a.len > b.len; });
+    p->nrun = (uint32_t)rl.runs.size();
+    p->nseg = (uint32_t)rl.nseg;
+    p->kcap = kcap_for(rl.max_seg);
     std::vector<uint32_t> tab;
-    build_table(c.chunk, cut.kcap, tab);
-    p->nseg = (uint32_t)cut.segs.size();
-    p->nids = (uint32_t)ids.size();
-    p->npolys = cut.n_table;
-    int rc = upload(&p->d_segs, cut.segs);
+    jump_table(c.chunk, p->kcap, tab);
+    int rc = upload(&p->d_runs, rl.runs);
     if (!rc) rc = upload(&p->d_polys, tab);
     if (!rc) rc = upload(&p->d_ids, ids);
     if (rc) return rc;
     p->grid = persistent_grid(h, c, p->nseg);
 
-    SegArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.segs = p->d_segs;
-    a.nseg = p->nseg;
-    a.ns = h->ns;
-    a.polys = p->d_polys;
-    a.polys_extra = nullptr;
-    a.n_table = p->npolys;
-    a.state = h->d_state;
-    a.state_next = h->d_state_next;
-    a.counter = h->d_counter;
-    a.unroll = c.unroll;
-
+    const SegArgs a = seg_args(h, c, p->d_runs, p->nrun, p->nseg, p->kcap, p->d_polys, h->d_counter);
     hipStream_t cs;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
         return set_error(CPRNG_E_HIP, "hipStreamCreate (capture)");
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) e = launch_zero_u32(h->d_counter, 1, cs);
-    if (e == hipSuccess && p->nseg) e = launch_segments(a, p->grid, c.block, 0, cs);
-    if (e == hipSuccess) e = launch_commit(h->d_state, h->d_state_next, p->d_ids, p->nids, h->ns, cs);
+    if (e == hipSuccess && p->nseg) e = launch_segments(a, p->grid, c.block, c.store, cs);
+    if (e == hipSuccess) e = launch_commit(h->d_state, h->d_state_next, p->d_ids, (uint32_t)ids.size(), h->ns, cs);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &graph);
     (void)hipStreamDestroy(cs);
@@ -265,7 +260,7 @@ RaggedPlan *find_plan(cprng_t *h, uint32_t *out, const uint64_t *lengths, const 
 {
     for (RaggedPlan *p : h->plans) {
         if (p->out != out || p->chunk != c.chunk || p->unroll != c.unroll || p->waves != c.waves ||
-            p->block != c.block)
+            p->block != c.block || p->store != c.store)
             continue;
         if (std::memcmp(p->lengths.data(), lengths, sizeof(uint64_t) * h->ns) != 0) continue;
         bool same = true;
@@ -314,6 +309,21 @@ void destroy_plans(cprng_t *h)
 {
     for (RaggedPlan *p : h->plans) free_plan(p);
     h->plans.clear();
+}
+
+void destroy_req_slots(cprng_t *h)
+{
+    for (ReqSlot *r : h->req_slots) {
+        if (r->d_counter) (void)hipFree(r->d_counter);
+        if (r->d_buf) (void)hipFree(r->d_buf);
+        if (r->h_stage) (void)hipHostFree(r->h_stage);
+        if (r->ev_stage) (void)hipEventDestroy(r->ev_stage);
+        delete r;
+    }
+    h->req_slots.clear();
+    for (auto &kv : h->d_req_poly_tables) (void)hipFree(kv.second);
+    h->d_req_poly_tables.clear();
+    h->req_poly_kcap.clear();
 }
 
 int ragged_with(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets,
@@ -387,17 +397,20 @@ extern "C" int cprng_autotune_ragged(cprng_t *h, uint32_t *out, const uint64_t *
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return set_error(CPRNG_E_HIP, "hipEventCreate");
-    const uint32_t chunks[] = {2048, 4096, 8192, 16384, 32768};
-    const uint32_t waves[] = {4, 8, 16};
-    const uint32_t unrolls[] = {16, 32};
+    const uint32_t chunks[] = {1024, 2048, 4096, 8192, 16384};
+    const uint32_t waves[] = {2, 4, 8};
+    // (store, unroll, block): per-lane stores and LDS tiles of several widths
+    const uint32_t modes[][3] = {{ST_DIRECT, 16, 256}, {ST_DIRECT, 32, 256}, {ST_DIRECT, 16, 64},
+                                 {ST_LDS, 64, 64}, {ST_LDS, 128, 64}, {ST_LDS_NT, 128, 64}};
     float best = 1e30f;
-    SegCfg best_c{8192, 32, 8, 256};
+    SegCfg best_c{2048, 16, 4, 256, ST_DIRECT};
     const bool saved_timing = h->timing;
     h->timing = false;
     for (uint32_t ch : chunks)
         for (uint32_t w : waves)
-            for (uint32_t u : unrolls) {
-                SegCfg c{ch, u, w, 256};
+            for (const auto &m : modes) {
+                SegCfg c{ch, m[1], w, m[2], m[0]};
+                normalize(c);
                 std::vector<float> t;
                 for (int r = 0; r < 4 && rc == CPRNG_OK; ++r) {
                     if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
@@ -429,6 +442,7 @@ extern "C" int cprng_autotune_ragged(cprng_t *h, uint32_t *out, const uint64_t *
     e.unroll = best_c.unroll;
     e.chunk = best_c.chunk;
     e.waves = best_c.waves;
+    e.store = best_c.store;
     tune_cache_store(tune_key_ragged(h, total, max_len), e);
     return CPRNG_OK;
 }
@@ -438,36 +452,21 @@ extern "C" int cprng_autotune_ragged(cprng_t *h, uint32_t *out, const uint64_t *
 // ---------------------------------------------------------------------------
 namespace {
 
-template <typename T>
-int ensure_dev(T **p, size_t *cap, size_t need)
+// Per-handle jump table for requests with chunk `chunk`, grown on demand.
+int request_table(cprng_t *h, uint32_t chunk, uint64_t max_seg, const uint32_t **dptr, uint32_t *kcap)
 {
-    if (need <= *cap) return CPRNG_OK;
-    size_t n = std::max<size_t>(need, *cap * 2);
-    if (*p) (void)hipFree(*p);
-    *p = nullptr;
-    *cap = 0;
-    if (hipMalloc(p, n * sizeof(T)) != hipSuccess) return set_error(CPRNG_E_NOMEM, "hipMalloc request buffer");
-    *cap = n;
-    return CPRNG_OK;
-}
-
-// Per-handle X^(h + k*chunk) table for requests, grown on demand.
-int request_table(cprng_t *h, uint32_t chunk, uint32_t kcap_needed, const uint32_t **dptr, uint32_t *kcap)
-{
-    auto it = h->req_poly_tables.find(chunk);
-    uint32_t have = (it == h->req_poly_tables.end()) ? 0u : (uint32_t)(it->second.size() / 20);
-    if (have >= kcap_needed) {
+    const uint32_t need = kcap_for(max_seg);
+    auto it = h->req_poly_kcap.find(chunk);
+    if (it != h->req_poly_kcap.end() && it->second >= need) {
         *dptr = h->d_req_poly_tables[chunk];
-        *kcap = have;
+        *kcap = it->second;
         return CPRNG_OK;
     }
-    uint32_t cap = 64;
-    while (cap < kcap_needed) cap *= 2;
     std::vector<uint32_t> tab;
-    build_table(chunk, cap, tab);
-    uint32_t *d = nullptr;
+    jump_table(chunk, need, tab);
     // The old table may still be read by queued work; wait before freeing it.
     if (hipDeviceSynchronize() != hipSuccess) return set_error(CPRNG_E_HIP, "hipDeviceSynchronize");
+    uint32_t *d = nullptr;
     if (hipMalloc(&d, tab.size() * sizeof(uint32_t)) != hipSuccess) return set_error(CPRNG_E_NOMEM, "hipMalloc table");
     if (hipMemcpy(d, tab.data(), tab.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(d);
@@ -476,10 +475,41 @@ int request_table(cprng_t *h, uint32_t chunk, uint32_t kcap_needed, const uint32
     auto dit = h->d_req_poly_tables.find(chunk);
     if (dit != h->d_req_poly_tables.end()) (void)hipFree(dit->second);
     h->d_req_poly_tables[chunk] = d;
-    h->req_poly_tables[chunk] = std::move(tab);
+    h->req_poly_kcap[chunk] = need;
     *dptr = d;
-    *kcap = cap;
+    *kcap = need;
     return CPRNG_OK;
+}
+
+// Chunk length of a request batch: the tuned chunk, halved (down to 1024)
+// while the batch would not give every SIMD two lanes of work.
+uint32_t request_chunk(const cprng_t *h, uint32_t chunk, uint64_t total)
+{
+    if (h->tuning.chunk) return chunk;
+    const uint64_t lanes_wanted = (uint64_t)h->n_cu * 4 * 64 * 2;
+    while (chunk > 1024 && total / chunk < lanes_wanted) chunk /= 2;
+    return chunk;
+}
+
+ReqSlot *find_slot(cprng_t *h, hipStream_t st, int *rc)
+{
+    for (ReqSlot *r : h->req_slots)
+        if (r->stream == st) return r;
+    if (h->req_slots.size() >= 16) {
+        *rc = set_error(CPRNG_E_UNSUPPORTED, "request batches on more than 16 distinct HIP streams");
+        return nullptr;
+    }
+    ReqSlot *r = new ReqSlot();
+    r->stream = st;
+    if (hipMalloc(&r->d_counter, 64) != hipSuccess ||
+        hipEventCreateWithFlags(&r->ev_stage, hipEventDisableTiming) != hipSuccess) {
+        if (r->d_counter) (void)hipFree(r->d_counter);
+        delete r;
+        *rc = set_error(CPRNG_E_NOMEM, "request slot allocation");
+        return nullptr;
+    }
+    h->req_slots.push_back(r);
+    return r;
 }
 
 }  // namespace
@@ -500,97 +530,86 @@ extern "C" int cprng_generate_requests(cprng_t *h, const cprng_request_t *reqs, 
         total += reqs[r].length;
         max_len = std::max(max_len, reqs[r].length);
     }
+    if (total == 0) return CPRNG_OK;
     DevGuard g(h->device);
     int rc = ensure_common(h);
     if (rc) return rc;
     SegCfg c = resolve_seg_cfg(h, total, max_len);
-    // Keep enough segments to fill the GPU when the batch is small.
-    if (!h->tuning.chunk) {
-        const uint64_t lanes_wanted = (uint64_t)h->n_cu * 4 * 64 * 2;
-        while (c.chunk > 1024 && total / c.chunk < lanes_wanted) c.chunk /= 2;
-    }
-    const uint32_t *d_tab = nullptr;
-    uint32_t kcap = 0;
-    rc = request_table(h, c.chunk, kcap_for(max_len, c.chunk), &d_tab, &kcap);
-    if (rc) return rc;
+    c.chunk = request_chunk(h, c.chunk, total);
 
-    Cutter cut;
-    cut.chunk = c.chunk;
-    cut.kcap = kcap;
-    cut.n_table = 4 * kcap;
-    std::unordered_map<uint32_t, uint64_t> done;   // outputs already assigned per stream
-    std::unordered_map<uint32_t, size_t> last_seg; // index of the stream's last segment
+    // Launch j serves the j-th non-empty request of every stream.
+    std::unordered_map<uint32_t, uint32_t> seen;
+    std::vector<RunList> launches;
+    std::vector<std::vector<uint32_t>> ids;
+    uint64_t max_seg = 0;
     for (uint32_t r = 0; r < count; ++r) {
         const cprng_request_t &q = reqs[r];
         if (q.length == 0) continue;
-        uint64_t &skip = done[q.stream];
-        cut.run(q.stream, (uint64_t)(uintptr_t)q.out, q.length, skip);
-        skip += q.length;
-        last_seg[q.stream] = cut.segs.size() - 1;
+        const uint32_t j = seen[q.stream]++;
+        if (j >= launches.size()) {
+            launches.emplace_back();
+            ids.emplace_back();
+        }
+        if (!launches[j].add(q.stream, (uint64_t)(uintptr_t)q.out, q.length, c.chunk, 1))
+            return set_error(CPRNG_E_INVAL, "too many segments in one launch");
+        ids[j].push_back(q.stream);
+        max_seg = std::max(max_seg, launches[j].max_seg);
     }
-    if (cut.need_bigger_table) return set_error(CPRNG_E_INVAL, "internal: jump table too small");
-    std::vector<uint32_t> ids;
-    ids.reserve(last_seg.size());
-    for (auto &kv : last_seg) {
-        cut.segs[kv.second].last = 1;
-        ids.push_back(kv.first);
-    }
-    if (cut.segs.empty()) return CPRNG_OK;
-    std::vector<size_t> order(cut.segs.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t a, size_t b) { return cut.segs[a].len > cut.segs[b].len; });
-    std::vector<SegDesc> sorted(cut.segs.size());
-    for (size_t i = 0; i < order.size(); ++i) sorted[i] = cut.segs[order[i]];
+    const uint32_t *d_tab = nullptr;
+    uint32_t kcap = 0;
+    rc = request_table(h, c.chunk, max_seg, &d_tab, &kcap);
+    if (rc) return rc;
 
     hipStream_t st = (hipStream_t)stream;
-    rc = ensure_dev(&h->d_req_segs, &h->req_segs_cap, sorted.size());
-    if (!rc) rc = ensure_dev(&h->d_req_polys, &h->req_polys_cap, std::max<size_t>(cut.extra.size(), 5));
-    if (!rc) rc = ensure_dev(&h->d_req_ids, &h->req_ids_cap, ids.size());
-    if (rc) return rc;
-    // Stage through pinned memory; wait until the previous call's upload has
-    // left the staging buffer before overwriting it.
-    const size_t bytes = sorted.size() * sizeof(SegDesc) + cut.extra.size() * 4 + ids.size() * 4 + 64;
-    if (!h->ev_stage && hipEventCreateWithFlags(&h->ev_stage, hipEventDisableTiming) != hipSuccess)
-        return set_error(CPRNG_E_HIP, "hipEventCreate");
-    if (hipEventSynchronize(h->ev_stage) != hipSuccess) return set_error(CPRNG_E_HIP, "hipEventSynchronize");
-    if (bytes > h->h_stage_cap) {
-        if (h->h_stage) (void)hipHostFree(h->h_stage);
-        h->h_stage = nullptr;
-        h->h_stage_cap = 0;
-        if (hipHostMalloc(&h->h_stage, bytes * 2, hipHostMallocDefault) != hipSuccess)
-            return set_error(CPRNG_E_NOMEM, "hipHostMalloc staging");
-        h->h_stage_cap = bytes * 2;
+    ReqSlot *slot = find_slot(h, st, &rc);
+    if (!slot) return rc;
+    // Stage every launch's runs and ids in one pinned buffer and copy it with
+    // one transfer.  The previous call on this stream may still be running:
+    // wait until its transfer has left the staging buffer; on the device the
+    // buffer is reused in stream order.
+    size_t bytes = 0;
+    std::vector<size_t> run_off(launches.size()), id_off(launches.size());
+    for (size_t j = 0; j < launches.size(); ++j) {
+        run_off[j] = bytes;
+        bytes += launches[j].runs.size() * sizeof(RunDesc);
     }
-    char *hs = (char *)h->h_stage;
-    const size_t o_segs = 0, o_polys = sorted.size() * sizeof(SegDesc),
-                 o_ids = o_polys + cut.extra.size() * 4;
-    std::memcpy(hs + o_segs, sorted.data(), sorted.size() * sizeof(SegDesc));
-    if (!cut.extra.empty()) std::memcpy(hs + o_polys, cut.extra.data(), cut.extra.size() * 4);
-    std::memcpy(hs + o_ids, ids.data(), ids.size() * 4);
-    hipError_t e = hipMemcpyAsync(h->d_req_segs, hs + o_segs, sorted.size() * sizeof(SegDesc), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && !cut.extra.empty())
-        e = hipMemcpyAsync(h->d_req_polys, hs + o_polys, cut.extra.size() * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(h->d_req_ids, hs + o_ids, ids.size() * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipEventRecord(h->ev_stage, st);
+    for (size_t j = 0; j < launches.size(); ++j) {
+        id_off[j] = bytes;
+        bytes += ids[j].size() * sizeof(uint32_t);
+    }
+    if (hipEventSynchronize(slot->ev_stage) != hipSuccess) return set_error(CPRNG_E_HIP, "hipEventSynchronize");
+    if (bytes > slot->buf_cap) {
+        if (slot->d_buf) (void)hipFree(slot->d_buf);       // hipFree waits for the device
+        if (slot->h_stage) (void)hipHostFree(slot->h_stage);
+        slot->d_buf = nullptr;
+        slot->h_stage = nullptr;
+        slot->buf_cap = 0;
+        const size_t cap = std::max<size_t>(bytes * 2, 1 << 16);
+        if (hipMalloc(&slot->d_buf, cap) != hipSuccess) return set_error(CPRNG_E_NOMEM, "hipMalloc request buffer");
+        if (hipHostMalloc(&slot->h_stage, cap, hipHostMallocDefault) != hipSuccess)
+            return set_error(CPRNG_E_NOMEM, "hipHostMalloc staging");
+        slot->buf_cap = cap;
+    }
+    char *hs = (char *)slot->h_stage;
+    for (size_t j = 0; j < launches.size(); ++j) {
+        std::memcpy(hs + run_off[j], launches[j].runs.data(), launches[j].runs.size() * sizeof(RunDesc));
+        std::memcpy(hs + id_off[j], ids[j].data(), ids[j].size() * sizeof(uint32_t));
+    }
+    hipError_t e = hipMemcpyAsync(slot->d_buf, hs, bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(slot->ev_stage, st);
     if (e != hipSuccess) return hip_error(e, "request upload");
 
-    SegArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.segs = h->d_req_segs;
-    a.nseg = (uint32_t)sorted.size();
-    a.ns = h->ns;
-    a.polys = d_tab;
-    a.polys_extra = h->d_req_polys;
-    a.n_table = cut.n_table;
-    a.state = h->d_state;
-    a.state_next = h->d_state_next;
-    a.counter = h->d_counter;
-    a.unroll = c.unroll;
+    char *db = (char *)slot->d_buf;
     if (h->timing && hipEventRecord(h->ev0, st) != hipSuccess) return set_error(CPRNG_E_HIP, "hipEventRecord");
-    e = launch_zero_u32(h->d_counter, 1, st);
-    if (e == hipSuccess) e = launch_segments(a, persistent_grid(h, c, a.nseg), c.block, 0, st);
-    if (e == hipSuccess) e = launch_commit(h->d_state, h->d_state_next, h->d_req_ids, (uint32_t)ids.size(), h->ns, st);
+    for (size_t j = 0; j < launches.size() && e == hipSuccess; ++j) {
+        const SegArgs a = seg_args(h, c, (const RunDesc *)(db + run_off[j]), (uint32_t)launches[j].runs.size(),
+                                   launches[j].nseg, kcap, d_tab, slot->d_counter);
+        e = launch_zero_u32(slot->d_counter, 1, st);
+        if (e == hipSuccess) e = launch_segments(a, persistent_grid(h, c, a.nseg), c.block, c.store, st);
+        if (e == hipSuccess)
+            e = launch_commit(h->d_state, h->d_state_next, (const uint32_t *)(db + id_off[j]),
+                              (uint32_t)ids[j].size(), h->ns, st);
+    }
     if (e != hipSuccess) return hip_error(e, "request kernels");
     if (h->timing) {
         if (hipEventRecord(h->ev1, st) != hipSuccess) return set_error(CPRNG_E_HIP, "hipEventRecord");
@@ -598,3 +617,21 @@ extern "C" int cprng_generate_requests(cprng_t *h, const cprng_request_t *reqs, 
     }
     return CPRNG_OK;
 }
+
+namespace cprng_impl {
+
+int prepare_request_tables(cprng_t *h, uint64_t max_len)
+{
+    int rc = ensure_common(h);
+    if (rc) return rc;
+    const SegCfg c = resolve_seg_cfg(h, max_len, max_len);
+    // Every chunk length request_chunk() can pick for a run of max_len.
+    for (uint32_t chunk = c.chunk;; chunk /= 2) {
+        const uint32_t *d = nullptr;
+        uint32_t kcap = 0;
+        rc = request_table(h, chunk, segments_of(max_len, 3, chunk), &d, &kcap);
+        if (rc || chunk <= 1024 || h->tuning.chunk) return rc;
+    }
+}
+
+}  // namespace cprng_impl

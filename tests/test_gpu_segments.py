@@ -70,14 +70,18 @@ def test_ragged_small_default_offsets(orc, G, torch):
 
 
 @pytest.mark.parametrize("chunk", [64, 256, 1024])
-def test_ragged_many_chunks_jump_ahead(orc, G, torch, chunk):
-    # Small chunks force many jumped segment starts per stream.
+@pytest.mark.parametrize("store,unroll", [(1, 16), (2, 32), (4, 64), (2, 128)])
+def test_ragged_many_chunks_jump_ahead(orc, G, torch, chunk, store, unroll):
+    # Small chunks force many jumped segment starts per stream; per-lane and
+    # LDS-tiled stores, tiles longer and shorter than the chunks.
     rng = np.random.default_rng(chunk)
     lengths = rng.integers(1, 20000, 70)
-    _check_ragged(orc, G, torch, lengths, tuning=dict(chunk=chunk, unroll=16, waves_per_cu=2))
+    _check_ragged(orc, G, torch, lengths,
+                  tuning=dict(chunk=chunk, unroll=unroll, waves_per_cu=2, store=store))
 
 
-def test_ragged_explicit_misaligned_offsets_with_gaps(orc, G, torch):
+@pytest.mark.parametrize("store", [1, 4])
+def test_ragged_explicit_misaligned_offsets_with_gaps(orc, G, torch, store):
     rng = np.random.default_rng(3)
     lengths = rng.integers(0, 3000, 50)
     lengths[[3, 17]] = 0
@@ -87,7 +91,7 @@ def test_ragged_explicit_misaligned_offsets_with_gaps(orc, G, torch):
     for s in order:
         offs[s] = pos
         pos += int(lengths[s]) + int(rng.integers(0, 7))
-    _check_ragged(orc, G, torch, lengths, offsets=offs, tuning=dict(chunk=512), pad=5)
+    _check_ragged(orc, G, torch, lengths, offsets=offs, tuning=dict(chunk=512, store=store), pad=5)
 
 
 def test_ragged_graph_replay_continues_streams(orc, G, torch):
