@@ -200,7 +200,9 @@ typedef struct cprng_tuning {
     uint32_t waves_per_cu;     /* ragged/requests: persistent waves per CU;
                                   LDS-transposed generate: residency cap (0 = none) */
     uint32_t streams_per_lane; /* LDS-transposed generate: 1, 2 or 4 streams per lane */
-    uint32_t reserved[2];
+    uint32_t exchange;         /* V2, LDS-transposed generate: 1 cross-lane reads,
+                                  2 LDS word buffer, 3 two steps per read round */
+    uint32_t reserved;
 } cprng_tuning_t;
 
 int cprng_set_tuning(cprng_t *h, const cprng_tuning_t *t);
@@ -314,6 +316,11 @@ int cprng_probe_fill(uint32_t *dst, uint64_t n_words, uint32_t value, cprng_stre
 /* Copy n_words uint32 from src to dst (device, 16-byte aligned): the copy
  * kernel used to calibrate hardware byte counters. */
 int cprng_probe_copy(uint32_t *dst, const uint32_t *src, uint64_t n_words, cprng_stream_t stream);
+
+/* 32-bit integer VALU issue-rate probe: n_threads lanes (a multiple of 256)
+ * each run `iters` iterations of 32 independent xor/shift instructions and
+ * write one word to out (device, n_threads uint32). */
+int cprng_probe_valu(uint32_t *out, uint32_t n_threads, uint32_t iters, cprng_stream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Errors.                                                                   */

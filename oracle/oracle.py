@@ -17,42 +17,71 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 V0, V1, V2 = 0, 1, 2
 
 _lib = None
+_override = None
+
+
+class use_library:
+    """Context manager: route every call of this module to another build of
+    the oracle (used by the mutation tests, which compile planted mistakes)."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _override
+        self.prev = _override
+        _override = _bind(C.CDLL(self.path))
+        return self
+
+    def __exit__(self, *exc):
+        global _override
+        _override = self.prev
 
 
 def lib():
+    if _override is not None:
+        return _override
+    return _default_lib()
+
+
+def _default_lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             from . import build as _b  # type: ignore
             _b.build()
-        L = C.CDLL(LIB_PATH)
-        u64, u32, i32, p = C.c_uint64, C.c_uint32, C.c_int, C.c_void_p
-        L.orc_sm64_mix.restype = u64
-        L.orc_sm64_mix.argtypes = [u64]
-        L.orc_sm64_draws.restype = None
-        L.orc_sm64_draws.argtypes = [u64, u64, p]
-        L.orc_gen_outputs.restype = i32
-        L.orc_gen_outputs.argtypes = [i32, i32, p, u64, p]
-        L.orc_xs32_orbit.restype = u64
-        L.orc_xs32_orbit.argtypes = [u32, u64, C.POINTER(i32)]
-        L.orc_ci_step.restype = u32
-        L.orc_ci_step.argtypes = [u32, u32]
-        L.orc_ci_step_batch.restype = None
-        L.orc_ci_step_batch.argtypes = [p, p, p, u64]
-        L.orc_state_words.restype = i32
-        L.orc_state_words.argtypes = [i32]
-        L.orc_seed.restype = i32
-        L.orc_seed.argtypes = [i32, i32, u64, u64, u64, p]
-        L.orc_comb_tables.restype = i32
-        L.orc_comb_tables.argtypes = [u32, p, p]
-        L.orc_generate.restype = i32
-        L.orc_generate.argtypes = [i32, i32, u64, p, u64, p, p, u32, p, p]
-        L.orc_consume_qc.restype = i32
-        L.orc_consume_qc.argtypes = [i32, i32, u64, p, u64, p, u32, p, p]
-        L.orc_qc_hit.restype = i32
-        L.orc_qc_hit.argtypes = [u32, u32]
-        _lib = L
+        _lib = _bind(C.CDLL(LIB_PATH))
     return _lib
+
+
+def _bind(L):
+    """Declare the C signatures on a loaded oracle library."""
+    u64, u32, i32, p = C.c_uint64, C.c_uint32, C.c_int, C.c_void_p
+    L.orc_sm64_mix.restype = u64
+    L.orc_sm64_mix.argtypes = [u64]
+    L.orc_sm64_draws.restype = None
+    L.orc_sm64_draws.argtypes = [u64, u64, p]
+    L.orc_gen_outputs.restype = i32
+    L.orc_gen_outputs.argtypes = [i32, i32, p, u64, p]
+    L.orc_xs32_orbit.restype = u64
+    L.orc_xs32_orbit.argtypes = [u32, u64, C.POINTER(i32)]
+    L.orc_ci_step.restype = u32
+    L.orc_ci_step.argtypes = [u32, u32]
+    L.orc_ci_step_batch.restype = None
+    L.orc_ci_step_batch.argtypes = [p, p, p, u64]
+    L.orc_state_words.restype = i32
+    L.orc_state_words.argtypes = [i32]
+    L.orc_seed.restype = i32
+    L.orc_seed.argtypes = [i32, i32, u64, u64, u64, p]
+    L.orc_comb_tables.restype = i32
+    L.orc_comb_tables.argtypes = [u32, p, p]
+    L.orc_generate.restype = i32
+    L.orc_generate.argtypes = [i32, i32, u64, p, u64, p, p, u32, p, p]
+    L.orc_consume_qc.restype = i32
+    L.orc_consume_qc.argtypes = [i32, i32, u64, p, u64, p, u32, p, p]
+    L.orc_qc_hit.restype = i32
+    L.orc_qc_hit.argtypes = [u32, u32]
+    return L
 
 
 def _ptr(a):

@@ -50,7 +50,7 @@ class Completion(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("block", C.c_uint32), ("unroll", C.c_uint32), ("store", C.c_uint32),
                 ("chunk", C.c_uint32), ("waves_per_cu", C.c_uint32), ("streams_per_lane", C.c_uint32),
-                ("reserved", C.c_uint32 * 2)]
+                ("exchange", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 EXPORTED = [
@@ -58,7 +58,7 @@ EXPORTED = [
     "cprng_generate_ragged", "cprng_generate_requests", "cprng_state_words", "cprng_get_state",
     "cprng_set_state", "cprng_n_streams", "cprng_variant", "cprng_default_combs",
     "cprng_set_tuning", "cprng_get_tuning", "cprng_autotune", "cprng_autotune_ragged",
-    "cprng_enable_timing", "cprng_last_kernel_ms", "cprng_probe_fill", "cprng_probe_copy",
+    "cprng_enable_timing", "cprng_last_kernel_ms", "cprng_probe_fill", "cprng_probe_copy", "cprng_probe_valu",
     "cprng_strerror", "cprng_last_error", "cprng_now_ns", "cprng_server_create", "cprng_server_submit",
     "cprng_server_poll", "cprng_server_release", "cprng_server_stats", "cprng_server_replay",
     "cprng_server_destroy",
@@ -99,6 +99,7 @@ def lib():
         "cprng_last_kernel_ms": (C.c_double, [vp]),
         "cprng_probe_fill": (i32, [vp, u64, u32, vp]),
         "cprng_probe_copy": (i32, [vp, vp, u64, vp]),
+        "cprng_probe_valu": (i32, [vp, u32, u32, vp]),
         "cprng_strerror": (C.c_char_p, [i32]),
         "cprng_last_error": (C.c_char_p, []),
         "cprng_now_ns": (u64, []),
@@ -222,8 +223,8 @@ def cprng_default_combs(Cg: int):
 
 
 def cprng_set_tuning(h: int, block=0, unroll=0, store=0, chunk=0, waves_per_cu=0,
-                     streams_per_lane=0) -> None:
-    t = Tuning(block, unroll, store, chunk, waves_per_cu, streams_per_lane)
+                     streams_per_lane=0, exchange=0) -> None:
+    t = Tuning(block, unroll, store, chunk, waves_per_cu, streams_per_lane, exchange)
     _check(lib().cprng_set_tuning(h, C.byref(t)), "cprng_set_tuning")
 
 
@@ -231,7 +232,8 @@ def cprng_get_tuning(h: int) -> dict:
     t = Tuning()
     _check(lib().cprng_get_tuning(h, C.byref(t)), "cprng_get_tuning")
     return {"block": t.block, "unroll": t.unroll, "store": t.store, "chunk": t.chunk,
-            "waves_per_cu": t.waves_per_cu, "streams_per_lane": t.streams_per_lane}
+            "waves_per_cu": t.waves_per_cu, "streams_per_lane": t.streams_per_lane,
+            "exchange": t.exchange}
 
 
 def cprng_autotune(h: int, scratch, n_per_stream: int, stream=None) -> None:
@@ -257,6 +259,10 @@ def cprng_probe_fill(dst, n_words: int, value: int, stream=None) -> None:
 
 def cprng_probe_copy(dst, src, n_words: int, stream=None) -> None:
     _check(lib().cprng_probe_copy(_addr(dst), _addr(src), n_words, _addr(stream)), "cprng_probe_copy")
+
+
+def cprng_probe_valu(out, n_threads: int, iters: int, stream=None) -> None:
+    _check(lib().cprng_probe_valu(_addr(out), n_threads, iters, _addr(stream)), "cprng_probe_valu")
 
 
 def cprng_strerror(status: int) -> str:

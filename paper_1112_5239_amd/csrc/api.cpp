@@ -162,8 +162,10 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
         c.unroll = e.unroll;
         c.store = e.store;
         c.slots = e.slots ? e.slots : 1;
+        if (e.exchange) c.exchange = e.exchange;
     }
     if (h->tuning.streams_per_lane) c.slots = h->tuning.streams_per_lane;
+    if (h->tuning.exchange) c.exchange = h->tuning.exchange;
     if (h->tuning.block) c.block = h->tuning.block;
     if (h->tuning.unroll) c.unroll = h->tuning.unroll;
     if (h->tuning.store && !consume) c.store = h->tuning.store;
@@ -193,8 +195,12 @@ int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchC
         // words must fit 64 KiB (K <= 256 always fits with block 64).
         if (c.unroll < 16) c.unroll = 16;
         if (c.slots != 1 && c.slots != 2 && c.slots != 4) c.slots = 1;
-        while (c.block > 64 && (uint64_t)c.block * c.slots * c.unroll * 4u > 65536u) c.block -= 64;
-        while (c.slots > 1 && (uint64_t)c.block * c.slots * c.unroll * 4u > 65536u) c.slots /= 2;
+        if (c.exchange < XCH_BPERM || c.exchange > XCH_BPERM2) c.exchange = XCH_BPERM;
+        // tile (+ the exchange buffer) per block must fit 64 KiB
+        const uint32_t extra = (h->variant == CPRNG_V2_SHMEM && c.exchange == XCH_LDS) ? 1u : 0u;
+        while (c.block > 64 && (uint64_t)c.block * c.slots * (c.unroll + extra) * 4u > 65536u) c.block -= 64;
+        while (c.slots > 1 && (uint64_t)c.block * c.slots * (c.unroll + extra) * 4u > 65536u) c.slots /= 2;
+        if ((uint64_t)c.block * c.slots * (c.unroll + extra) * 4u > 65536u) c.unroll /= 2;
     }
     int rc = begin_timing(h, st);
     if (rc) return rc;
@@ -342,6 +348,7 @@ int cprng_set_tuning(cprng_t *h, const cprng_tuning_t *t)
     if (t->waves_per_cu > 32) return set_error(CPRNG_E_INVAL, "waves_per_cu must be <= 32");
     if (t->streams_per_lane && t->streams_per_lane != 1 && t->streams_per_lane != 2 && t->streams_per_lane != 4)
         return set_error(CPRNG_E_INVAL, "streams_per_lane must be 1, 2 or 4");
+    if (t->exchange > 3) return set_error(CPRNG_E_INVAL, "exchange must be 0..3");
     h->tuning = *t;
     return CPRNG_OK;
 }
@@ -383,6 +390,13 @@ int cprng_probe_copy(uint32_t *dst, const uint32_t *src, uint64_t n_words, cprng
     if (!dst || !src || (uintptr_t)dst % 16u || (uintptr_t)src % 16u)
         return set_error(CPRNG_E_INVAL, "dst and src must be 16-byte aligned");
     HIP_TRY(launch_copy(dst, src, n_words, (hipStream_t)stream), "copy kernel launch");
+    return CPRNG_OK;
+}
+
+int cprng_probe_valu(uint32_t *out, uint32_t n_threads, uint32_t iters, cprng_stream_t stream)
+{
+    if (!out || n_threads == 0 || n_threads % 256) return set_error(CPRNG_E_INVAL, "n_threads must be a positive multiple of 256");
+    HIP_TRY(launch_valu_probe(out, n_threads, iters, (hipStream_t)stream), "VALU probe launch");
     return CPRNG_OK;
 }
 

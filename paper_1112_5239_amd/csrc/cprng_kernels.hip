@@ -110,13 +110,19 @@ struct Stream<0, T> {                       // V0 PLAIN
         x ^= x128_next(g);
         return x;
     }
+    __device__ __forceinline__ void next2(uint32_t &r0, uint32_t &r1)
+    {
+        r0 = next();
+        r1 = next();
+    }
 };
 
 template <typename T>
 struct Stream<2, T> {                       // V2 SHMEM (Algorithm 4)
     X128 g;
     uint32_t x, t;                          // t: this stream's previous mixed word
-    int addr1, addr2;                       // byte addresses of the two source lanes
+    int a1, a2;                             // byte addresses of lanes o1(j), o2(j)
+    int a11, a21, a12, a22;                 // lanes o1(o1(j)), o2(o1(j)), o1(o2(j)), o2(o2(j))
     __device__ void load(const GenArgs &a, uint32_t s)
     {
         const uint32_t *p = a.state + s;
@@ -137,19 +143,67 @@ struct Stream<2, T> {                       // V2 SHMEM (Algorithm 4)
     {
         // o = threadIdx - offset + comb[offset], offset = threadIdx mod C,
         // within the wave (the group never straddles a wave since C | 64).
-        const uint32_t off = lane & (a.group - 1);
-        const uint32_t gbase = lane - off;
-        addr1 = (int)((gbase + a.comb1[off]) << 2);
-        addr2 = (int)((gbase + a.comb2[off]) << 2);
+        const uint32_t m = a.group - 1;
+        const uint32_t gb = lane & ~m;
+        const uint32_t o1 = gb + a.comb1[lane & m];
+        const uint32_t o2 = gb + a.comb2[lane & m];
+        a1 = (int)(o1 << 2);
+        a2 = (int)(o2 << 2);
+        a11 = (int)((gb + a.comb1[o1 & m]) << 2);
+        a21 = (int)((gb + a.comb2[o1 & m]) << 2);
+        a12 = (int)((gb + a.comb1[o2 & m]) << 2);
+        a22 = (int)((gb + a.comb2[o2 & m]) << 2);
     }
     __device__ __forceinline__ uint32_t next()
     {
         const uint32_t u = x128_next(g);
-        const uint32_t n1 = (uint32_t)__builtin_amdgcn_ds_bpermute(addr1, (int)t);
-        const uint32_t n2 = (uint32_t)__builtin_amdgcn_ds_bpermute(addr2, (int)t);
+        const uint32_t n1 = (uint32_t)__builtin_amdgcn_ds_bpermute(a1, (int)t);
+        const uint32_t n2 = (uint32_t)__builtin_amdgcn_ds_bpermute(a2, (int)t);
         t = u ^ n1 ^ n2;
         x ^= t;
         return x;
+    }
+    // One step with the exchange through a per-wave LDS buffer xb[64]: every
+    // lane writes its previous word, then reads the two words it mixes.  LDS
+    // executes one wave's instructions in order, so all writes of the step
+    // land before any read; comb1/comb2 permute each group of consecutive
+    // words, so the reads are bank-conflict-free.
+    __device__ __forceinline__ uint32_t next_lds(uint32_t *xb, uint32_t lane)
+    {
+        const uint32_t u = x128_next(g);
+        xb[lane] = t;
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t n1 = xb[a1 >> 2];
+        const uint32_t n2 = xb[a2 >> 2];
+        __builtin_amdgcn_wave_barrier();
+        t = u ^ n1 ^ n2;
+        x ^= t;
+        return x;
+    }
+    // Two steps with one round of cross-lane reads:
+    //   t1 = u1 ^ t[o1] ^ t[o2]
+    //   t2 = u2 ^ t1[o1] ^ t1[o2]
+    //      = u2 ^ u1[o1] ^ u1[o2] ^ t[o1(o1)] ^ t[o2(o1)] ^ t[o1(o2)] ^ t[o2(o2)]
+    // (all reads see the words of the step before, as in next()).
+    __device__ __forceinline__ void next2(uint32_t &r0, uint32_t &r1)
+    {
+        const uint32_t u1 = x128_next(g);
+        const uint32_t u2 = x128_next(g);
+        const uint32_t p1 = (uint32_t)__builtin_amdgcn_ds_bpermute(a1, (int)t);
+        const uint32_t p2 = (uint32_t)__builtin_amdgcn_ds_bpermute(a2, (int)t);
+        const uint32_t p11 = (uint32_t)__builtin_amdgcn_ds_bpermute(a11, (int)t);
+        const uint32_t p21 = (uint32_t)__builtin_amdgcn_ds_bpermute(a21, (int)t);
+        const uint32_t p12 = (uint32_t)__builtin_amdgcn_ds_bpermute(a12, (int)t);
+        const uint32_t p22 = (uint32_t)__builtin_amdgcn_ds_bpermute(a22, (int)t);
+        const uint32_t q1 = (uint32_t)__builtin_amdgcn_ds_bpermute(a1, (int)u1);
+        const uint32_t q2 = (uint32_t)__builtin_amdgcn_ds_bpermute(a2, (int)u1);
+        const uint32_t t1 = u1 ^ p1 ^ p2;
+        const uint32_t t2 = u2 ^ q1 ^ q2 ^ p11 ^ p21 ^ p12 ^ p22;
+        x ^= t1;
+        r0 = x;
+        x ^= t2;
+        r1 = x;
+        t = t2;
     }
 };
 
@@ -197,6 +251,11 @@ struct Stream<1, T> {                       // V1 NAIVE3 (Listing 1, Algorithm 3
     {
         x ^= naive3_strategy(g);
         return x;
+    }
+    __device__ __forceinline__ void next2(uint32_t &r0, uint32_t &r1)
+    {
+        r0 = next();
+        r1 = next();
     }
 };
 
@@ -296,7 +355,7 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs a)
 // past the end run on a zero state and are never stored (for V2 these are
 // whole groups, so no live stream reads them).
 // ------------------------------------------------------------------------
-template <int VAR, typename T, int K, int S, bool NT>
+template <int VAR, typename T, int K, int S, bool NT, int XM>
 __global__ __launch_bounds__(256) void k_generate_tile(GenArgs a)
 {
     HIP_DYNAMIC_SHARED(uint32_t, lds);
@@ -305,6 +364,8 @@ __global__ __launch_bounds__(256) void k_generate_tile(GenArgs a)
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t base = wave * 64u * S;
     uint32_t *tile = lds + (threadIdx.x >> 6) * (64 * S * K);
+    // V2 with the LDS exchange: 64 words per slot after all tiles of the block.
+    uint32_t *xb = lds + (blockDim.x >> 6) * (64 * S * K) + (threadIdx.x >> 6) * (64 * S);
     const uint64_t n = a.n;
 
     Stream<VAR, T> st[S];
@@ -320,10 +381,22 @@ __global__ __launch_bounds__(256) void k_generate_tile(GenArgs a)
 #pragma unroll
         for (int q = 0; q < QPR; ++q) {
             uint32_t v[4][S];
+            if constexpr (XM == XCH_LDS) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
+                for (int e = 0; e < 4; ++e)
 #pragma unroll
-                for (int k = 0; k < S; ++k) v[e][k] = st[k].next();
+                    for (int k = 0; k < S; ++k) v[e][k] = st[k].next_lds(xb + 64 * k, lane);
+            } else if constexpr (XM == XCH_BPERM2) {
+#pragma unroll
+                for (int e = 0; e < 4; e += 2)
+#pragma unroll
+                    for (int k = 0; k < S; ++k) st[k].next2(v[e][k], v[e + 1][k]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int k = 0; k < S; ++k) v[e][k] = st[k].next();
+            }
 #pragma unroll
             for (int k = 0; k < S; ++k)
                 store4<false>(tile + (64 * k + lane) * K + 4 * (q ^ (lane & (QPR - 1))),
@@ -671,6 +744,22 @@ __global__ __launch_bounds__(256) void k_copy(uint32_t *dst, const uint32_t *src
     }
 }
 
+// VALU issue-rate probe: 8 independent xor/shift chains per lane, 4 VALU
+// instructions per chain per iteration (shift, xor, shift, xor), so one
+// iteration is 32 VALU instructions per lane.
+__global__ __launch_bounds__(256) void k_valu_probe(uint32_t *out, uint32_t iters)
+{
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t a0 = gid, a1 = gid + 1, a2 = gid + 2, a3 = gid + 3, a4 = gid + 4, a5 = gid + 5, a6 = gid + 6,
+             a7 = gid + 7;
+    for (uint32_t i = 0; i < iters; ++i) {
+#define XS(a) a ^= a << 7; a ^= a >> 9;
+        XS(a0) XS(a1) XS(a2) XS(a3) XS(a4) XS(a5) XS(a6) XS(a7)
+#undef XS
+    }
+    out[gid] = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7;
+}
+
 __global__ void k_tail_words(uint32_t *dst, const uint32_t *src, uint64_t begin, uint64_t end, uint32_t value)
 {
     const uint64_t i = begin + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
@@ -695,9 +784,20 @@ hipError_t tile_launch(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
     const uint32_t wpb = c.block / 64;
     const uint32_t grid = (uint32_t)((waves + wpb - 1) / wpb);
     size_t lds = (size_t)wpb * 64 * S * K * sizeof(uint32_t);
+    const int xm = (VAR == 2) ? (int)c.exchange : XCH_BPERM;
+    if (xm == XCH_LDS) lds += (size_t)wpb * 64 * S * sizeof(uint32_t);
     if (lds > 65536) return hipErrorInvalidValue;   // the host keeps tiles within 64 KiB
     if (c.lds_bytes > lds) lds = c.lds_bytes;
-    hipLaunchKernelGGL((k_generate_tile<VAR, T, K, S, NT>), dim3(grid), dim3(c.block), lds, st, a);
+    if constexpr (VAR == 2) {
+        if (xm == XCH_LDS)
+            hipLaunchKernelGGL((k_generate_tile<VAR, T, K, S, NT, XCH_LDS>), dim3(grid), dim3(c.block), lds, st, a);
+        else if (xm == XCH_BPERM2)
+            hipLaunchKernelGGL((k_generate_tile<VAR, T, K, S, NT, XCH_BPERM2>), dim3(grid), dim3(c.block), lds, st, a);
+        else
+            hipLaunchKernelGGL((k_generate_tile<VAR, T, K, S, NT, XCH_BPERM>), dim3(grid), dim3(c.block), lds, st, a);
+    } else {
+        hipLaunchKernelGGL((k_generate_tile<VAR, T, K, S, NT, XCH_BPERM>), dim3(grid), dim3(c.block), lds, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -835,6 +935,13 @@ static uint32_t probe_grid(uint64_t nq)
     const uint64_t cap = 256ull * 64;          // plenty of waves for 256 CUs
     if (g > cap) g = cap;
     return (uint32_t)(g ? g : 1);
+}
+
+hipError_t launch_valu_probe(uint32_t *out, uint32_t n_threads, uint32_t iters, hipStream_t st)
+{
+    if (n_threads == 0 || n_threads % 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_valu_probe, dim3(n_threads / 256), dim3(256), 0, st, out, iters);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill(uint32_t *dst, uint64_t n_words, uint32_t value, hipStream_t st)

@@ -20,6 +20,13 @@ enum StoreMode : int {
     ST_GENERIC = 6        // any alignment / length: one dword per output
 };
 
+// Neighbour-exchange implementations of the V2 variant (tiled kernel).
+enum ExchangeMode : int {
+    XCH_BPERM = 1,        // two cross-lane reads (ds_bpermute) per step
+    XCH_LDS = 2,          // per-wave LDS word buffer: one write, two reads per step
+    XCH_BPERM2 = 3        // two steps per round of eight cross-lane reads
+};
+
 // Kernel arguments of the plain generate / consume kernels.
 struct GenArgs {
     uint32_t *state;       // SoA: word k of stream s at state[k * ns + s]
@@ -38,6 +45,7 @@ struct LaunchCfg {
     uint32_t store;        // StoreMode
     uint32_t lds_bytes;    // LDS modes: dynamic LDS per block (>= the tile; more caps occupancy)
     uint32_t slots;        // LDS modes: streams per lane (1, 2 or 4)
+    uint32_t exchange;     // V2, LDS modes: ExchangeMode
 };
 
 // variant: 0 V0, 1 V1 (w32 selects 32-bit words), 2 V2.
@@ -84,6 +92,7 @@ hipError_t launch_commit(uint32_t *state, const uint32_t *state_next, const uint
 hipError_t launch_zero_u32(uint32_t *p, uint32_t count, hipStream_t st);
 
 hipError_t launch_fill(uint32_t *dst, uint64_t n_words, uint32_t value, hipStream_t st);
+hipError_t launch_valu_probe(uint32_t *out, uint32_t n_threads, uint32_t iters, hipStream_t st);
 hipError_t launch_copy(uint32_t *dst, const uint32_t *src, uint64_t n_words, hipStream_t st);
 
 }  // namespace cprng_impl

@@ -61,8 +61,8 @@ void load_file_locked()
     while (std::fgets(line, sizeof line, f)) {
         char key[256];
         TuneEntry e;
-        if (std::sscanf(line, " \"%255[^\"]\" : {\"block\": %u, \"unroll\": %u, \"store\": %u, \"chunk\": %u, \"waves\": %u, \"slots\": %u}",
-                        key, &e.block, &e.unroll, &e.store, &e.chunk, &e.waves, &e.slots) == 7)
+        if (std::sscanf(line, " \"%255[^\"]\" : {\"block\": %u, \"unroll\": %u, \"store\": %u, \"chunk\": %u, \"waves\": %u, \"slots\": %u, \"exchange\": %u}",
+                        key, &e.block, &e.unroll, &e.store, &e.chunk, &e.waves, &e.slots, &e.exchange) == 8)
             g_table[key] = e;
     }
     std::fclose(f);
@@ -79,8 +79,8 @@ void save_file_locked()
     size_t i = 0;
     for (const auto &kv : g_table) {
         const TuneEntry &e = kv.second;
-        std::fprintf(f, "  \"%s\": {\"block\": %u, \"unroll\": %u, \"store\": %u, \"chunk\": %u, \"waves\": %u, \"slots\": %u}%s\n",
-                     kv.first.c_str(), e.block, e.unroll, e.store, e.chunk, e.waves, e.slots,
+        std::fprintf(f, "  \"%s\": {\"block\": %u, \"unroll\": %u, \"store\": %u, \"chunk\": %u, \"waves\": %u, \"slots\": %u, \"exchange\": %u}%s\n",
+                     kv.first.c_str(), e.block, e.unroll, e.store, e.chunk, e.waves, e.slots, e.exchange,
                      ++i < g_table.size() ? "," : "");
     }
     std::fprintf(f, "}\n");
@@ -100,6 +100,7 @@ LaunchCfg default_cfg(uint32_t variant, bool w32, bool consume)
     c.store = e.store;
     c.lds_bytes = 0;
     c.slots = e.slots ? e.slots : 1;
+    c.exchange = e.exchange ? e.exchange : (uint32_t)XCH_BPERM;
     return c;
 }
 
@@ -111,6 +112,7 @@ TuneEntry default_entry(uint32_t variant, bool consume)
     // VALU-bound and takes K = 64.
     TuneEntry e;
     e.slots = 1;
+    e.exchange = XCH_BPERM;
     switch (variant) {
     case CPRNG_V0_PLAIN:
         e.block = 128; e.unroll = 128; e.store = ST_LDS_NT; e.waves = 8;
@@ -204,6 +206,7 @@ extern "C" int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n, cprng_s
     const uint32_t stores[] = {ST_DIRECT, ST_LDS, ST_LDS_NT};
     const uint32_t caps[] = {0, 4, 8};
     const uint32_t slot_opts[] = {1, 2, 4};
+    const uint32_t xch_opts[] = {XCH_BPERM, XCH_LDS};
     float best = 1e30f;
     TuneEntry best_e;
     const bool saved_timing = h->timing;
@@ -213,12 +216,14 @@ extern "C" int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n, cprng_s
         for (uint32_t u : unrolls)
             for (uint32_t s : stores)
                 for (uint32_t w : caps)
-                for (uint32_t sl : slot_opts) {
+                for (uint32_t sl : slot_opts)
+                for (uint32_t xm : xch_opts) {
                 const bool lds_mode = s == ST_LDS || s == ST_LDS_NT;
-                if (!lds_mode && (u > 32 || w || sl > 1)) continue;   // direct modes: K <= 32
+                if (!lds_mode && (u > 32 || w || sl > 1 || xm != XCH_BPERM)) continue;   // direct: K <= 32
+                if (h->variant != CPRNG_V2_SHMEM && xm != XCH_BPERM) continue;
                 if (lds_mode && u < 16) continue;
-                if (lds_mode && (size_t)b * sl * u * 4 > 65536) continue;
-                LaunchCfg c{b, u, s, lds_for_waves(b, w), sl};
+                if (lds_mode && (size_t)b * sl * (u + (xm == XCH_LDS ? 1 : 0)) * 4 > 65536) continue;
+                LaunchCfg c{b, u, s, lds_for_waves(b, w), sl, xm};
                 std::vector<float> t;
                 for (int r = 0; r < 4 && rc == CPRNG_OK; ++r) {
                     if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
@@ -239,6 +244,7 @@ extern "C" int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n, cprng_s
                     best_e.store = s;
                     best_e.waves = w;
                     best_e.slots = sl;
+                    best_e.exchange = xm;
                 }
             }
     h->timing = saved_timing;

@@ -8,7 +8,7 @@
 namespace cprng_impl {
 
 struct TuneEntry {
-    uint32_t block = 0, unroll = 0, store = 0, chunk = 0, waves = 0, slots = 0;
+    uint32_t block = 0, unroll = 0, store = 0, chunk = 0, waves = 0, slots = 0, exchange = 0;
 };
 
 LaunchCfg default_cfg(uint32_t variant, bool w32, bool consume);

@@ -93,6 +93,22 @@ def test_v2_shmem_4096x1024(orc, G, store, unroll):
     _gen_check(orc, G, "v2", 2, 4096, 1024, sigma=1, tuning=dict(store=store, unroll=unroll, block=64))
 
 
+@pytest.mark.parametrize("exchange", [1, 2, 3])
+@pytest.mark.parametrize("unroll,block,slots", [(32, 128, 1), (64, 64, 2), (128, 64, 1), (16, 256, 4)])
+def test_v2_exchange_modes(orc, G, exchange, unroll, block, slots):
+    # Cross-lane reads, LDS word buffer, and two steps per read round; a
+    # partial last wave (2080 streams) and a tail (n = 1000).
+    _gen_check(orc, G, "v2", 2, 2080, 1000, sigma=14,
+               tuning=dict(store=2, unroll=unroll, block=block, streams_per_lane=slots, exchange=exchange))
+
+
+@pytest.mark.parametrize("exchange", [2, 3])
+@pytest.mark.parametrize("group", [4, 16, 64])
+def test_v2_exchange_modes_group_sizes(orc, G, exchange, group):
+    _gen_check(orc, G, "v2", 2, 512, 200, sigma=15, group=group,
+               tuning=dict(store=4, unroll=32, block=128, exchange=exchange))
+
+
 @pytest.mark.parametrize("group", [4, 8, 16, 64])
 def test_v2_other_group_sizes_default_combs(orc, G, group):
     _gen_check(orc, G, "v2", 2, 512, 200, sigma=3, group=group)

@@ -455,3 +455,10 @@ def test_consume_predicate_edges(orc):
     assert not orc.qc_hit((U + 1) << 8, (U + 1) << 8)
     # (2^24-1, 0): u^2 rounds to 1 - 2^-23 < 1 -> hit
     assert orc.qc_hit(0xFFFFFF00, 0)
+    # A pair whose binary32 sum rounds to exactly 1 (u^2 -> 1 - 2^-23, v^2 ->
+    # 2^-23 + 4416*2^-48): the strict '<' must exclude it.
+    U, V = (1 << 24) - 1, 5793
+    u = np.float32(U) * np.float32(2.0 ** -24)
+    v = np.float32(V) * np.float32(2.0 ** -24)
+    assert (u * u) + (v * v) == np.float32(1.0)
+    assert not orc.qc_hit(U << 8, V << 8)
