@@ -190,14 +190,24 @@ int cprng_default_combs(uint32_t C, uint32_t *comb1, uint32_t *comb2);
 
 /* Kernel configuration used by the hot-path entry points.  Zero fields mean
  * "autotuned / default".  store: 0 auto, 1 per-lane direct, 2 LDS-transposed,
- * 3 direct non-temporal, 4 LDS-transposed non-temporal. */
+ * 3 direct non-temporal, 4 LDS-transposed non-temporal, 7 persistent
+ * pipelined (waves_per_cu one-wave workgroups per CU take 64-stream blocks in
+ * address order; two LDS tiles so each round's stores overlap the next
+ * round's generation), 8 as 7 with non-temporal stores.  Handles created with
+ * CPRNG_F_INTERLEAVED take 0/2/7 (LDS tiles of unroll steps x block streams,
+ * each step's block stored as one contiguous run; needs n_streams % 4 == 0 and
+ * a 16-byte aligned output, else the per-lane path runs), 4/8 (the same,
+ * non-temporal) or 1/3 (per-lane dword stores). */
 typedef struct cprng_tuning {
-    uint32_t block;            /* threads per block: 64, 128, 192 or 256 */
+    uint32_t block;            /* threads per block: 64, 128, 192 or 256; the interleaved
+                                  layout's tiles take 256, 512 or 1024 (streams per tile) */
     uint32_t unroll;           /* outputs per stream per round: 8, 16, 32 (direct);
-                                  16..256, powers of two (LDS-transposed) */
+                                  16..256, powers of two (LDS-transposed);
+                                  16..128 (pipelined) */
     uint32_t store;            /* store mode, see above */
     uint32_t chunk;            /* ragged/requests: outputs per chunk (multiple of 64) */
-    uint32_t waves_per_cu;     /* ragged/requests: persistent waves per CU;
+    uint32_t waves_per_cu;     /* ragged/requests and pipelined generate: persistent
+                                  waves per CU (0 = default);
                                   LDS-transposed generate: residency cap (0 = none) */
     uint32_t streams_per_lane; /* LDS-transposed generate: 1, 2 or 4 streams per lane */
     uint32_t exchange;         /* V2, LDS-transposed generate: 1 cross-lane reads,

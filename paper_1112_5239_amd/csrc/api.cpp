@@ -155,6 +155,18 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
         tune_cache_load(h);
         h->tuned_loaded = true;
     }
+    if (!consume && (h->flags & CPRNG_F_INTERLEAVED)) {
+        // Interleaved layout: LDS tiles of K steps x block streams (measured
+        // on MI355X: 1,024 streams x 16 steps, 4 KiB contiguous per step);
+        // direct store modes select the per-lane dword kernel.
+        LaunchCfg c{1024, 16, ST_ILV_TILE, 0, 1, XCH_BPERM, 0};
+        if (h->tuning.store == ST_DIRECT || h->tuning.store == ST_DIRECT_NT) c.store = ST_INTERLEAVED;
+        if (h->tuning.store == ST_LDS_NT || h->tuning.store == ST_PIPE_NT) c.store = ST_ILV_TILE_NT;
+        if (h->tuning.block) c.block = h->tuning.block;
+        if (h->tuning.unroll) c.unroll = h->tuning.unroll;
+        if (h->tuning.exchange) c.exchange = h->tuning.exchange;
+        return c;
+    }
     LaunchCfg c = default_cfg(h->variant, (h->flags & CPRNG_F_V1_W32) != 0, consume);
     TuneEntry e = default_entry(h->variant, consume);
     if (!consume && tune_cache_lookup(h, n, &e)) {
@@ -170,7 +182,14 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
     if (h->tuning.unroll) c.unroll = h->tuning.unroll;
     if (h->tuning.store && !consume) c.store = h->tuning.store;
     const uint32_t wpc = h->tuning.waves_per_cu ? h->tuning.waves_per_cu : (consume ? 0u : e.waves);
-    c.lds_bytes = lds_for_waves(c.block, wpc);
+    if (c.store == ST_PIPE || c.store == ST_PIPE_NT) {
+        // persistent: waves per CU sets the grid, one wave per workgroup
+        c.block = 64;
+        c.grid = h->n_cu * (wpc ? wpc : 2u);
+        c.lds_bytes = 0;
+    } else {
+        c.lds_bytes = lds_for_waves(c.block, wpc);
+    }
     return c;
 }
 
@@ -185,8 +204,28 @@ int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchC
     a.out = out;
     a.n = n;
     if (h->flags & CPRNG_F_INTERLEAVED) {
-        c.store = ST_INTERLEAVED;
+        const bool tile_ok = ((uintptr_t)out % 16u) == 0 && (h->ns % 4u) == 0;
+        if (!tile_ok || (c.store != ST_ILV_TILE && c.store != ST_ILV_TILE_NT)) c.store = ST_INTERLEAVED;
+        if (c.store == ST_INTERLEAVED) {
+            if (c.block > 256) c.block = 256;
+            if (c.unroll > 32) c.unroll = 32;
+        } else {
+            // block: 256, 512 or 1024 streams; K * block words (+ the V2
+            // exchange buffer) must fit 64 KiB
+            uint32_t b = 256;
+            while (b < c.block && b < 1024) b *= 2;
+            c.block = b;
+            if (c.unroll < 8) c.unroll = 8;
+            if (c.unroll > 64) c.unroll = 64;
+            if (c.exchange < XCH_BPERM || c.exchange > XCH_LDS) c.exchange = XCH_BPERM;
+            const uint32_t extra = (h->variant == CPRNG_V2_SHMEM && c.exchange == XCH_LDS) ? 1u : 0u;
+            while ((uint64_t)(c.unroll + extra) * c.block * 4u > 65536u) {
+                if (c.unroll > 8) c.unroll /= 2;
+                else c.block /= 2;
+            }
+        }
     } else {
+        if (c.block > 256) c.block = 256;
         const bool aligned = ((uintptr_t)out % 16u) == 0 && (n % 4u) == 0;
         if (!aligned) c.store = ST_GENERIC;
     }
@@ -201,6 +240,17 @@ int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchC
         while (c.block > 64 && (uint64_t)c.block * c.slots * (c.unroll + extra) * 4u > 65536u) c.block -= 64;
         while (c.slots > 1 && (uint64_t)c.block * c.slots * (c.unroll + extra) * 4u > 65536u) c.slots /= 2;
         if ((uint64_t)c.block * c.slots * (c.unroll + extra) * 4u > 65536u) c.unroll /= 2;
+    }
+    if ((c.store == ST_PIPE || c.store == ST_PIPE_NT) && n >= (1ull << 26)) c.store = ST_LDS;   // 32-bit block offsets
+    if (c.store == ST_PIPE || c.store == ST_PIPE_NT) {
+        // two tiles (+ the exchange buffer) per wave must fit 64 KiB
+        c.block = 64;
+        if (c.unroll < 16) c.unroll = 16;
+        if (c.unroll > 128) c.unroll = 128;
+        if (c.exchange < XCH_BPERM || c.exchange > XCH_BPERM2) c.exchange = XCH_BPERM;
+        const uint32_t extra = (h->variant == CPRNG_V2_SHMEM && c.exchange == XCH_LDS) ? 64u : 0u;
+        if ((uint64_t)2 * 64 * c.unroll * 4u + extra * 4u > 65536u) c.unroll /= 2;
+        if (!c.grid) c.grid = h->n_cu * 2u;
     }
     int rc = begin_timing(h, st);
     if (rc) return rc;
@@ -339,11 +389,13 @@ int cprng_default_combs(uint32_t C, uint32_t *comb1, uint32_t *comb2)
 int cprng_set_tuning(cprng_t *h, const cprng_tuning_t *t)
 {
     if (!h || !t) return set_error(CPRNG_E_INVAL, "NULL argument");
-    if (t->block && (t->block % 64 || t->block > 256)) return set_error(CPRNG_E_INVAL, "block must be 64, 128, 192 or 256");
+    if (t->block && (t->block % 64 || t->block > 1024))
+        return set_error(CPRNG_E_INVAL, "block must be a multiple of 64, <= 1024 (above 256: interleaved tiles)");
     if (t->unroll && t->unroll != 8 && t->unroll != 16 && t->unroll != 32 && t->unroll != 64 &&
         t->unroll != 128 && t->unroll != 256)
         return set_error(CPRNG_E_INVAL, "unroll must be 8, 16, 32, 64, 128 or 256 (above 32: LDS store modes)");
-    if (t->store > 4) return set_error(CPRNG_E_INVAL, "store mode must be 0..4");
+    if (t->store > 8 || t->store == 5 || t->store == 6)
+        return set_error(CPRNG_E_INVAL, "store mode must be 0..4, 7 or 8");
     if (t->chunk && (t->chunk % 64 || t->chunk > (1u << 24))) return set_error(CPRNG_E_INVAL, "chunk must be a multiple of 64, <= 2^24");
     if (t->waves_per_cu > 32) return set_error(CPRNG_E_INVAL, "waves_per_cu must be <= 32");
     if (t->streams_per_lane && t->streams_per_lane != 1 && t->streams_per_lane != 2 && t->streams_per_lane != 4)

@@ -280,6 +280,24 @@ __device__ __forceinline__ void load4(const uint32_t *p, uint32_t &a, uint32_t &
     a = v.x; b = v.y; c = v.z; d = v.w;
 }
 
+// Pointers rebuilt from integers default to the generic (flat) address
+// space; these keep chunk outputs in the global address space.
+typedef __attribute__((address_space(1))) uint32_t gu32;
+
+__device__ __forceinline__ gu32 *gptr(uint64_t addr) { return (gu32 *)(uintptr_t)addr; }
+
+template <bool NT>
+__device__ __forceinline__ void gstore4(gu32 *p, uint32_t a, uint32_t b, uint32_t c, uint32_t d)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(1))) u32x4 gu32x4;
+    u32x4 v = {a, b, c, d};
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, (gu32x4 *)p);
+    else
+        *(gu32x4 *)p = v;
+}
+
 // ------------------------------------------------------------------------
 // Plain generate kernel: one lane per stream, K outputs per lane per round.
 //   ST_DIRECT(_NT): lane stores its K outputs as K/4 aligned 16-byte quads.
@@ -430,6 +448,159 @@ __global__ __launch_bounds__(256) void k_generate_tile(GenArgs a)
 }
 
 // ------------------------------------------------------------------------
+// Persistent pipelined tile kernel (ST_PIPE, ST_PIPE_NT): one wave per
+// workgroup and gridDim.x workgroups, which take 64-stream blocks in address
+// order (block b, b + gridDim.x, ...), so the rows written at any moment are
+// neighbours in memory and the set of open DRAM pages stays small with only
+// a few waves per CU.  Two LDS tiles alternate: while round r is generated
+// into one, round r-1 is stored from the other, one store instruction per
+// generated quad, so a wave's VALU work overlaps its own stores.  Store
+// instruction j of a round covers rows j*RPI .. j*RPI+RPI-1 (RPI = 64/(K/4)).
+// ------------------------------------------------------------------------
+template <int VAR, typename T, int K, bool NT, int XM>
+__global__ __launch_bounds__(64) void k_generate_pipe(GenArgs a)
+{
+    HIP_DYNAMIC_SHARED(uint32_t, lds);
+    constexpr int QPR = K / 4;
+    constexpr int RPI = 64 / QPR;
+    static_assert(K >= 16 && QPR <= 64 && 64 % QPR == 0, "K must divide 256");
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t q = lane % QPR;
+    const uint32_t rsub = lane / QPR;
+    uint32_t *xb = lds + 2 * 64 * K;         // V2 with the LDS exchange
+    const uint64_t n = a.n;
+    const uint64_t rounds = n / K;
+    // The host launches this kernel only when a 64-stream block spans fewer
+    // than 2^32 words (n < 2^26), so in-block offsets fit 32 bits and every
+    // store is a uniform block base plus a 32-bit lane offset.
+    const uint32_t jstride = (uint32_t)(RPI * n);  // words between store instructions' rows
+    const uint32_t nblk = (a.ns + 63u) / 64u;
+    for (uint32_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const uint64_t base = (uint64_t)blk * 64u;
+        const uint64_t s = base + lane;
+        Stream<VAR, T> st;
+        if (s < a.ns) st.load(a, (uint32_t)s);
+        else st = Stream<VAR, T>{};
+        st.init_exchange(a, lane);
+        const uint32_t nrows = (a.ns - base) < 64u ? (uint32_t)(a.ns - base) : 64u;
+        gu32 *blk_out = gptr((uint64_t)(uintptr_t)(a.out + base * n));
+        const uint32_t lane_off = rsub * (uint32_t)n + 4u * q;
+        auto gen_quad = [&](uint32_t *buf, int qq) {
+            uint32_t v[4];
+            if constexpr (XM == XCH_LDS) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = st.next_lds(xb, lane);
+            } else if constexpr (XM == XCH_BPERM2) {
+                st.next2(v[0], v[1]);
+                st.next2(v[2], v[3]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = st.next();
+            }
+            store4<false>(buf + lane * K + 4 * (qq ^ (lane & (QPR - 1))), v[0], v[1], v[2], v[3]);
+        };
+        auto put_quad = [&](const uint32_t *buf, int j, uint32_t off) {
+            const uint32_t r = j * RPI + rsub;
+            uint32_t x0, x1, x2, x3;
+            load4(buf + r * K + 4 * (q ^ (r & (QPR - 1))), x0, x1, x2, x3);
+            gstore4<NT>(blk_out + (off + (uint32_t)j * jstride), x0, x1, x2, x3);
+        };
+        // A full block runs the pipelined rounds; the last block of a launch
+        // whose stream count is not a multiple of 64 stores per lane (its
+        // absent rows' lanes stay inactive; V2 groups are whole, so the
+        // present lanes never read an absent lane's word).
+        uint64_t t0 = 0;
+        if (nrows == 64u && rounds) {
+#pragma unroll
+            for (int qq = 0; qq < QPR; ++qq) gen_quad(lds, qq);
+            __syncthreads();
+            for (uint64_t r = 1; r < rounds; ++r) {
+                uint32_t *cur = lds + (r & 1u) * (64 * K);
+                const uint32_t *prev = lds + ((r - 1) & 1u) * (64 * K);
+                const uint32_t off = lane_off + (uint32_t)(r - 1) * K;
+#pragma unroll
+                for (int qq = 0; qq < QPR; ++qq) {
+                    gen_quad(cur, qq);
+                    put_quad(prev, qq, off);
+                }
+                __syncthreads();
+            }
+            const uint32_t *last = lds + ((rounds - 1) & 1u) * (64 * K);
+            const uint32_t off = lane_off + (uint32_t)(rounds - 1) * K;
+#pragma unroll
+            for (int j = 0; j < QPR; ++j) put_quad(last, j, off);
+            __syncthreads();
+            t0 = rounds * K;
+        }
+        if (s < a.ns) {
+            uint32_t *o = a.out + s * n;
+            for (uint64_t t = t0; t < n; t += 4) {    // n % 4 == 0
+                const uint32_t v0 = st.next(), v1 = st.next(), v2 = st.next(), v3 = st.next();
+                store4<NT>(o + t, v0, v1, v2, v3);
+            }
+            st.save(a, (uint32_t)s);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Interleaved-layout tile kernel (ST_ILV_TILE, ST_ILV_TILE_NT), output
+// out[i * ns + s].  A workgroup of B threads holds B consecutive streams.
+// Each round every thread writes its next K outputs into column t of a K x B
+// LDS tile; row k of the tile is step i + k of B neighbouring streams, i.e.
+// 4B contiguous bytes of the output, and the rows are stored as 16-byte
+// quads, 64 consecutive quads (1 KiB) per store instruction.  Workgroups that
+// run together advance through the steps together, so the writes in flight
+// form a few long contiguous fronts.  Needs ns % 4 == 0 and a 16-byte
+// aligned output.
+// ------------------------------------------------------------------------
+template <int VAR, typename T, int K, int B, bool NT, int XM>
+__global__ __launch_bounds__(B) void k_generate_ilv(GenArgs a)
+{
+    HIP_DYNAMIC_SHARED(uint32_t, lds);
+    constexpr int QR = B / 4;                // quads per tile row
+    static_assert(B >= 256 && (B & (B - 1)) == 0 && K % 4 == 0, "B a power of two >= 256");
+    const uint32_t t = threadIdx.x;
+    const uint32_t lane = t & 63u;
+    const uint64_t ns = a.ns;
+    const uint64_t base = (uint64_t)blockIdx.x * B;
+    const uint64_t s = base + t;
+    uint32_t *xb = lds + K * B + (t & ~63u); // V2 with the LDS exchange: 64 words per wave
+    Stream<VAR, T> st;
+    if (s < ns) st.load(a, (uint32_t)s);
+    else st = Stream<VAR, T>{};
+    st.init_exchange(a, lane);
+    const uint32_t cq = t % QR;              // quad column this thread stores
+    const uint32_t r0 = t / QR;              // its row among each group of B / QR = 4 rows
+    const bool col_ok = base + 4u * cq < ns;
+    const uint64_t n = a.n;
+    gu32 *out = gptr((uint64_t)(uintptr_t)a.out) + base + 4u * cq;
+    uint64_t i = 0;
+    for (; i + K <= n; i += K) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            uint32_t v;
+            if constexpr (XM == XCH_LDS) v = st.next_lds(xb, lane);
+            else v = st.next();
+            lds[k * B + t] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < K / 4; ++j) {
+            const uint32_t row = 4u * j + r0;
+            uint32_t x0, x1, x2, x3;
+            load4(lds + row * B + 4u * cq, x0, x1, x2, x3);
+            if (col_ok) gstore4<NT>(out + (i + row) * ns, x0, x1, x2, x3);
+        }
+        __syncthreads();
+    }
+    if (s < ns) {                            // whole V2 groups: present lanes read present lanes only
+        for (; i < n; ++i) a.out[i * ns + s] = st.next();
+        st.save(a, (uint32_t)s);
+    }
+}
+
+// ------------------------------------------------------------------------
 // Consumption kernel: pairs of outputs -> binary32 point in [0,1)^2 -> hit
 // count of the unit quarter circle.  Products and the sum are rounded one by
 // one (contraction is off for this file).
@@ -515,7 +686,7 @@ __device__ __forceinline__ void jump_v0(X128 &g, uint32_t &x, const uint32_t *po
 
 // Segment idx -> its run, position, length, head and jump polynomial.
 struct Seg {
-    uint32_t *out;         // first output of the segment
+    gu32 *out;             // first output of the segment
     uint32_t len, head, stream, last;
     const uint32_t *poly;  // nullptr: no jump (segment 0)
     uint64_t pos;          // start position within the run
@@ -549,7 +720,7 @@ __device__ __forceinline__ Seg decode_segment(const SegArgs &a, uint32_t idx)
         s.poly = a.polys + 5ull * ((uint64_t)r.head * a.kcap + k);
     }
     s.len = (uint32_t)len;
-    s.out = reinterpret_cast<uint32_t *>(r.out) + s.pos;
+    s.out = gptr(r.out) + s.pos;
     s.last = (r.last && s.pos + len == r.len) ? 1u : 0u;
     return s;
 }
@@ -571,7 +742,7 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a)
             X128 g{p[0], p[ns], p[2 * ns], p[3 * ns]};
             uint32_t x = p[4 * ns];
             if (d.poly) jump_v0(g, x, d.poly);
-            uint32_t *o = d.out;
+            gu32 *o = d.out;
             const uint32_t len = d.len;
             uint32_t i = 0;
             const uint32_t head = d.head < len ? d.head : len;
@@ -588,7 +759,7 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a)
                 }
 #pragma unroll
                 for (int q = 0; q < K / 4; ++q)
-                    store4<false>(o + i + 4 * q, v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+                    gstore4<false>(o + i + 4 * q, v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
             }
             for (; i + 4 <= len; i += 4) {
                 uint32_t v0, v1, v2, v3;
@@ -596,7 +767,7 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a)
                 x ^= x128_next(g); v1 = x;
                 x ^= x128_next(g); v2 = x;
                 x ^= x128_next(g); v3 = x;
-                store4<false>(o + i, v0, v1, v2, v3);
+                gstore4<false>(o + i, v0, v1, v2, v3);
             }
             for (; i < len; ++i) {
                 x ^= x128_next(g);
@@ -612,20 +783,28 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a)
 }
 
 // Tiled variant of k_segments: one wave per workgroup (each wave runs its
-// own number of rounds, so barriers must stay wave-local).  Each round every
-// lane writes its segment's next K outputs to its LDS row; the wave then
-// stores the 64 x K tile with whole-line 16-byte stores, using each row's
-// destination and count (a row's last partial quad is stored word by word).
-// Rows start 16-byte aligned after the segment's head (0..3 outputs stored
-// singly before the first round).
+// own number of rounds, so barriers must stay wave-local).  After a grab of
+// 64 segments the wave stores, in each round, every segment's next K outputs
+// through an LDS tile as in k_generate_tile.  Store instruction j of a round
+// covers rows j*RPI .. j*RPI+RPI-1 (RPI = 64/(K/4) rows of K words); the rows
+// a lane serves are the same in every round, so their base addresses and
+// lengths are read once per grab into registers.  Rounds in which every row
+// is full take a branch-free store loop; the last rounds of short segments
+// store whole quads, then the final partial quad word by word.  Rows start
+// 16-byte aligned after the segment's head (0..3 outputs stored singly).
 template <int K, bool NT>
 __global__ __launch_bounds__(64) void k_segments_tile(SegArgs a)
 {
     HIP_DYNAMIC_SHARED(uint32_t, lds);
-    constexpr int QPR = K / 4;
+    constexpr int QPR = K / 4;               // quads per row
+    constexpr int RPI = 64 / QPR;            // rows per store instruction
+    static_assert(QPR <= 64 && 64 % QPR == 0, "K must divide 256");
     uint32_t *tile = lds;                    // 64 rows x K words, quad-swizzled
-    uint32_t *meta = lds + 64 * K;           // per row: address lo, hi, count
+    uint64_t *mbase = reinterpret_cast<uint64_t *>(lds + 64 * K);   // per row: base after head
+    uint32_t *mlen = lds + 64 * K + 128;     // per row: outputs after head
     const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t q = lane % QPR;           // quad a lane stores
+    const uint32_t rsub = lane / QPR;        // row within an instruction's RPI rows
     const uint64_t ns = a.ns;
     for (;;) {
         uint32_t base = 0;
@@ -635,36 +814,46 @@ __global__ __launch_bounds__(64) void k_segments_tile(SegArgs a)
         const uint32_t idx = base + lane;
         X128 g{0u, 0u, 0u, 0u};
         uint32_t x = 0, rem = 0, stream = 0, last = 0;
-        uint32_t *o = nullptr;
+        uint64_t obase = 0;
         if (idx < a.nseg) {
             const Seg d = decode_segment(a, idx);
             const uint32_t *p = a.state + d.stream;
             g = X128{p[0], p[ns], p[2 * ns], p[3 * ns]};
             x = p[4 * ns];
             if (d.poly) jump_v0(g, x, d.poly);
-            o = d.out;
             const uint32_t head = d.head < d.len ? d.head : d.len;
             for (uint32_t i = 0; i < head; ++i) {
                 x ^= x128_next(g);
-                o[i] = x;
+                d.out[i] = x;
             }
-            o += head;
+            obase = (uint64_t)(uintptr_t)(d.out + head);
             rem = d.len - head;
             stream = d.stream;
             last = d.last;
         }
+        mbase[lane] = obase;
+        mlen[lane] = rem;
+        __syncthreads();
+        uint64_t rb[QPR];
+        uint32_t rl[QPR];
+#pragma unroll
+        for (int j = 0; j < QPR; ++j) {
+            rb[j] = mbase[j * RPI + rsub] + 16u * q;
+            rl[j] = mlen[j * RPI + rsub];
+        }
+        uint32_t done = 0;                   // outputs per row stored so far (uniform)
+        uint32_t *row = tile + lane * K;
         while (__ballot(rem > 0u) != 0ull) {
             const uint32_t cnt = rem < (uint32_t)K ? rem : (uint32_t)K;
-            uint32_t *row = tile + lane * K;
             if (cnt == (uint32_t)K) {
 #pragma unroll
-                for (int q = 0; q < QPR; ++q) {
+                for (int qq = 0; qq < QPR; ++qq) {
                     uint32_t v0, v1, v2, v3;
                     x ^= x128_next(g); v0 = x;
                     x ^= x128_next(g); v1 = x;
                     x ^= x128_next(g); v2 = x;
                     x ^= x128_next(g); v3 = x;
-                    store4<false>(row + 4 * (q ^ (lane & (QPR - 1))), v0, v1, v2, v3);
+                    store4<false>(row + 4 * (qq ^ (lane & (QPR - 1))), v0, v1, v2, v3);
                 }
             } else {
                 for (uint32_t j = 0; j < cnt; ++j) {
@@ -672,38 +861,43 @@ __global__ __launch_bounds__(64) void k_segments_tile(SegArgs a)
                     row[4 * ((j >> 2) ^ (lane & (QPR - 1))) + (j & 3u)] = x;
                 }
             }
-            const uint64_t oa = (uint64_t)(uintptr_t)o;
-            meta[lane * 4 + 0] = (uint32_t)oa;
-            meta[lane * 4 + 1] = (uint32_t)(oa >> 32);
-            meta[lane * 4 + 2] = cnt;
             __syncthreads();
-#pragma unroll 8
-            for (int j = 0; j < QPR; ++j) {
-                const uint32_t Q = j * 64 + lane;
-                const uint32_t r = Q / QPR;
-                const uint32_t q = Q % QPR;
-                const uint32_t cr = meta[r * 4 + 2];
-                if (4 * q < cr) {
-                    uint32_t *dst = reinterpret_cast<uint32_t *>(
-                        (uintptr_t)(((uint64_t)meta[r * 4 + 1] << 32) | meta[r * 4 + 0])) + 4 * q;
-                    const uint32_t *src = tile + r * K + 4 * (q ^ (r & (QPR - 1)));
-                    if (4 * q + 4 <= cr) {
-                        uint32_t x0, x1, x2, x3;
-                        load4(src, x0, x1, x2, x3);
-                        store4<NT>(dst, x0, x1, x2, x3);
-                    } else {
-                        for (uint32_t e = 0; e < cr - 4 * q; ++e) dst[e] = src[e];
+            const bool all_full = __ballot(cnt != (uint32_t)K) == 0ull;
+            if (all_full) {
+#pragma unroll
+                for (int j = 0; j < QPR; ++j) {
+                    const uint32_t r = j * RPI + rsub;
+                    uint32_t x0, x1, x2, x3;
+                    load4(tile + r * K + 4 * (q ^ (r & (QPR - 1))), x0, x1, x2, x3);
+                    gstore4<NT>(gptr(rb[j] + 4ull * done), x0, x1, x2, x3);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < QPR; ++j) {
+                    const uint32_t r = j * RPI + rsub;
+                    const uint32_t left = rl[j] > done ? rl[j] - done : 0u;
+                    const uint32_t cr = left < (uint32_t)K ? left : (uint32_t)K;
+                    if (4 * q < cr) {
+                        const uint32_t *src = tile + r * K + 4 * (q ^ (r & (QPR - 1)));
+                        gu32 *dst = gptr(rb[j] + 4ull * done);
+                        if (4 * q + 4 <= cr) {
+                            uint32_t x0, x1, x2, x3;
+                            load4(src, x0, x1, x2, x3);
+                            gstore4<NT>(dst, x0, x1, x2, x3);
+                        } else {
+                            for (uint32_t e = 0; e < cr - 4 * q; ++e) dst[e] = src[e];
+                        }
                     }
                 }
             }
             __syncthreads();
-            o += cnt;
+            done += (uint32_t)K;
             rem -= cnt;
         }
         if (last) {
-            uint32_t *q = a.state_next + stream;
-            q[0] = g.x; q[ns] = g.y; q[2 * ns] = g.z; q[3 * ns] = g.w;
-            q[4 * ns] = x;
+            uint32_t *st = a.state_next + stream;
+            st[0] = g.x; st[ns] = g.y; st[2 * ns] = g.z; st[3 * ns] = g.w;
+            st[4 * ns] = x;
         }
     }
 }
@@ -813,6 +1007,55 @@ hipError_t tile_by_slots(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
     return hipErrorInvalidValue;
 }
 
+template <int VAR, typename T, int K, bool NT>
+hipError_t pipe_launch(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
+{
+    const uint32_t nblk = (a.ns + 63u) / 64u;
+    uint32_t grid = c.grid ? c.grid : nblk;
+    if (grid > nblk) grid = nblk;
+    if (a.n >= (1ull << 26)) return hipErrorInvalidValue;   // in-block offsets are 32-bit
+    const int xm = (VAR == 2) ? (int)c.exchange : XCH_BPERM;
+    const size_t lds = (size_t)2 * 64 * K * sizeof(uint32_t) + (xm == XCH_LDS ? 64 * sizeof(uint32_t) : 0);
+    if (lds > 65536) return hipErrorInvalidValue;   // the host keeps both tiles within 64 KiB
+    if constexpr (VAR == 2) {
+        if (xm == XCH_LDS)
+            hipLaunchKernelGGL((k_generate_pipe<VAR, T, K, NT, XCH_LDS>), dim3(grid), dim3(64), lds, st, a);
+        else if (xm == XCH_BPERM2)
+            hipLaunchKernelGGL((k_generate_pipe<VAR, T, K, NT, XCH_BPERM2>), dim3(grid), dim3(64), lds, st, a);
+        else
+            hipLaunchKernelGGL((k_generate_pipe<VAR, T, K, NT, XCH_BPERM>), dim3(grid), dim3(64), lds, st, a);
+    } else {
+        hipLaunchKernelGGL((k_generate_pipe<VAR, T, K, NT, XCH_BPERM>), dim3(grid), dim3(64), lds, st, a);
+    }
+    return hipGetLastError();
+}
+
+template <int VAR, typename T, int K, bool NT>
+hipError_t ilv_launch(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
+{
+    const int xm = (VAR == 2) ? (int)c.exchange : XCH_BPERM;
+    const size_t lds = (size_t)K * c.block * sizeof(uint32_t) + (xm == XCH_LDS ? (size_t)c.block * sizeof(uint32_t) : 0);
+    if (lds > 65536 || a.ns % 4u) return hipErrorInvalidValue;
+    const uint32_t grid = (a.ns + c.block - 1) / c.block;
+#define ILV(B, X) hipLaunchKernelGGL((k_generate_ilv<VAR, T, K, B, NT, X>), dim3(grid), dim3(B), lds, st, a)
+#define ILVB(X)                                                      \
+    switch (c.block) {                                               \
+    case 256: ILV(256, X); break;                                    \
+    case 512: if constexpr (K <= 32) { ILV(512, X); break; } return hipErrorInvalidValue;   \
+    case 1024: if constexpr (K <= 16) { ILV(1024, X); break; } return hipErrorInvalidValue; \
+    default: return hipErrorInvalidValue;                            \
+    }
+    if constexpr (VAR == 2) {
+        if (xm == XCH_LDS) { ILVB(XCH_LDS) }
+        else { ILVB(XCH_BPERM) }
+    } else {
+        ILVB(XCH_BPERM)
+    }
+#undef ILVB
+#undef ILV
+    return hipGetLastError();
+}
+
 template <int VAR, typename T, int K>
 hipError_t gen_by_mode(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
 {
@@ -824,6 +1067,10 @@ hipError_t gen_by_mode(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
     case ST_LDS_NT: if constexpr (K >= 16) return tile_by_slots<VAR, T, K, true>(a, c, st); break;
     case ST_INTERLEAVED: if constexpr (small) return gen_launch<VAR, T, K, ST_INTERLEAVED>(a, c, st); break;
     case ST_GENERIC: if constexpr (small) return gen_launch<VAR, T, K, ST_GENERIC>(a, c, st); break;
+    case ST_ILV_TILE: if constexpr (K >= 8 && K <= 64) return ilv_launch<VAR, T, K, false>(a, c, st); break;
+    case ST_ILV_TILE_NT: if constexpr (K >= 8 && K <= 64) return ilv_launch<VAR, T, K, true>(a, c, st); break;
+    case ST_PIPE: if constexpr (K >= 16 && K <= 128) return pipe_launch<VAR, T, K, false>(a, c, st); break;
+    case ST_PIPE_NT: if constexpr (K >= 16 && K <= 128) return pipe_launch<VAR, T, K, true>(a, c, st); break;
     default: break;
     }
     return hipErrorInvalidValue;
@@ -833,7 +1080,8 @@ template <int VAR, typename T>
 hipError_t gen_by_unroll(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
 {
     // Modes that need K <= 32 fall back to K = 32 when a larger K is asked.
-    const bool lds_mode = c.store == ST_LDS || c.store == ST_LDS_NT;
+    const bool lds_mode = c.store == ST_LDS || c.store == ST_LDS_NT || c.store == ST_PIPE || c.store == ST_PIPE_NT ||
+                          c.store == ST_ILV_TILE || c.store == ST_ILV_TILE_NT;
     const uint32_t k = (!lds_mode && c.unroll > 32) ? 32 : c.unroll;
     switch (k) {
     case 8: return gen_by_mode<VAR, T, 8>(a, c, st);
@@ -863,7 +1111,8 @@ hipError_t consume_by_unroll(const GenArgs &a, const LaunchCfg &c, hipStream_t s
 
 hipError_t launch_generate(const GenArgs &a, int variant, int w32, const LaunchCfg &c, hipStream_t st)
 {
-    if (c.block == 0 || c.block % 64 != 0 || c.block > 256) return hipErrorInvalidValue;
+    const uint32_t max_block = (c.store == ST_ILV_TILE || c.store == ST_ILV_TILE_NT) ? 1024u : 256u;
+    if (c.block == 0 || c.block % 64 != 0 || c.block > max_block) return hipErrorInvalidValue;
     switch (variant) {
     case 0: return gen_by_unroll<0, uint32_t>(a, c, st);
     case 1: return w32 ? gen_by_unroll<1, uint32_t>(a, c, st) : gen_by_unroll<1, uint64_t>(a, c, st);
@@ -888,7 +1137,7 @@ hipError_t launch_segments(const SegArgs &a, uint32_t grid, uint32_t block, uint
     if (grid == 0) return hipErrorInvalidValue;
     if (store == ST_LDS || store == ST_LDS_NT) {
         const bool nt = store == ST_LDS_NT;
-        const size_t lds = (size_t)64 * a.unroll * 4 + 64 * 16;
+        const size_t lds = (size_t)64 * a.unroll * 4 + 64 * 12;
 #define SEG_TILE(K)                                                                              \
     do {                                                                                         \
         if (nt) hipLaunchKernelGGL((k_segments_tile<K, true>), dim3(grid), dim3(64), lds, st, a);  \
@@ -898,7 +1147,7 @@ hipError_t launch_segments(const SegArgs &a, uint32_t grid, uint32_t block, uint
         case 32: SEG_TILE(32); break;
         case 64: SEG_TILE(64); break;
         case 128: SEG_TILE(128); break;
-        case 256: return hipErrorInvalidValue;          // 64 KiB tile + metadata exceeds 64 KiB
+        case 256: return hipErrorInvalidValue;          // 64 KiB tile + row data exceeds 64 KiB
         default: return hipErrorInvalidValue;
         }
 #undef SEG_TILE

@@ -17,7 +17,11 @@ enum StoreMode : int {
     ST_DIRECT_NT = 3,     // as ST_DIRECT with non-temporal stores
     ST_LDS_NT = 4,        // as ST_LDS with non-temporal stores
     ST_INTERLEAVED = 5,   // out[i * n_streams + s], one dword per lane
-    ST_GENERIC = 6        // any alignment / length: one dword per output
+    ST_GENERIC = 6,       // any alignment / length: one dword per output
+    ST_PIPE = 7,          // persistent waves, double-buffered LDS tiles, stores overlapped
+    ST_PIPE_NT = 8,       // as ST_PIPE with non-temporal stores
+    ST_ILV_TILE = 9,      // interleaved layout through a K x block LDS tile, 16-byte stores
+    ST_ILV_TILE_NT = 10   // as ST_ILV_TILE with non-temporal stores
 };
 
 // Neighbour-exchange implementations of the V2 variant (tiled kernel).
@@ -46,6 +50,7 @@ struct LaunchCfg {
     uint32_t lds_bytes;    // LDS modes: dynamic LDS per block (>= the tile; more caps occupancy)
     uint32_t slots;        // LDS modes: streams per lane (1, 2 or 4)
     uint32_t exchange;     // V2, LDS modes: ExchangeMode
+    uint32_t grid;         // ST_PIPE modes: persistent workgroups (0: one per 64 streams)
 };
 
 // variant: 0 V0, 1 V1 (w32 selects 32-bit words), 2 V2.

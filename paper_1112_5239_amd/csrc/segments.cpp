@@ -131,9 +131,11 @@ void normalize(SegCfg &c)
 SegCfg resolve_seg_cfg(const cprng_t *h, uint64_t total, uint64_t max_len)
 {
     // Default measured on MI355X for 4,096 streams of 1e3..1e7 outputs:
-    // per-lane stores, 2048-output chunks (a wave's 64 chunks then span
-    // 512 KiB of the output), one persistent wave per SIMD.
-    SegCfg c{2048, 16, 4, 256, ST_DIRECT};
+    // LDS-tiled stores of K = 32 outputs per row and round, 2048-output
+    // chunks (a wave's 64 chunks then span 512 KiB of the output), two
+    // persistent waves per CU: fewer rows written at once keeps the set of
+    // open DRAM pages small, which outweighs the lost VALU parallelism.
+    SegCfg c{2048, 32, 2, 64, ST_LDS};
     TuneEntry e;
     if (tune_cache_lookup_key(tune_key_ragged(h, total, max_len), &e)) {
         if (e.chunk) c.chunk = e.chunk;
@@ -146,7 +148,15 @@ SegCfg resolve_seg_cfg(const cprng_t *h, uint64_t total, uint64_t max_len)
     if (h->tuning.waves_per_cu) c.waves = h->tuning.waves_per_cu;
     if (h->tuning.unroll) c.unroll = h->tuning.unroll;
     if (h->tuning.block) c.block = h->tuning.block;
-    if (h->tuning.store) c.store = h->tuning.store == ST_DIRECT_NT ? (uint32_t)ST_DIRECT : h->tuning.store;
+    if (h->tuning.store) {
+        // the chunk kernels are persistent already: pipelined modes map to LDS tiles
+        switch (h->tuning.store) {
+        case ST_DIRECT_NT: c.store = ST_DIRECT; break;
+        case ST_PIPE: c.store = ST_LDS; break;
+        case ST_PIPE_NT: c.store = ST_LDS_NT; break;
+        default: c.store = h->tuning.store; break;
+        }
+    }
     normalize(c);
     return c;
 }
@@ -398,12 +408,12 @@ extern "C" int cprng_autotune_ragged(cprng_t *h, uint32_t *out, const uint64_t *
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return set_error(CPRNG_E_HIP, "hipEventCreate");
     const uint32_t chunks[] = {1024, 2048, 4096, 8192, 16384};
-    const uint32_t waves[] = {2, 4, 8};
+    const uint32_t waves[] = {1, 2, 3, 4, 8};
     // (store, unroll, block): per-lane stores and LDS tiles of several widths
-    const uint32_t modes[][3] = {{ST_DIRECT, 16, 256}, {ST_DIRECT, 32, 256}, {ST_DIRECT, 16, 64},
-                                 {ST_LDS, 64, 64}, {ST_LDS, 128, 64}, {ST_LDS_NT, 128, 64}};
+    const uint32_t modes[][3] = {{ST_DIRECT, 16, 256}, {ST_DIRECT, 32, 256}, {ST_LDS, 32, 64},
+                                 {ST_LDS, 64, 64}, {ST_LDS, 128, 64}, {ST_LDS_NT, 32, 64}};
     float best = 1e30f;
-    SegCfg best_c{2048, 16, 4, 256, ST_DIRECT};
+    SegCfg best_c = resolve_seg_cfg(h, total, max_len);
     const bool saved_timing = h->timing;
     h->timing = false;
     for (uint32_t ch : chunks)

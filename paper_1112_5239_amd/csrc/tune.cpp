@@ -101,6 +101,7 @@ LaunchCfg default_cfg(uint32_t variant, bool w32, bool consume)
     c.lds_bytes = 0;
     c.slots = e.slots ? e.slots : 1;
     c.exchange = e.exchange ? e.exchange : (uint32_t)XCH_BPERM;
+    c.grid = 0;
     return c;
 }
 
@@ -108,8 +109,8 @@ TuneEntry default_entry(uint32_t variant, bool consume)
 {
     // Measured on MI355X at 2^20 streams x 1024 outputs (see profiles/):
     // V0 prefers long rows per round (K = 128) with non-temporal stores; V2's
-    // exchange chain needs the occupancy of smaller tiles (K = 32); V1 is
-    // VALU-bound and takes K = 64.
+    // exchange chain needs the occupancy of smaller tiles (K = 32) and reads
+    // its neighbours' words from an LDS copy; V1 is VALU-bound and takes K = 64.
     TuneEntry e;
     e.slots = 1;
     e.exchange = XCH_BPERM;
@@ -121,7 +122,7 @@ TuneEntry default_entry(uint32_t variant, bool consume)
         e.block = 256; e.unroll = 64; e.store = ST_LDS_NT; e.waves = 3;
         break;
     default:
-        e.block = 128; e.unroll = 32; e.store = ST_LDS; e.waves = 0;
+        e.block = 128; e.unroll = 32; e.store = ST_LDS; e.waves = 0; e.exchange = XCH_LDS;
         break;
     }
     if (consume) {

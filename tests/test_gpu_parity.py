@@ -74,6 +74,26 @@ def test_lds_tiles_and_occupancy_caps(orc, G, unroll, block, waves, slots):
                                streams_per_lane=slots))
 
 
+@pytest.mark.parametrize("store", [7, 8])
+@pytest.mark.parametrize("unroll", [16, 32, 64, 128])
+def test_pipelined_persistent_modes(orc, G, store, unroll):
+    # One persistent wave per CU over ~40k streams: each workgroup takes
+    # several 64-stream blocks in turn, the last block is partial, and
+    # n = 1000 leaves a tail after the pipelined rounds.
+    for name, variant in (("v0", 0), ("v2", 2), ("v1", 1)):
+        ns = 40032 if variant == 2 else 40037
+        _gen_check(orc, G, name, variant, ns, 1000, sigma=21,
+                   tuning=dict(store=store, unroll=unroll, waves_per_cu=1))
+
+
+@pytest.mark.parametrize("exchange", [1, 2, 3])
+@pytest.mark.parametrize("n", [4, 1024, 1000])
+def test_pipelined_v2_exchange_modes(orc, G, exchange, n):
+    # n = 4: no full round (per-lane path only); 1024: rounds only.
+    _gen_check(orc, G, "v2", 2, 20480, n, sigma=22, calls=2,
+               tuning=dict(store=7, unroll=64 if exchange != 2 else 32, waves_per_cu=2, exchange=exchange))
+
+
 @pytest.mark.parametrize("w32", [False, True])
 def test_v1_naive3_1024x1024(orc, G, w32):
     _gen_check(orc, G, "v1", 1, 1024, 1024, sigma=0, w32=w32)
@@ -159,6 +179,53 @@ def test_interleaved_layout(orc, G, variant_name, variant):
         got = G.as_u32(g.generate(n))
         assert got.shape == (n, ns)
         want, _ = orc.generate(variant, _oracle_states(orc, variant, 8, ns), n)
+        assert np.array_equal(got.T, want)
+    finally:
+        g.close()
+
+
+def _ilv_check(orc, G, variant_name, variant, ns, n, sigma, tuning=None, calls=2):
+    g = G.Generator(ns, variant_name, seed=sigma, interleaved=True)
+    try:
+        if tuning:
+            g.set_tuning(**tuning)
+        st = _oracle_states(orc, variant, sigma, ns)
+        for _ in range(calls):
+            got = G.as_u32(g.generate(n))
+            assert got.shape == (n, ns)
+            want, _ = orc.generate(variant, st, n)
+            bad = np.argwhere(got.T != want)
+            assert bad.size == 0, f"first mismatch (stream, step) at {bad[:3].tolist()}"
+        assert np.array_equal(g.get_state(), st), "end state differs"
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("store", [2, 4, 1])
+@pytest.mark.parametrize("block,unroll", [(256, 64), (512, 32), (1024, 16), (1024, 8), (256, 8)])
+def test_interleaved_tiles(orc, G, store, block, unroll):
+    # 3008 streams: a partial last tile (whole V2 groups); n = 1003: rounds
+    # plus a tail of single steps; two calls continue the streams.
+    for name, variant in (("v0", 0), ("v2", 2), ("v1", 1)):
+        _ilv_check(orc, G, name, variant, 3008, 1003, sigma=23,
+                   tuning=dict(store=store, block=block, unroll=unroll))
+
+
+@pytest.mark.parametrize("exchange", [1, 2])
+def test_interleaved_tiles_v2_exchange(orc, G, exchange):
+    _ilv_check(orc, G, "v2", 2, 4096, 512, sigma=24, tuning=dict(exchange=exchange, block=512, unroll=16))
+
+
+def test_interleaved_fallbacks(orc, G, torch):
+    # n_streams % 4 != 0 and a misaligned output select the per-lane kernel.
+    _ilv_check(orc, G, "v0", 0, 1001, 100, sigma=25)
+    g = G.Generator(1024, "v0", seed=26, interleaved=True)
+    try:
+        buf = torch.empty(1024 * 64 + 1, dtype=torch.int32, device="cuda")
+        view = buf[1:]
+        g.generate(64, out=view)
+        want, _ = orc.generate(0, _oracle_states(orc, 0, 26, 1024), 64)
+        got = G.as_u32(view).reshape(64, 1024)
         assert np.array_equal(got.T, want)
     finally:
         g.close()
