@@ -3,16 +3,20 @@
 
 One step = one cprng_generate call of the paper-shaped workload: the
 neighbour-exchange variant (Algorithm 4) on 2^20 streams x 1,024 uint32
-outputs (4 GiB written to HBM), states seeded from SplitMix64 with seed 1 and
-already resident on the device.  Prints ONE JSON line.
+outputs (4 GiB written to HBM), in the interleaved layout out[i * 2^20 + s]
+(the collision-free reading of the paper's store index with NumThreads the
+number of threads), states seeded from SplitMix64 with seed 1 and already
+resident on the device.  Prints ONE JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extra] [--no-cpu-baseline]
     python bench.py --workload serving [--duration 60]
 
-Secondary measurements (same JSON line, "extra"): plain variants V0 and V1 at
-the same shape, batched uneven streams (4,096 streams, log-uniform lengths in
-[1e3, 1e7], one hipGraph launch), in-kernel consumption (2^36 numbers), and
-the store-only fill probe.
+Secondary measurements (same JSON line, "extra"): the same workload in the
+stream-major layout out[s * 1024 + i], the plain variants V0 and V1 in both
+layouts, batched uneven streams (4,096 streams, log-uniform lengths in
+[1e3, 1e7], one hipGraph launch), in-kernel consumption (2^36 numbers) against
+its instruction-mix ALU roofline, the VALU issue-rate probes and the store-only
+fill probe.
 """
 import argparse
 import hashlib
@@ -27,7 +31,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-VALU_INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CU x 64 lanes/clk x 2.4 GHz = 39.3 Tops/s
+CU, CLOCK_HZ = 256, 2.4e9      # MI355X compute units, peak engine clock
+# VALU lanes per CU per clock by instruction class on gfx950: xor/add/
+# f32 mul/add issue two wave64 instructions per CU-clock (the rate behind the
+# published 157.3 TFLOP/s fp32 vector peak), 32-bit shifts one.
+LANES_FAST, LANES_SHIFT = 128, 64
+# VALU instructions per generated number in the consumption kernels' loop
+# (gfx950 code object of cprng_kernels.hip, unroll 16): shift-class
+# (v_lshlrev/v_lshrrev) and everything else.
+CONSUME_MIX = {"v0": (71 / 16, 162 / 16), "v2": (71 / 16, 194 / 16)}
 
 
 def log(msg):
@@ -96,12 +108,15 @@ def cpu_baseline_paper(budget_s=12.0):
                       f"{elapsed:.1f} s of single-thread CPU time"}
 
 
-def run_paper(torch, G, L, args):
+def run_paper(torch, G, L, args, interleaved, steps=None, warmup=None):
     ns, n = 1 << 20, 1024
-    log(f"[bench] paper workload: V2, {ns} streams x {n}, seed 1")
-    g = G.Generator(ns, "v2", seed=1)
-    out = torch.empty((ns, n), dtype=torch.int32, device="cuda")
-    ms, wall = timed(torch, lambda: g.generate(n, out=out), args.steps, args.warmup)
+    log(f"[bench] paper workload: V2, {ns} streams x {n}, seed 1, "
+        f"{'interleaved' if interleaved else 'stream-major'} layout")
+    g = G.Generator(ns, "v2", seed=1, interleaved=interleaved)
+    shape = (n, ns) if interleaved else (ns, n)
+    out = torch.empty(shape, dtype=torch.int32, device="cuda")
+    ms, wall = timed(torch, lambda: g.generate(n, out=out), steps or args.steps,
+                     args.warmup if warmup is None else warmup)
     numbers = ns * n
     alg_bytes = numbers * 4 + ns * 6 * 4 * 2
     achieved = alg_bytes / (ms / 1e3) / 1e9
@@ -110,22 +125,25 @@ def run_paper(torch, G, L, args):
     return ms, wall, numbers, alg_bytes, achieved
 
 
-def run_plain(torch, G, variant, args):
+def run_plain(torch, G, variant, args, interleaved=False):
     ns, n = 1 << 20, 1024
     words = {"v0": 5, "v1": 23}[variant]
-    g = G.Generator(ns, variant, seed=1)
-    out = torch.empty((ns, n), dtype=torch.int32, device="cuda")
+    g = G.Generator(ns, variant, seed=1, interleaved=interleaved)
+    shape = (n, ns) if interleaved else (ns, n)
+    out = torch.empty(shape, dtype=torch.int32, device="cuda")
     ms, _ = timed(torch, lambda: g.generate(n, out=out), max(5, args.steps // 2), 2)
     g.close()
     del out
     gn = ns * n / (ms / 1e3) / 1e9
     byts = ns * n * 4 + ns * words * 8
-    return {"workload": f"{variant}: 2^20 streams x 1024, seed 1", "ms": round(ms, 4),
-            "gnumbers_per_s": round(gn, 2), "hbm_gbs": round(byts / (ms / 1e3) / 1e9, 1),
+    return {"workload": f"{variant}: 2^20 streams x 1024, seed 1, "
+                        f"{'interleaved' if interleaved else 'stream-major'} layout",
+            "ms": round(ms, 4), "gnumbers_per_s": round(gn, 2), "hbm_gbs": round(byts / (ms / 1e3) / 1e9, 1),
             "frac_hbm_peak": round(byts / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def run_ragged(torch, G, args, ref_v0_gn):
+    """Ratio is against plain V0 in the same (stream-major) layout."""
     from paper_1112_5239_amd import workloads
     lengths = workloads.ragged_lengths()
     ns = lengths.size
@@ -145,18 +163,37 @@ def run_ragged(torch, G, args, ref_v0_gn):
             "ratio_to_plain_v0": round(gn / ref_v0_gn, 4) if ref_v0_gn else None}
 
 
+def run_valu_probes(torch, L):
+    """Issue rates (wave64 instructions per CU per clock at the peak clock) of
+    the three probe classes, with every CU holding its full complement of waves."""
+    n_threads, iters = 1 << 21, 1024
+    out = torch.empty(n_threads, dtype=torch.int32, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    res = {}
+    for kind, name in ((0, "xor"), (1, "shift"), (2, "f32_mul_add")):
+        ms, _ = timed(torch, lambda: L.cprng_probe_valu(kind, out, n_threads, iters, st), 3, 1)
+        rate = n_threads / 64 * iters * 32 / (ms / 1e3)
+        res[name] = round(rate / CU / CLOCK_HZ, 3)
+    del out
+    return {"unit": "wave64 instructions per CU per clock at 2.4 GHz", **res,
+            "peak_fast": LANES_FAST / 64, "peak_shift": LANES_SHIFT / 64}
+
+
 def run_consume(torch, G, args):
     ns, n = 1 << 20, 1 << 16
     res = {}
-    for variant, ops in (("v2", 15.5), ("v0", 13.5)):
+    for variant in ("v2", "v0"):
         g = G.Generator(ns, variant, seed=3)
         counts = torch.empty(ns, dtype=torch.int64, device="cuda")
         ms, _ = timed(torch, lambda: g.consume_qc(n, counts=counts), 3, 1)
         g.close()
         gn = ns * n / (ms / 1e3) / 1e9
+        n_shift, n_fast = CONSUME_MIX[variant]
+        peak = CU * CLOCK_HZ / (n_shift / LANES_SHIFT + n_fast / LANES_FAST) / 1e9
         res[variant] = {"ms": round(ms, 3), "gnumbers_per_s": round(gn, 1),
-                        "valu_ops_per_number": ops,
-                        "frac_valu_peak": round(gn * 1e9 * ops / (VALU_INT32_PEAK_TOPS * 1e12), 4)}
+                        "valu_instr_per_number": {"shift": round(n_shift, 3), "other": round(n_fast, 3)},
+                        "roofline": {"bound": "alu", "achieved": round(gn, 1), "peak": round(peak, 1),
+                                     "unit": "Gnumbers/s", "frac": round(gn / peak, 4)}}
     return {"workload": "2^36 uint32 (2^20 streams x 2^16) -> quarter-circle hit counts, seed 3", **res}
 
 
@@ -201,7 +238,7 @@ def main():
         print(json.dumps(res), flush=True)
         return
 
-    ms, wall, numbers, alg_bytes, achieved = run_paper(torch, G, L, args)
+    ms, wall, numbers, alg_bytes, achieved = run_paper(torch, G, L, args, interleaved=True)
     if args.copy_probe:
         n_words = 1 << 28
         src = torch.zeros(n_words, dtype=torch.int32, device="cuda")
@@ -215,14 +252,23 @@ def main():
     log(f"[bench] paper: {ms:.4f} ms/step, {value:.1f} Gnumbers/s, {achieved:.0f} GB/s")
     extra = {}
     if not args.no_extra:
-        extra["v0_plain"] = run_plain(torch, G, "v0", args)
-        log(f"[bench] v0: {extra['v0_plain']}")
-        extra["v1_naive3"] = run_plain(torch, G, "v1", args)
-        log(f"[bench] v1: {extra['v1_naive3']}")
-        extra["ragged"] = run_ragged(torch, G, args, extra["v0_plain"]["gnumbers_per_s"])
+        sm_ms, _, _, sm_bytes, sm_ach = run_paper(torch, G, L, args, interleaved=False,
+                                                  steps=max(5, args.steps // 2), warmup=2)
+        extra["v2_stream_major"] = {"workload": "the same run in the stream-major layout out[s * 1024 + i]",
+                                    "ms": round(sm_ms, 4), "gnumbers_per_s": round(numbers / (sm_ms / 1e3) / 1e9, 2),
+                                    "hbm_gbs": round(sm_ach, 1), "frac_hbm_peak": round(sm_ach / HBM_PEAK_GBS, 4)}
+        log(f"[bench] v2 stream-major: {extra['v2_stream_major']}")
+        for variant in ("v0", "v1"):
+            for ilv in (True, False):
+                key = f"{variant}_{'interleaved' if ilv else 'stream_major'}"
+                extra[key] = run_plain(torch, G, variant, args, interleaved=ilv)
+                log(f"[bench] {key}: {extra[key]}")
+        extra["ragged"] = run_ragged(torch, G, args, extra["v0_stream_major"]["gnumbers_per_s"])
         log(f"[bench] ragged: {extra['ragged']}")
         extra["consume"] = run_consume(torch, G, args)
         log(f"[bench] consume: {extra['consume']}")
+        extra["valu_probe"] = run_valu_probes(torch, L)
+        log(f"[bench] valu probe: {extra['valu_probe']}")
         extra["fill_probe"] = run_fill_probe(torch, L)
         log(f"[bench] fill probe: {extra['fill_probe']}")
     cpu = None
@@ -243,11 +289,12 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "paper-shaped neighbour-exchange variant (Algorithm 4): 2^20 streams "
-                               "x 1024 uint32 outputs (4 GiB), SplitMix64 seed 1, group 32",
-                   "n_streams": 1 << 20, "n_per_stream": 1024, "variant": "v2"},
+                               "x 1024 uint32 outputs (4 GiB), SplitMix64 seed 1, group 32, interleaved "
+                               "layout out[i * 2^20 + s]",
+                   "n_streams": 1 << 20, "n_per_stream": 1024, "variant": "v2", "layout": "interleaved"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profile("k_generate_v2_paper"),
+                     "traffic": traffic_from_profile("k_generate_ilv_v2_paper"),
                      "algorithmic_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "extra": extra,

@@ -99,7 +99,7 @@ def lib():
         "cprng_last_kernel_ms": (C.c_double, [vp]),
         "cprng_probe_fill": (i32, [vp, u64, u32, vp]),
         "cprng_probe_copy": (i32, [vp, vp, u64, vp]),
-        "cprng_probe_valu": (i32, [vp, u32, u32, vp]),
+        "cprng_probe_valu": (i32, [u32, vp, u32, u32, vp]),
         "cprng_strerror": (C.c_char_p, [i32]),
         "cprng_last_error": (C.c_char_p, []),
         "cprng_now_ns": (u64, []),
@@ -261,8 +261,8 @@ def cprng_probe_copy(dst, src, n_words: int, stream=None) -> None:
     _check(lib().cprng_probe_copy(_addr(dst), _addr(src), n_words, _addr(stream)), "cprng_probe_copy")
 
 
-def cprng_probe_valu(out, n_threads: int, iters: int, stream=None) -> None:
-    _check(lib().cprng_probe_valu(_addr(out), n_threads, iters, _addr(stream)), "cprng_probe_valu")
+def cprng_probe_valu(kind: int, out, n_threads: int, iters: int, stream=None) -> None:
+    _check(lib().cprng_probe_valu(kind, _addr(out), n_threads, iters, _addr(stream)), "cprng_probe_valu")
 
 
 def cprng_strerror(status: int) -> str:

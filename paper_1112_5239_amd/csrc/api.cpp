@@ -157,10 +157,12 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
     }
     if (!consume && (h->flags & CPRNG_F_INTERLEAVED)) {
         // Interleaved layout: LDS tiles of K steps x block streams (measured
-        // on MI355X: 1,024 streams x 16 steps, 4 KiB contiguous per step);
-        // direct store modes select the per-lane dword kernel.
-        LaunchCfg c{1024, 16, ST_ILV_TILE, 0, 1, XCH_BPERM, 0};
+        // on MI355X at 2^20 streams x 1024: 256 streams x 64 steps with
+        // non-temporal stores; wider tiles were slower); direct store modes
+        // select the per-lane dword kernel.
+        LaunchCfg c{256, 64, ST_ILV_TILE_NT, 0, 1, XCH_BPERM, 0};
         if (h->tuning.store == ST_DIRECT || h->tuning.store == ST_DIRECT_NT) c.store = ST_INTERLEAVED;
+        if (h->tuning.store == ST_LDS || h->tuning.store == ST_PIPE) c.store = ST_ILV_TILE;
         if (h->tuning.store == ST_LDS_NT || h->tuning.store == ST_PIPE_NT) c.store = ST_ILV_TILE_NT;
         if (h->tuning.block) c.block = h->tuning.block;
         if (h->tuning.unroll) c.unroll = h->tuning.unroll;
@@ -445,10 +447,11 @@ int cprng_probe_copy(uint32_t *dst, const uint32_t *src, uint64_t n_words, cprng
     return CPRNG_OK;
 }
 
-int cprng_probe_valu(uint32_t *out, uint32_t n_threads, uint32_t iters, cprng_stream_t stream)
+int cprng_probe_valu(uint32_t kind, uint32_t *out, uint32_t n_threads, uint32_t iters, cprng_stream_t stream)
 {
     if (!out || n_threads == 0 || n_threads % 256) return set_error(CPRNG_E_INVAL, "n_threads must be a positive multiple of 256");
-    HIP_TRY(launch_valu_probe(out, n_threads, iters, (hipStream_t)stream), "VALU probe launch");
+    if (kind > 2) return set_error(CPRNG_E_INVAL, "kind must be 0 (xor), 1 (shift) or 2 (f32 mul/add)");
+    HIP_TRY(launch_valu_probe(kind, out, n_threads, iters, (hipStream_t)stream), "VALU probe launch");
     return CPRNG_OK;
 }
 

@@ -938,21 +938,38 @@ __global__ __launch_bounds__(256) void k_copy(uint32_t *dst, const uint32_t *src
     }
 }
 
-// VALU issue-rate probe: 8 independent xor/shift chains per lane, 4 VALU
-// instructions per chain per iteration (shift, xor, shift, xor), so one
-// iteration is 32 VALU instructions per lane.
+// VALU issue-rate probe: each iteration issues 32 instructions of one class
+// on 8 registers per lane, ordered (inline assembly, so the compiler keeps
+// the order) so that every instruction depends only on one issued four or
+// more instructions earlier.  KIND 0: v_xor_b32; 1: v_lshlrev_b32; 2:
+// v_mul_f32 / v_add_f32.  On gfx950 the classes issue at different rates,
+// which the ALU roofline of the consumption kernel is weighted by.
+#define CPRNG_PROBE_ROUND(OP)                                                              \
+    OP " %0, %0, %1\n" OP " %2, %2, %3\n" OP " %4, %4, %5\n" OP " %6, %6, %7\n"            \
+    OP " %1, %1, %2\n" OP " %3, %3, %4\n" OP " %5, %5, %6\n" OP " %7, %7, %0\n"
+template <int KIND>
 __global__ __launch_bounds__(256) void k_valu_probe(uint32_t *out, uint32_t iters)
 {
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t a0 = gid, a1 = gid + 1, a2 = gid + 2, a3 = gid + 3, a4 = gid + 4, a5 = gid + 5, a6 = gid + 6,
              a7 = gid + 7;
     for (uint32_t i = 0; i < iters; ++i) {
-#define XS(a) a ^= a << 7; a ^= a >> 9;
-        XS(a0) XS(a1) XS(a2) XS(a3) XS(a4) XS(a5) XS(a6) XS(a7)
-#undef XS
+        if constexpr (KIND == 0)
+            asm volatile(CPRNG_PROBE_ROUND("v_xor_b32") CPRNG_PROBE_ROUND("v_xor_b32")
+                         CPRNG_PROBE_ROUND("v_xor_b32") CPRNG_PROBE_ROUND("v_xor_b32")
+                         : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7));
+        else if constexpr (KIND == 1)
+            asm volatile(CPRNG_PROBE_ROUND("v_lshlrev_b32") CPRNG_PROBE_ROUND("v_lshlrev_b32")
+                         CPRNG_PROBE_ROUND("v_lshlrev_b32") CPRNG_PROBE_ROUND("v_lshlrev_b32")
+                         : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7));
+        else
+            asm volatile(CPRNG_PROBE_ROUND("v_mul_f32") CPRNG_PROBE_ROUND("v_add_f32")
+                         CPRNG_PROBE_ROUND("v_mul_f32") CPRNG_PROBE_ROUND("v_add_f32")
+                         : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7));
     }
     out[gid] = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7;
 }
+#undef CPRNG_PROBE_ROUND
 
 __global__ void k_tail_words(uint32_t *dst, const uint32_t *src, uint64_t begin, uint64_t end, uint32_t value)
 {
@@ -1186,10 +1203,15 @@ static uint32_t probe_grid(uint64_t nq)
     return (uint32_t)(g ? g : 1);
 }
 
-hipError_t launch_valu_probe(uint32_t *out, uint32_t n_threads, uint32_t iters, hipStream_t st)
+hipError_t launch_valu_probe(uint32_t kind, uint32_t *out, uint32_t n_threads, uint32_t iters, hipStream_t st)
 {
     if (n_threads == 0 || n_threads % 256) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_valu_probe, dim3(n_threads / 256), dim3(256), 0, st, out, iters);
+    switch (kind) {
+    case 0: hipLaunchKernelGGL(k_valu_probe<0>, dim3(n_threads / 256), dim3(256), 0, st, out, iters); break;
+    case 1: hipLaunchKernelGGL(k_valu_probe<1>, dim3(n_threads / 256), dim3(256), 0, st, out, iters); break;
+    case 2: hipLaunchKernelGGL(k_valu_probe<2>, dim3(n_threads / 256), dim3(256), 0, st, out, iters); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

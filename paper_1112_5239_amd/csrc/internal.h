@@ -97,7 +97,7 @@ hipError_t launch_commit(uint32_t *state, const uint32_t *state_next, const uint
 hipError_t launch_zero_u32(uint32_t *p, uint32_t count, hipStream_t st);
 
 hipError_t launch_fill(uint32_t *dst, uint64_t n_words, uint32_t value, hipStream_t st);
-hipError_t launch_valu_probe(uint32_t *out, uint32_t n_threads, uint32_t iters, hipStream_t st);
+hipError_t launch_valu_probe(uint32_t kind, uint32_t *out, uint32_t n_threads, uint32_t iters, hipStream_t st);
 hipError_t launch_copy(uint32_t *dst, const uint32_t *src, uint64_t n_words, hipStream_t st);
 
 }  // namespace cprng_impl
