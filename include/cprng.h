@@ -209,7 +209,9 @@ typedef struct cprng_tuning {
     uint32_t waves_per_cu;     /* ragged/requests and pipelined generate: persistent
                                   waves per CU (0 = default);
                                   LDS-transposed generate: residency cap (0 = none) */
-    uint32_t streams_per_lane; /* LDS-transposed generate: 1, 2 or 4 streams per lane */
+    uint32_t streams_per_lane; /* LDS-transposed generate: 1, 2 or 4 streams per lane;
+                                  interleaved tiles: 2 = two tile buffers, so each
+                                  round's stores overlap the next round's steps */
     uint32_t exchange;         /* V2, LDS-transposed generate: 1 cross-lane reads,
                                   2 LDS word buffer, 3 two steps per read round */
     uint32_t reserved;

@@ -156,11 +156,18 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
         h->tuned_loaded = true;
     }
     if (!consume && (h->flags & CPRNG_F_INTERLEAVED)) {
-        // Interleaved layout: LDS tiles of K steps x block streams (measured
-        // on MI355X at 2^20 streams x 1024: 256 streams x 64 steps with
-        // non-temporal stores; wider tiles were slower); direct store modes
-        // select the per-lane dword kernel.
-        LaunchCfg c{256, 64, ST_ILV_TILE_NT, 0, 1, XCH_BPERM, 0};
+        // Interleaved layout: LDS tiles of K steps x block streams, spread
+        // over the XCDs in bands.  Measured on MI355X at 2^20 streams x 1024:
+        // 1,024 streams x 8 steps, two tile buffers, non-temporal stores, V2
+        // exchange by cross-lane reads; V1, VALU-bound, 256 x 32 with one
+        // buffer.  Direct store modes select the per-lane dword kernel.
+        LaunchCfg c{1024, 8, ST_ILV_TILE_NT, 0, 2, XCH_BPERM, 0};
+        if (h->variant == CPRNG_V1_NAIVE3) {
+            c.block = 256;
+            c.unroll = 32;
+            c.slots = 1;
+        }
+        if (h->tuning.streams_per_lane) c.slots = h->tuning.streams_per_lane;
         if (h->tuning.store == ST_DIRECT || h->tuning.store == ST_DIRECT_NT) c.store = ST_INTERLEAVED;
         if (h->tuning.store == ST_LDS || h->tuning.store == ST_PIPE) c.store = ST_ILV_TILE;
         if (h->tuning.store == ST_LDS_NT || h->tuning.store == ST_PIPE_NT) c.store = ST_ILV_TILE_NT;
@@ -219,11 +226,13 @@ int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchC
             c.block = b;
             if (c.unroll < 8) c.unroll = 8;
             if (c.unroll > 64) c.unroll = 64;
-            if (c.exchange < XCH_BPERM || c.exchange > XCH_LDS) c.exchange = XCH_BPERM;
+            if (c.exchange < XCH_BPERM || c.exchange > XCH_BPERM2) c.exchange = XCH_BPERM;
+            if (c.slots != 2) c.slots = 1;      // 2: double-buffered tiles
             const uint32_t extra = (h->variant == CPRNG_V2_SHMEM && c.exchange == XCH_LDS) ? 1u : 0u;
-            while ((uint64_t)(c.unroll + extra) * c.block * 4u > 65536u) {
+            while ((uint64_t)(c.slots * c.unroll + extra) * c.block * 4u > 65536u) {
                 if (c.unroll > 8) c.unroll /= 2;
-                else c.block /= 2;
+                else if (c.block > 256) c.block /= 2;
+                else c.slots = 1;
             }
         }
     } else {

@@ -298,6 +298,18 @@ __device__ __forceinline__ void gstore4(gu32 *p, uint32_t a, uint32_t b, uint32_
         *(gu32x4 *)p = v;
 }
 
+// Workgroup -> tile map for the 8 XCDs of the chip.  Workgroups are handed
+// to the XCDs round-robin (workgroup b runs on XCD b % 8); this bijection of
+// [0, nb) gives XCD x the contiguous run of tiles x*floor(nb/8) + min(x, nb%8)
+// ... , so each XCD's L2 and its stores sweep one band of the output in
+// order instead of every XCD touching every eighth tile.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb)
+{
+    const uint32_t x = b & 7u, local = b >> 3;
+    const uint32_t per = nb >> 3, extra = nb & 7u;
+    return x * per + (x < extra ? x : extra) + local;
+}
+
 // ------------------------------------------------------------------------
 // Plain generate kernel: one lane per stream, K outputs per lane per round.
 //   ST_DIRECT(_NT): lane stores its K outputs as K/4 aligned 16-byte quads.
@@ -379,7 +391,7 @@ __global__ __launch_bounds__(256) void k_generate_tile(GenArgs a)
     HIP_DYNAMIC_SHARED(uint32_t, lds);
     constexpr int QPR = K / 4;               // quads per row
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t wave = ((uint64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
     const uint64_t base = wave * 64u * S;
     uint32_t *tile = lds + (threadIdx.x >> 6) * (64 * S * K);
     // V2 with the LDS exchange: 64 words per slot after all tiles of the block.
@@ -549,23 +561,24 @@ __global__ __launch_bounds__(64) void k_generate_pipe(GenArgs a)
 // Each round every thread writes its next K outputs into column t of a K x B
 // LDS tile; row k of the tile is step i + k of B neighbouring streams, i.e.
 // 4B contiguous bytes of the output, and the rows are stored as 16-byte
-// quads, 64 consecutive quads (1 KiB) per store instruction.  Workgroups that
-// run together advance through the steps together, so the writes in flight
-// form a few long contiguous fronts.  Needs ns % 4 == 0 and a 16-byte
-// aligned output.
+// quads, 64 consecutive quads (1 KiB) per store instruction.  Tiles are
+// spread over the XCDs in bands (xcd_tile): the workgroups of one XCD run in
+// order over neighbouring tiles, so each XCD writes long contiguous fronts of
+// every step row.  Needs ns % 4 == 0 and a 16-byte aligned output.
 // ------------------------------------------------------------------------
-template <int VAR, typename T, int K, int B, bool NT, int XM>
+template <int VAR, typename T, int K, int B, bool NT, int XM, bool DB>
 __global__ __launch_bounds__(B) void k_generate_ilv(GenArgs a)
 {
     HIP_DYNAMIC_SHARED(uint32_t, lds);
     constexpr int QR = B / 4;                // quads per tile row
+    constexpr int NBUF = DB ? 2 : 1;         // DB: round r is generated while round r-1 is stored
     static_assert(B >= 256 && (B & (B - 1)) == 0 && K % 4 == 0, "B a power of two >= 256");
     const uint32_t t = threadIdx.x;
     const uint32_t lane = t & 63u;
     const uint64_t ns = a.ns;
-    const uint64_t base = (uint64_t)blockIdx.x * B;
+    const uint64_t base = (uint64_t)xcd_tile(blockIdx.x, gridDim.x) * B;
     const uint64_t s = base + t;
-    uint32_t *xb = lds + K * B + (t & ~63u); // V2 with the LDS exchange: 64 words per wave
+    uint32_t *xb = lds + NBUF * K * B + (t & ~63u);   // V2 with the LDS exchange: 64 words per wave
     Stream<VAR, T> st;
     if (s < ns) st.load(a, (uint32_t)s);
     else st = Stream<VAR, T>{};
@@ -575,24 +588,58 @@ __global__ __launch_bounds__(B) void k_generate_ilv(GenArgs a)
     const bool col_ok = base + 4u * cq < ns;
     const uint64_t n = a.n;
     gu32 *out = gptr((uint64_t)(uintptr_t)a.out) + base + 4u * cq;
+    auto gen4 = [&](uint32_t *buf, int k0) {   // steps k0 .. k0+3 into column t
+        uint32_t v[4];
+        if constexpr (XM == XCH_LDS) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = st.next_lds(xb, lane);
+        } else if constexpr (XM == XCH_BPERM2) {
+            st.next2(v[0], v[1]);
+            st.next2(v[2], v[3]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = st.next();
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) buf[(k0 + e) * B + t] = v[e];
+    };
+    auto put = [&](const uint32_t *buf, int j, uint64_t i) {   // rows 4j .. 4j+3 of the tile
+        const uint32_t row = 4u * j + r0;
+        uint32_t x0, x1, x2, x3;
+        load4(buf + row * B + 4u * cq, x0, x1, x2, x3);
+        if (col_ok) gstore4<NT>(out + (i + row) * ns, x0, x1, x2, x3);
+    };
     uint64_t i = 0;
-    for (; i + K <= n; i += K) {
+    if constexpr (DB) {
+        const uint64_t rounds = n / K;
+        if (rounds) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            uint32_t v;
-            if constexpr (XM == XCH_LDS) v = st.next_lds(xb, lane);
-            else v = st.next();
-            lds[k * B + t] = v;
-        }
-        __syncthreads();
+            for (int k = 0; k < K; k += 4) gen4(lds, k);
+            __syncthreads();
+            for (uint64_t r = 1; r < rounds; ++r) {
+                uint32_t *cur = lds + (r & 1u) * (K * B);
+                const uint32_t *prev = lds + ((r - 1) & 1u) * (K * B);
 #pragma unroll
-        for (int j = 0; j < K / 4; ++j) {
-            const uint32_t row = 4u * j + r0;
-            uint32_t x0, x1, x2, x3;
-            load4(lds + row * B + 4u * cq, x0, x1, x2, x3);
-            if (col_ok) gstore4<NT>(out + (i + row) * ns, x0, x1, x2, x3);
+                for (int j = 0; j < K / 4; ++j) {
+                    gen4(cur, 4 * j);
+                    put(prev, j, (r - 1) * K);
+                }
+                __syncthreads();
+            }
+            const uint32_t *last = lds + ((rounds - 1) & 1u) * (K * B);
+#pragma unroll
+            for (int j = 0; j < K / 4; ++j) put(last, j, (rounds - 1) * K);
+            i = rounds * K;
         }
-        __syncthreads();
+    } else {
+        for (; i + K <= n; i += K) {
+#pragma unroll
+            for (int k = 0; k < K; k += 4) gen4(lds, k);
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < K / 4; ++j) put(lds, j, i);
+            __syncthreads();
+        }
     }
     if (s < ns) {                            // whole V2 groups: present lanes read present lanes only
         for (; i < n; ++i) a.out[i * ns + s] = st.next();
@@ -684,6 +731,33 @@ __device__ __forceinline__ void jump_v0(X128 &g, uint32_t &x, const uint32_t *po
     x = a4;
 }
 
+// Work queues of the chunk kernels: one per XCD.  Queue x holds the
+// contiguous run of segments [lo(x), lo(x) + count(x)) (the split of
+// xcd_tile), its counter is a.counter[x]; a wave takes 64 segments at a time
+// from its own XCD's queue (workgroup b runs on XCD b % 8) and, once that is
+// empty, from the others in turn.  Each XCD thus writes one band of the
+// output in order.  Returns false when every queue is empty.
+__device__ __forceinline__ bool grab_segments(const SegArgs &a, uint32_t lane, uint32_t &qi, uint32_t &base,
+                                              uint32_t &end)
+{
+    const uint32_t per = a.nseg >> 3, extra = a.nseg & 7u;
+    while (qi < 8u) {
+        const uint32_t x = (blockIdx.x + qi) & 7u;
+        const uint32_t lo = x * per + (x < extra ? x : extra);
+        const uint32_t hi = lo + per + (x < extra ? 1u : 0u);
+        uint32_t off = 0;
+        if (lane == 0) off = atomicAdd(a.counter + x, 64u);
+        off = (uint32_t)__builtin_amdgcn_readfirstlane((int)off);
+        if (off < hi - lo) {
+            base = lo + off;
+            end = (hi - base) < 64u ? hi : base + 64u;
+            return true;
+        }
+        ++qi;
+    }
+    return false;
+}
+
 // Segment idx -> its run, position, length, head and jump polynomial.
 struct Seg {
     gu32 *out;             // first output of the segment
@@ -730,13 +804,10 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t ns = a.ns;
-    for (;;) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(a.counter, 64u);
-        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
-        if (base >= a.nseg) break;
+    uint32_t qi = 0, base = 0, end = 0;
+    while (grab_segments(a, lane, qi, base, end)) {
         const uint32_t idx = base + lane;
-        if (idx < a.nseg) {
+        if (idx < end) {
             const Seg d = decode_segment(a, idx);
             const uint32_t *p = a.state + d.stream;
             X128 g{p[0], p[ns], p[2 * ns], p[3 * ns]};
@@ -806,16 +877,13 @@ __global__ __launch_bounds__(64) void k_segments_tile(SegArgs a)
     const uint32_t q = lane % QPR;           // quad a lane stores
     const uint32_t rsub = lane / QPR;        // row within an instruction's RPI rows
     const uint64_t ns = a.ns;
-    for (;;) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(a.counter, 64u);
-        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
-        if (base >= a.nseg) break;
+    uint32_t qi = 0, base = 0, end = 0;
+    while (grab_segments(a, lane, qi, base, end)) {
         const uint32_t idx = base + lane;
         X128 g{0u, 0u, 0u, 0u};
         uint32_t x = 0, rem = 0, stream = 0, last = 0;
         uint64_t obase = 0;
-        if (idx < a.nseg) {
+        if (idx < end) {
             const Seg d = decode_segment(a, idx);
             const uint32_t *p = a.state + d.stream;
             g = X128{p[0], p[ns], p[2 * ns], p[3 * ns]};
@@ -1051,23 +1119,28 @@ template <int VAR, typename T, int K, bool NT>
 hipError_t ilv_launch(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
 {
     const int xm = (VAR == 2) ? (int)c.exchange : XCH_BPERM;
-    const size_t lds = (size_t)K * c.block * sizeof(uint32_t) + (xm == XCH_LDS ? (size_t)c.block * sizeof(uint32_t) : 0);
+    const bool db = c.slots == 2;            // interleaved tiles: slots = number of tile buffers
+    const size_t lds = (size_t)(db ? 2 : 1) * K * c.block * sizeof(uint32_t) +
+                       (xm == XCH_LDS ? (size_t)c.block * sizeof(uint32_t) : 0);
     if (lds > 65536 || a.ns % 4u) return hipErrorInvalidValue;
     const uint32_t grid = (a.ns + c.block - 1) / c.block;
-#define ILV(B, X) hipLaunchKernelGGL((k_generate_ilv<VAR, T, K, B, NT, X>), dim3(grid), dim3(B), lds, st, a)
-#define ILVB(X)                                                      \
+#define ILV(B, X, D) hipLaunchKernelGGL((k_generate_ilv<VAR, T, K, B, NT, X, D>), dim3(grid), dim3(B), lds, st, a)
+#define ILVB(X, D)                                                   \
     switch (c.block) {                                               \
-    case 256: ILV(256, X); break;                                    \
-    case 512: if constexpr (K <= 32) { ILV(512, X); break; } return hipErrorInvalidValue;   \
-    case 1024: if constexpr (K <= 16) { ILV(1024, X); break; } return hipErrorInvalidValue; \
+    case 256: ILV(256, X, D); break;                                 \
+    case 512: if constexpr (K <= 32) { ILV(512, X, D); break; } return hipErrorInvalidValue;   \
+    case 1024: if constexpr (K <= 16) { ILV(1024, X, D); break; } return hipErrorInvalidValue; \
     default: return hipErrorInvalidValue;                            \
     }
+#define ILVX(X) if (db) { ILVB(X, true) } else { ILVB(X, false) }
     if constexpr (VAR == 2) {
-        if (xm == XCH_LDS) { ILVB(XCH_LDS) }
-        else { ILVB(XCH_BPERM) }
+        if (xm == XCH_LDS) { ILVX(XCH_LDS) }
+        else if (xm == XCH_BPERM2) { ILVX(XCH_BPERM2) }
+        else { ILVX(XCH_BPERM) }
     } else {
-        ILVB(XCH_BPERM)
+        ILVX(XCH_BPERM)
     }
+#undef ILVX
 #undef ILVB
 #undef ILV
     return hipGetLastError();

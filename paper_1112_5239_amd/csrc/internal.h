@@ -85,7 +85,7 @@ struct SegArgs {
     uint32_t ns;           // streams (SoA stride)
     const uint32_t *state; // current states (read only during the launch)
     uint32_t *state_next;  // end states of runs with `last`
-    uint32_t *counter;     // work-queue counter (reset before each launch)
+    uint32_t *counter;     // work-queue counters, one per XCD (8 words, reset before each launch)
     uint32_t unroll;       // outputs per lane per round
 };
 

@@ -247,7 +247,7 @@ int build_plan(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
         return set_error(CPRNG_E_HIP, "hipStreamCreate (capture)");
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = launch_zero_u32(h->d_counter, 1, cs);
+    if (e == hipSuccess) e = launch_zero_u32(h->d_counter, 8, cs);
     if (e == hipSuccess && p->nseg) e = launch_segments(a, p->grid, c.block, c.store, cs);
     if (e == hipSuccess) e = launch_commit(h->d_state, h->d_state_next, p->d_ids, (uint32_t)ids.size(), h->ns, cs);
     hipGraph_t graph = nullptr;
@@ -614,7 +614,7 @@ extern "C" int cprng_generate_requests(cprng_t *h, const cprng_request_t *reqs, 
     for (size_t j = 0; j < launches.size() && e == hipSuccess; ++j) {
         const SegArgs a = seg_args(h, c, (const RunDesc *)(db + run_off[j]), (uint32_t)launches[j].runs.size(),
                                    launches[j].nseg, kcap, d_tab, slot->d_counter);
-        e = launch_zero_u32(slot->d_counter, 1, st);
+        e = launch_zero_u32(slot->d_counter, 8, st);
         if (e == hipSuccess) e = launch_segments(a, persistent_grid(h, c, a.nseg), c.block, c.store, st);
         if (e == hipSuccess)
             e = launch_commit(h->d_state, h->d_state_next, (const uint32_t *)(db + id_off[j]),

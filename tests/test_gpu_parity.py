@@ -211,9 +211,23 @@ def test_interleaved_tiles(orc, G, store, block, unroll):
                    tuning=dict(store=store, block=block, unroll=unroll))
 
 
-@pytest.mark.parametrize("exchange", [1, 2])
+@pytest.mark.parametrize("exchange", [1, 2, 3])
 def test_interleaved_tiles_v2_exchange(orc, G, exchange):
     _ilv_check(orc, G, "v2", 2, 4096, 512, sigma=24, tuning=dict(exchange=exchange, block=512, unroll=16))
+
+
+@pytest.mark.parametrize("block,unroll", [(1024, 8), (512, 16), (256, 32), (256, 8)])
+@pytest.mark.parametrize("exchange", [1, 2, 3])
+def test_interleaved_double_buffered_tiles(orc, G, block, unroll, exchange):
+    # Two tile buffers: each round's stores overlap the next round's steps;
+    # 5,024 streams leave a partial last tile, n = 1003 a tail, and a tile
+    # count that is not a multiple of 8 exercises the XCD band map.
+    _ilv_check(orc, G, "v2", 2, 5024, 1003, sigma=27,
+               tuning=dict(exchange=exchange, block=block, unroll=unroll, streams_per_lane=2, store=4))
+    if exchange == 1:
+        for name, variant in (("v0", 0), ("v1", 1)):
+            _ilv_check(orc, G, name, variant, 5024, 1003, sigma=27,
+                       tuning=dict(block=block, unroll=unroll, streams_per_lane=2, store=2))
 
 
 def test_interleaved_fallbacks(orc, G, torch):
