@@ -131,7 +131,7 @@ def run_plain(torch, G, variant, args, interleaved=False):
     g = G.Generator(ns, variant, seed=1, interleaved=interleaved)
     shape = (n, ns) if interleaved else (ns, n)
     out = torch.empty(shape, dtype=torch.int32, device="cuda")
-    ms, _ = timed(torch, lambda: g.generate(n, out=out), max(5, args.steps // 2), 2)
+    ms, _ = timed(torch, lambda: g.generate(n, out=out), max(5, args.steps // 2), 30)
     g.close()
     del out
     gn = ns * n / (ms / 1e3) / 1e9
@@ -152,7 +152,7 @@ def run_ragged(torch, G, args, ref_v0_gn):
     out = torch.empty(total, dtype=torch.int32, device="cuda")
     if args.autotune:
         g.autotune_ragged(lengths, out=out)
-    ms, _ = timed(torch, lambda: g.generate_ragged(lengths, out=out), max(5, args.steps // 4), 2)
+    ms, _ = timed(torch, lambda: g.generate_ragged(lengths, out=out), max(5, args.steps // 4), 10)
     g.close()
     del out
     gn = total / (ms / 1e3) / 1e9
@@ -209,8 +209,9 @@ def run_fill_probe(torch, L):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=50,
+                    help="untimed steps; the first ~50 launches after the GPU has been idle run slower")
     ap.add_argument("--workload", default="paper", choices=["paper", "serving"])
     ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     ap.add_argument("--no-extra", action="store_true")
@@ -253,7 +254,7 @@ def main():
     extra = {}
     if not args.no_extra:
         sm_ms, _, _, sm_bytes, sm_ach = run_paper(torch, G, L, args, interleaved=False,
-                                                  steps=max(5, args.steps // 2), warmup=2)
+                                                  steps=max(5, args.steps // 2), warmup=30)
         extra["v2_stream_major"] = {"workload": "the same run in the stream-major layout out[s * 1024 + i]",
                                     "ms": round(sm_ms, 4), "gnumbers_per_s": round(numbers / (sm_ms / 1e3) / 1e9, 2),
                                     "hbm_gbs": round(sm_ach, 1), "frac_hbm_peak": round(sm_ach / HBM_PEAK_GBS, 4)}

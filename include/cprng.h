@@ -197,18 +197,22 @@ int cprng_default_combs(uint32_t C, uint32_t *comb1, uint32_t *comb2);
  * CPRNG_F_INTERLEAVED take 0/2/7 (LDS tiles of unroll steps x block streams,
  * each step's block stored as one contiguous run; needs n_streams % 4 == 0 and
  * a 16-byte aligned output, else the per-lane path runs), 4/8 (the same,
- * non-temporal) or 1/3 (per-lane dword stores). */
+ * non-temporal) or 1/3 (per-lane dword stores).  The chunk kernels of
+ * cprng_generate_ragged / cprng_generate_requests take 1 (per-lane), 2/4
+ * (LDS tiles, persistent waves fed by one work queue per XCD) or 7/8 (LDS
+ * tiles, one workgroup per 64 chunks banded over the XCDs; waves_per_cu then
+ * caps residency, 0 = none). */
 typedef struct cprng_tuning {
     uint32_t block;            /* threads per block: 64, 128, 192 or 256; the interleaved
                                   layout's tiles take 256, 512 or 1024 (streams per tile) */
     uint32_t unroll;           /* outputs per stream per round: 8, 16, 32 (direct);
-                                  16..256, powers of two (LDS-transposed);
-                                  16..128 (pipelined) */
+                                  16..256, powers of two (LDS-transposed; chunk
+                                  kernels 32..256); 16..128 (pipelined) */
     uint32_t store;            /* store mode, see above */
     uint32_t chunk;            /* ragged/requests: outputs per chunk (multiple of 64) */
-    uint32_t waves_per_cu;     /* ragged/requests and pipelined generate: persistent
-                                  waves per CU (0 = default);
-                                  LDS-transposed generate: residency cap (0 = none) */
+    uint32_t waves_per_cu;     /* ragged/requests (store 1/2/4) and pipelined generate:
+                                  persistent waves per CU (0 = default); LDS-transposed
+                                  generate and ragged store 7/8: residency cap (0 = none) */
     uint32_t streams_per_lane; /* LDS-transposed generate: 1, 2 or 4 streams per lane;
                                   interleaved tiles: 2 = two tile buffers, so each
                                   round's stores overlap the next round's steps */

@@ -158,10 +158,11 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
     if (!consume && (h->flags & CPRNG_F_INTERLEAVED)) {
         // Interleaved layout: LDS tiles of K steps x block streams, spread
         // over the XCDs in bands.  Measured on MI355X at 2^20 streams x 1024:
-        // 1,024 streams x 8 steps, two tile buffers, non-temporal stores, V2
-        // exchange by cross-lane reads; V1, VALU-bound, 256 x 32 with one
-        // buffer.  Direct store modes select the per-lane dword kernel.
-        LaunchCfg c{1024, 8, ST_ILV_TILE_NT, 0, 2, XCH_BPERM, 0};
+        // 1,024 streams x 16 steps, two tile buffers (128 KiB of LDS),
+        // non-temporal stores, V2 exchange by cross-lane reads; V1,
+        // VALU-bound, 256 x 32 with one buffer.  Direct store modes select
+        // the per-lane dword kernel.
+        LaunchCfg c{1024, 16, ST_ILV_TILE_NT, 0, 2, XCH_BPERM, 0};
         if (h->variant == CPRNG_V1_NAIVE3) {
             c.block = 256;
             c.unroll = 32;
@@ -219,8 +220,8 @@ int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchC
             if (c.block > 256) c.block = 256;
             if (c.unroll > 32) c.unroll = 32;
         } else {
-            // block: 256, 512 or 1024 streams; K * block words (+ the V2
-            // exchange buffer) must fit 64 KiB
+            // block: 256, 512 or 1024 streams; the tiles (+ the V2 exchange
+            // buffer) must fit a workgroup's LDS
             uint32_t b = 256;
             while (b < c.block && b < 1024) b *= 2;
             c.block = b;
@@ -229,7 +230,8 @@ int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchC
             if (c.exchange < XCH_BPERM || c.exchange > XCH_BPERM2) c.exchange = XCH_BPERM;
             if (c.slots != 2) c.slots = 1;      // 2: double-buffered tiles
             const uint32_t extra = (h->variant == CPRNG_V2_SHMEM && c.exchange == XCH_LDS) ? 1u : 0u;
-            while ((uint64_t)(c.slots * c.unroll + extra) * c.block * 4u > 65536u) {
+            if (c.block == 1024 && c.unroll > 32) c.unroll = 32;
+            while ((uint64_t)(c.slots * c.unroll + extra) * c.block * 4u > kMaxLdsBytes) {
                 if (c.unroll > 8) c.unroll /= 2;
                 else if (c.block > 256) c.block /= 2;
                 else c.slots = 1;

@@ -731,7 +731,7 @@ __device__ __forceinline__ void jump_v0(X128 &g, uint32_t &x, const uint32_t *po
     x = a4;
 }
 
-// Work queues of the chunk kernels: one per XCD.  Queue x holds the
+// Work queues of the chunk kernels (persistent launches): one per XCD.  Queue x holds the
 // contiguous run of segments [lo(x), lo(x) + count(x)) (the split of
 // xcd_tile), its counter is a.counter[x]; a wave takes 64 segments at a time
 // from its own XCD's queue (workgroup b runs on XCD b % 8) and, once that is
@@ -740,6 +740,16 @@ __device__ __forceinline__ void jump_v0(X128 &g, uint32_t &x, const uint32_t *po
 __device__ __forceinline__ bool grab_segments(const SegArgs &a, uint32_t lane, uint32_t &qi, uint32_t &base,
                                               uint32_t &end)
 {
+    if (!a.persistent) {
+        // One grab per wave: wave w of workgroup b takes the 64 segments of
+        // tile xcd_tile(b) * (waves per workgroup) + w.
+        if (qi) return false;
+        qi = 8u;
+        const uint32_t wpb = blockDim.x >> 6;
+        base = (xcd_tile(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6)) * 64u;
+        end = (a.nseg - base) < 64u ? a.nseg : base + 64u;
+        return base < a.nseg;
+    }
     const uint32_t per = a.nseg >> 3, extra = a.nseg & 7u;
     while (qi < 8u) {
         const uint32_t x = (blockIdx.x + qi) & 7u;
@@ -1122,14 +1132,14 @@ hipError_t ilv_launch(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
     const bool db = c.slots == 2;            // interleaved tiles: slots = number of tile buffers
     const size_t lds = (size_t)(db ? 2 : 1) * K * c.block * sizeof(uint32_t) +
                        (xm == XCH_LDS ? (size_t)c.block * sizeof(uint32_t) : 0);
-    if (lds > 65536 || a.ns % 4u) return hipErrorInvalidValue;
+    if (lds > kMaxLdsBytes || a.ns % 4u) return hipErrorInvalidValue;
     const uint32_t grid = (a.ns + c.block - 1) / c.block;
 #define ILV(B, X, D) hipLaunchKernelGGL((k_generate_ilv<VAR, T, K, B, NT, X, D>), dim3(grid), dim3(B), lds, st, a)
 #define ILVB(X, D)                                                   \
     switch (c.block) {                                               \
     case 256: ILV(256, X, D); break;                                 \
-    case 512: if constexpr (K <= 32) { ILV(512, X, D); break; } return hipErrorInvalidValue;   \
-    case 1024: if constexpr (K <= 16) { ILV(1024, X, D); break; } return hipErrorInvalidValue; \
+    case 512: ILV(512, X, D); break;                                 \
+    case 1024: if constexpr (K <= 32) { ILV(1024, X, D); break; } return hipErrorInvalidValue; \
     default: return hipErrorInvalidValue;                            \
     }
 #define ILVX(X) if (db) { ILVB(X, true) } else { ILVB(X, false) }
@@ -1222,12 +1232,14 @@ hipError_t launch_consume(const GenArgs &a, int variant, int w32, const LaunchCf
     }
 }
 
-hipError_t launch_segments(const SegArgs &a, uint32_t grid, uint32_t block, uint32_t store, hipStream_t st)
+hipError_t launch_segments(const SegArgs &a, uint32_t grid, uint32_t block, uint32_t store, uint32_t lds_min,
+                           hipStream_t st)
 {
     if (grid == 0) return hipErrorInvalidValue;
     if (store == ST_LDS || store == ST_LDS_NT) {
         const bool nt = store == ST_LDS_NT;
-        const size_t lds = (size_t)64 * a.unroll * 4 + 64 * 12;
+        size_t lds = (size_t)64 * a.unroll * 4 + 64 * 12;
+        if (lds < lds_min) lds = lds_min;
 #define SEG_TILE(K)                                                                              \
     do {                                                                                         \
         if (nt) hipLaunchKernelGGL((k_segments_tile<K, true>), dim3(grid), dim3(64), lds, st, a);  \
@@ -1237,7 +1249,7 @@ hipError_t launch_segments(const SegArgs &a, uint32_t grid, uint32_t block, uint
         case 32: SEG_TILE(32); break;
         case 64: SEG_TILE(64); break;
         case 128: SEG_TILE(128); break;
-        case 256: return hipErrorInvalidValue;          // 64 KiB tile + row data exceeds 64 KiB
+        case 256: SEG_TILE(256); break;                 // 64 KiB tile + row data (gfx950: 160 KiB per workgroup)
         default: return hipErrorInvalidValue;
         }
 #undef SEG_TILE

@@ -10,6 +10,9 @@
 
 namespace cprng_impl {
 
+// LDS a gfx950 workgroup may allocate (the whole 160 KiB of a CU).
+constexpr uint32_t kMaxLdsBytes = 160u * 1024u;
+
 // Store modes of the plain generate kernel.
 enum StoreMode : int {
     ST_DIRECT = 1,        // each lane stores its own stream's 16-byte quads
@@ -87,9 +90,11 @@ struct SegArgs {
     uint32_t *state_next;  // end states of runs with `last`
     uint32_t *counter;     // work-queue counters, one per XCD (8 words, reset before each launch)
     uint32_t unroll;       // outputs per lane per round
+    uint32_t persistent;   // 1: waves take grabs from the queues; 0: one grab per wave, by workgroup id
 };
 
-hipError_t launch_segments(const SegArgs &a, uint32_t grid, uint32_t block, uint32_t store,
+// lds_min: dynamic LDS per workgroup at least this (caps residency).
+hipError_t launch_segments(const SegArgs &a, uint32_t grid, uint32_t block, uint32_t store, uint32_t lds_min,
                            hipStream_t st);
 // state[k * ns + ids[i]] = state_next[k * ns + ids[i]] for k < 5.
 hipError_t launch_commit(uint32_t *state, const uint32_t *state_next, const uint32_t *ids,

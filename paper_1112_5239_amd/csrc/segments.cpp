@@ -112,20 +112,34 @@ struct SegCfg {
     uint32_t chunk, unroll, waves, block, store;
 };
 
-// Tiled stores (one wave per workgroup) take K in {32, 64, 128}; per-lane
-// stores take K in {8, 16, 32} and any block size.
+// Store codes of the chunk kernels: ST_LDS / ST_LDS_NT persistent waves
+// taking grabs from the per-XCD queues (waves = persistent waves per CU);
+// ST_PIPE / ST_PIPE_NT one workgroup per grab, banded over the XCDs and
+// scheduled by the hardware (waves = residency cap through LDS, 0 = none);
+// ST_DIRECT per-lane stores, persistent.
+bool seg_persistent(const SegCfg &c) { return c.store != ST_PIPE && c.store != ST_PIPE_NT; }
+
+uint32_t seg_kernel_store(const SegCfg &c)
+{
+    if (c.store == ST_PIPE) return ST_LDS;
+    if (c.store == ST_PIPE_NT) return ST_LDS_NT;
+    return c.store;
+}
+
+// Tiled stores (one wave per workgroup) take K in {32, 64, 128, 256};
+// per-lane stores take K in {8, 16, 32} and any block size.
 void normalize(SegCfg &c)
 {
-    if (c.store == ST_LDS || c.store == ST_LDS_NT) {
+    if (c.store == ST_LDS || c.store == ST_LDS_NT || c.store == ST_PIPE || c.store == ST_PIPE_NT) {
         c.block = 64;
         if (c.unroll < 32) c.unroll = 32;
-        if (c.unroll > 128) c.unroll = 128;
+        if (c.unroll > 256) c.unroll = 256;
     } else {
         c.store = ST_DIRECT;
         if (c.unroll > 32) c.unroll = 32;
         if (c.unroll < 8) c.unroll = 8;
     }
-    if (c.waves == 0) c.waves = 4;
+    if (c.waves == 0 && seg_persistent(c)) c.waves = 4;
 }
 
 SegCfg resolve_seg_cfg(const cprng_t *h, uint64_t total, uint64_t max_len)
@@ -148,15 +162,7 @@ SegCfg resolve_seg_cfg(const cprng_t *h, uint64_t total, uint64_t max_len)
     if (h->tuning.waves_per_cu) c.waves = h->tuning.waves_per_cu;
     if (h->tuning.unroll) c.unroll = h->tuning.unroll;
     if (h->tuning.block) c.block = h->tuning.block;
-    if (h->tuning.store) {
-        // the chunk kernels are persistent already: pipelined modes map to LDS tiles
-        switch (h->tuning.store) {
-        case ST_DIRECT_NT: c.store = ST_DIRECT; break;
-        case ST_PIPE: c.store = ST_LDS; break;
-        case ST_PIPE_NT: c.store = ST_LDS_NT; break;
-        default: c.store = h->tuning.store; break;
-        }
-    }
+    if (h->tuning.store) c.store = h->tuning.store == ST_DIRECT_NT ? (uint32_t)ST_DIRECT : h->tuning.store;
     normalize(c);
     return c;
 }
@@ -164,6 +170,11 @@ SegCfg resolve_seg_cfg(const cprng_t *h, uint64_t total, uint64_t max_len)
 uint32_t persistent_grid(const cprng_t *h, const SegCfg &c, uint64_t nseg)
 {
     const uint32_t waves_per_block = c.block / 64;
+    if (!seg_persistent(c)) {                          // one grab of 64 segments per wave
+        const uint64_t grabs = (nseg + 63) / 64;
+        const uint64_t blocks = (grabs + waves_per_block - 1) / waves_per_block;
+        return (uint32_t)(blocks ? blocks : 1);
+    }
     uint64_t grid = (uint64_t)h->n_cu * c.waves / waves_per_block;
     const uint64_t needed = (nseg + 63) / 64;          // one grab per wave
     const uint64_t needed_blocks = (needed + waves_per_block - 1) / waves_per_block;
@@ -197,8 +208,11 @@ SegArgs seg_args(const cprng_t *h, const SegCfg &c, const RunDesc *runs, uint32_
     a.state_next = h->d_state_next;
     a.counter = counter;
     a.unroll = c.unroll;
+    a.persistent = seg_persistent(c) ? 1u : 0u;
     return a;
 }
+
+uint32_t seg_lds_min(const SegCfg &c) { return seg_persistent(c) ? 0u : lds_for_waves(c.block, c.waves); }
 
 int build_plan(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets,
                const SegCfg &c, RaggedPlan **res)
@@ -248,7 +262,7 @@ int build_plan(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_
         return set_error(CPRNG_E_HIP, "hipStreamCreate (capture)");
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) e = launch_zero_u32(h->d_counter, 8, cs);
-    if (e == hipSuccess && p->nseg) e = launch_segments(a, p->grid, c.block, c.store, cs);
+    if (e == hipSuccess && p->nseg) e = launch_segments(a, p->grid, c.block, seg_kernel_store(c), seg_lds_min(c), cs);
     if (e == hipSuccess) e = launch_commit(h->d_state, h->d_state_next, p->d_ids, (uint32_t)ids.size(), h->ns, cs);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &graph);
@@ -411,7 +425,8 @@ extern "C" int cprng_autotune_ragged(cprng_t *h, uint32_t *out, const uint64_t *
     const uint32_t waves[] = {1, 2, 3, 4, 8};
     // (store, unroll, block): per-lane stores and LDS tiles of several widths
     const uint32_t modes[][3] = {{ST_DIRECT, 16, 256}, {ST_DIRECT, 32, 256}, {ST_LDS, 32, 64},
-                                 {ST_LDS, 64, 64}, {ST_LDS, 128, 64}, {ST_LDS_NT, 32, 64}};
+                                 {ST_LDS, 64, 64}, {ST_LDS, 128, 64}, {ST_LDS_NT, 32, 64},
+                                 {ST_PIPE, 64, 64}, {ST_PIPE, 128, 64}, {ST_PIPE_NT, 128, 64}};
     float best = 1e30f;
     SegCfg best_c = resolve_seg_cfg(h, total, max_len);
     const bool saved_timing = h->timing;
@@ -615,7 +630,7 @@ extern "C" int cprng_generate_requests(cprng_t *h, const cprng_request_t *reqs, 
         const SegArgs a = seg_args(h, c, (const RunDesc *)(db + run_off[j]), (uint32_t)launches[j].runs.size(),
                                    launches[j].nseg, kcap, d_tab, slot->d_counter);
         e = launch_zero_u32(slot->d_counter, 8, st);
-        if (e == hipSuccess) e = launch_segments(a, persistent_grid(h, c, a.nseg), c.block, c.store, st);
+        if (e == hipSuccess) e = launch_segments(a, persistent_grid(h, c, a.nseg), c.block, seg_kernel_store(c), seg_lds_min(c), st);
         if (e == hipSuccess)
             e = launch_commit(h->d_state, h->d_state_next, (const uint32_t *)(db + id_off[j]),
                               (uint32_t)ids[j].size(), h->ns, st);

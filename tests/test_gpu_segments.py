@@ -70,7 +70,8 @@ def test_ragged_small_default_offsets(orc, G, torch):
 
 
 @pytest.mark.parametrize("chunk", [64, 256, 1024])
-@pytest.mark.parametrize("store,unroll", [(1, 16), (2, 32), (4, 64), (2, 128)])
+@pytest.mark.parametrize("store,unroll", [(1, 16), (2, 32), (4, 64), (2, 128), (2, 256), (7, 64), (8, 128),
+                                          (7, 256)])
 def test_ragged_many_chunks_jump_ahead(orc, G, torch, chunk, store, unroll):
     # Small chunks force many jumped segment starts per stream; per-lane and
     # LDS-tiled stores, tiles longer and shorter than the chunks.
@@ -80,7 +81,7 @@ def test_ragged_many_chunks_jump_ahead(orc, G, torch, chunk, store, unroll):
                   tuning=dict(chunk=chunk, unroll=unroll, waves_per_cu=2, store=store))
 
 
-@pytest.mark.parametrize("store", [1, 4])
+@pytest.mark.parametrize("store", [1, 4, 7])
 def test_ragged_explicit_misaligned_offsets_with_gaps(orc, G, torch, store):
     rng = np.random.default_rng(3)
     lengths = rng.integers(0, 3000, 50)
