@@ -212,7 +212,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=50,
                     help="untimed steps; the first ~50 launches after the GPU has been idle run slower")
-    ap.add_argument("--workload", default="paper", choices=["paper", "serving"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "ragged", "serving"])
     ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -237,6 +237,26 @@ def main():
         from paper_1112_5239_amd import serving
         res = serving.bench_line(args)
         print(json.dumps(res), flush=True)
+        return
+    if args.workload == "ragged":
+        # The batched half of the metric alone, for profiling: uneven streams
+        # in one hipGraph launch, against plain V0 (stream-major) timed first.
+        ref = run_plain(torch, G, "v0", args, interleaved=False)
+        if args.copy_probe:
+            n_words = 1 << 28
+            src = torch.zeros(n_words, dtype=torch.int32, device="cuda")
+            dst = torch.empty(n_words, dtype=torch.int32, device="cuda")
+            for _ in range(2):
+                L.cprng_probe_copy(dst, src, n_words, torch.cuda.current_stream().cuda_stream)
+            torch.cuda.synchronize()
+            del src, dst
+        res = run_ragged(torch, G, args, ref["gnumbers_per_s"])
+        log(f"[bench] ragged: {res}")
+        print(json.dumps({"metric": "batched uneven streams: Gnumbers/s and ratio to plain V0",
+                          "value": res["gnumbers_per_s"], "unit": "Gnumbers/s", "n_gpus": 1,
+                          "ms_per_step": res["ms"], "higher_is_better": True, "dtype": "u32",
+                          "data": "synthetic", "config": {"workload": res["workload"]},
+                          "plain_v0": ref, "ragged": res}), flush=True)
         return
 
     ms, wall, numbers, alg_bytes, achieved = run_paper(torch, G, L, args, interleaved=True)

@@ -772,7 +772,8 @@ __device__ __forceinline__ bool grab_segments(const SegArgs &a, uint32_t lane, u
 struct Seg {
     gu32 *out;             // first output of the segment
     uint32_t len, head, stream, last;
-    const uint32_t *poly;  // nullptr: no jump (segment 0)
+    const uint32_t *poly;  // nullptr: no jump (segment 0); else X^(k*chunk) mod q
+    uint32_t skip;         // steps after the jump: the run's head
     uint64_t pos;          // start position within the run
 };
 
@@ -796,12 +797,15 @@ __device__ __forceinline__ Seg decode_segment(const SegArgs &a, uint32_t idx)
         len = r.len < seg0 ? r.len : seg0;
         s.head = r.head;
         s.poly = nullptr;
+        s.skip = 0;
     } else {
+        // position head + k*chunk: jump by k*chunk, then step head times
         s.pos = seg0 + (uint64_t)(k - 1) * a.chunk;
         const uint64_t left = r.len - s.pos;
         len = left < a.chunk ? left : a.chunk;
         s.head = 0;
-        s.poly = a.polys + 5ull * ((uint64_t)r.head * a.kcap + k);
+        s.poly = a.polys + 5ull * k;
+        s.skip = r.head;
     }
     s.len = (uint32_t)len;
     s.out = gptr(r.out) + s.pos;
@@ -822,7 +826,10 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a)
             const uint32_t *p = a.state + d.stream;
             X128 g{p[0], p[ns], p[2 * ns], p[3 * ns]};
             uint32_t x = p[4 * ns];
-            if (d.poly) jump_v0(g, x, d.poly);
+            if (d.poly) {
+                jump_v0(g, x, d.poly);
+                for (uint32_t i = 0; i < d.skip; ++i) x ^= x128_next(g);
+            }
             gu32 *o = d.out;
             const uint32_t len = d.len;
             uint32_t i = 0;
@@ -872,7 +879,8 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a)
 // lengths are read once per grab into registers.  Rounds in which every row
 // is full take a branch-free store loop; the last rounds of short segments
 // store whole quads, then the final partial quad word by word.  Rows start
-// 16-byte aligned after the segment's head (0..3 outputs stored singly).
+// 256-byte aligned after the run's head (0..63 outputs stored singly by
+// segment 0), so full rounds write whole lines.
 template <int K, bool NT>
 __global__ __launch_bounds__(64) void k_segments_tile(SegArgs a)
 {
@@ -898,7 +906,10 @@ __global__ __launch_bounds__(64) void k_segments_tile(SegArgs a)
             const uint32_t *p = a.state + d.stream;
             g = X128{p[0], p[ns], p[2 * ns], p[3 * ns]};
             x = p[4 * ns];
-            if (d.poly) jump_v0(g, x, d.poly);
+            if (d.poly) {
+                jump_v0(g, x, d.poly);
+                for (uint32_t i = 0; i < d.skip; ++i) x ^= x128_next(g);
+            }
             const uint32_t head = d.head < d.len ? d.head : d.len;
             for (uint32_t i = 0; i < head; ++i) {
                 x ^= x128_next(g);

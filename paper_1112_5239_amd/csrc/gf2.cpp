@@ -208,26 +208,22 @@ namespace cprng_impl {
 
 namespace {
 std::mutex g_tab_mu;
-// Per chunk length: X^(h + k*chunk) mod q for h = 0..3, k = 0, 1, 2, ...
-std::map<uint32_t, std::array<std::vector<JPoly>, 4>> g_tables;
+// Per chunk length: X^(k*chunk) mod q for k = 0, 1, 2, ...
+std::map<uint32_t, std::vector<JPoly>> g_tables;
 }  // namespace
 
 void jump_table(uint32_t chunk, uint32_t kcap, std::vector<uint32_t> &out)
 {
     std::lock_guard<std::mutex> lk(g_tab_mu);
-    auto &rows = g_tables[chunk];
-    if (rows[0].size() < kcap) {
+    std::vector<JPoly> &r = g_tables[chunk];
+    if (r.size() < kcap) {
         const JPoly step = jump_xpow(chunk);
-        for (uint32_t h = 0; h < 4; ++h) {
-            std::vector<JPoly> &r = rows[h];
-            if (r.empty()) r.push_back(jump_xpow(h));
-            r.reserve(kcap);
-            while (r.size() < kcap) r.push_back(jump_mul(r.back(), step));
-        }
+        if (r.empty()) r.push_back(jump_xpow(0));
+        r.reserve(kcap);
+        while (r.size() < kcap) r.push_back(jump_mul(r.back(), step));
     }
-    out.assign((size_t)4 * kcap * 5, 0u);
-    for (uint32_t h = 0; h < 4; ++h)
-        for (uint32_t k = 0; k < kcap; ++k) jump_pack(rows[h][k], &out[((size_t)h * kcap + k) * 5]);
+    out.assign((size_t)kcap * 5, 0u);
+    for (uint32_t k = 0; k < kcap; ++k) jump_pack(r[k], &out[(size_t)k * 5]);
 }
 
 }  // namespace cprng_impl

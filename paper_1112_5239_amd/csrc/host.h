@@ -40,8 +40,8 @@ JPoly jump_xpow(uint64_t J);          // X^J mod q
 JPoly jump_one();
 // Pack into the kernel's 5 x 32-bit coefficient words (coefficients 0..128).
 void jump_pack(const JPoly &p, uint32_t out[5]);
-// Packed table of X^(h + k*chunk) mod q, h = 0..3, k = 0..kcap-1, at index
-// h*kcap + k (5 words each).  Cached per process and extended on demand.
+// Packed table of X^(k*chunk) mod q, k = 0..kcap-1, at index k (5 words
+// each).  Cached per process and extended on demand.
 void jump_table(uint32_t chunk, uint32_t kcap, std::vector<uint32_t> &out);
 // Make sure request batches of runs up to max_len outputs find their jump
 // table on the device without rebuilding it (segments.cpp).

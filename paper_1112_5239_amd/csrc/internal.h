@@ -65,15 +65,15 @@ hipError_t launch_consume(const GenArgs &a, int variant, int w32, const LaunchCf
 // A run of consecutive outputs of one stream (a batched stream or a request)
 // for the chunked kernels.  The run is cut into chunks ("segments"):
 // segment 0 covers positions [0, min(len, head + chunk)), segment k >= 1
-// covers [head + k*chunk, min(len, head + (k+1)*chunk)); `head` (0..3) makes
-// every segment after the first start on a 16-byte boundary.  Segment k starts
-// from the stream's state jumped ahead by its start position, with the jump
-// polynomial X^(head + k*chunk) at table index head*kcap + k (k >= 1).
+// covers [head + k*chunk, min(len, head + (k+1)*chunk)); `head` (0..63) makes
+// every segment after the first start on a 256-byte boundary.  Segment k >= 1
+// starts from the stream's state jumped ahead by k*chunk (polynomial at table
+// index k) and then stepped `head` times.
 struct RunDesc {
     uint64_t out;          // device address of the run's first output
     uint64_t len;          // outputs in the run (> 0)
     uint32_t stream;       // stream id
-    uint32_t head;         // 0..3
+    uint32_t head;         // 0..63: outputs before the run's first 256-byte boundary
     uint32_t first_seg;    // global index of the run's segment 0
     uint32_t last;         // 1: the run ends the stream's work of this launch
 };
@@ -83,8 +83,8 @@ struct SegArgs {
     uint32_t nrun;
     uint32_t nseg;         // total segments
     uint32_t chunk;        // outputs per segment (multiple of 64)
-    uint32_t kcap;         // jump table: kcap entries per head value
-    const uint32_t *polys; // 4*kcap polynomials, 5 words each, bit k = coeff of X^k
+    uint32_t kcap;         // jump table entries (distances k * chunk, k < kcap)
+    const uint32_t *polys; // kcap polynomials X^(k*chunk) mod q, 5 words each, bit i = coeff of X^i
     uint32_t ns;           // streams (SoA stride)
     const uint32_t *state; // current states (read only during the launch)
     uint32_t *state_next;  // end states of runs with `last`

@@ -55,7 +55,10 @@ void free_plan(RaggedPlan *p)
     delete p;
 }
 
-uint32_t head_of(uint64_t addr) { return (uint32_t)((4u - (uint32_t)((addr / 4u) % 4u)) % 4u); }
+// Outputs before the first 256-byte boundary of a run: the run's segment 0
+// stores them one by one, so every later segment (a multiple of 64 outputs)
+// starts on a 256-byte boundary and the tiles write whole lines.
+uint32_t head_of(uint64_t addr) { return (uint32_t)((64u - (uint32_t)((addr / 4u) % 64u)) % 64u); }
 
 uint64_t segments_of(uint64_t len, uint32_t head, uint32_t chunk)
 {
@@ -145,11 +148,12 @@ void normalize(SegCfg &c)
 SegCfg resolve_seg_cfg(const cprng_t *h, uint64_t total, uint64_t max_len)
 {
     // Default measured on MI355X for 4,096 streams of 1e3..1e7 outputs:
-    // LDS-tiled stores of K = 32 outputs per row and round, 2048-output
-    // chunks (a wave's 64 chunks then span 512 KiB of the output), two
-    // persistent waves per CU: fewer rows written at once keeps the set of
-    // open DRAM pages small, which outweighs the lost VALU parallelism.
-    SegCfg c{2048, 32, 2, 64, ST_LDS};
+    // LDS-tiled non-temporal stores of K = 128 outputs per row and round,
+    // 2048-output chunks (a wave's 64 chunks span 512 KiB of the output),
+    // three persistent waves per CU.  With runs aligned to 256 bytes every
+    // round writes whole lines; then 3 waves per CU keep enough SIMDs busy
+    // without widening the set of rows written at once too far.
+    SegCfg c{2048, 128, 3, 64, ST_LDS_NT};
     TuneEntry e;
     if (tune_cache_lookup_key(tune_key_ragged(h, total, max_len), &e)) {
         if (e.chunk) c.chunk = e.chunk;
@@ -654,7 +658,7 @@ int prepare_request_tables(cprng_t *h, uint64_t max_len)
     for (uint32_t chunk = c.chunk;; chunk /= 2) {
         const uint32_t *d = nullptr;
         uint32_t kcap = 0;
-        rc = request_table(h, chunk, segments_of(max_len, 3, chunk), &d, &kcap);
+        rc = request_table(h, chunk, segments_of(max_len, 0, chunk), &d, &kcap);
         if (rc || chunk <= 1024 || h->tuning.chunk) return rc;
     }
 }
