@@ -731,12 +731,14 @@ __device__ __forceinline__ void jump_v0(X128 &g, uint32_t &x, const uint32_t *po
     x = a4;
 }
 
-// Work queues of the chunk kernels (persistent launches): one per XCD.  Queue x holds the
-// contiguous run of segments [lo(x), lo(x) + count(x)) (the split of
-// xcd_tile), its counter is a.counter[x]; a wave takes 64 segments at a time
-// from its own XCD's queue (workgroup b runs on XCD b % 8) and, once that is
-// empty, from the others in turn.  Each XCD thus writes one band of the
-// output in order.  Returns false when every queue is empty.
+// Work queues of the chunk kernels (persistent launches): one per XCD.  The
+// segments form grabs of 64 (the last may be short); queue x holds the
+// contiguous run of grabs that xcd_tile gives XCD x, and its counter
+// a.counter[x] counts the grabs taken.  A wave takes one grab at a time from
+// its own XCD's queue (workgroup b runs on XCD b % 8) and, once that is empty,
+// from the others in turn.  Each XCD thus writes one band of the output in
+// order, and small launches still take whole grabs.  Returns false when every
+// queue is empty.
 __device__ __forceinline__ bool grab_segments(const SegArgs &a, uint32_t lane, uint32_t &qi, uint32_t &base,
                                               uint32_t &end)
 {
@@ -750,17 +752,18 @@ __device__ __forceinline__ bool grab_segments(const SegArgs &a, uint32_t lane, u
         end = (a.nseg - base) < 64u ? a.nseg : base + 64u;
         return base < a.nseg;
     }
-    const uint32_t per = a.nseg >> 3, extra = a.nseg & 7u;
+    const uint32_t grabs = (a.nseg + 63u) >> 6;
+    const uint32_t per = grabs >> 3, extra = grabs & 7u;
     while (qi < 8u) {
         const uint32_t x = (blockIdx.x + qi) & 7u;
         const uint32_t lo = x * per + (x < extra ? x : extra);
-        const uint32_t hi = lo + per + (x < extra ? 1u : 0u);
+        const uint32_t count = per + (x < extra ? 1u : 0u);
         uint32_t off = 0;
-        if (lane == 0) off = atomicAdd(a.counter + x, 64u);
+        if (lane == 0) off = atomicAdd(a.counter + x, 1u);
         off = (uint32_t)__builtin_amdgcn_readfirstlane((int)off);
-        if (off < hi - lo) {
-            base = lo + off;
-            end = (hi - base) < 64u ? hi : base + 64u;
+        if (off < count) {
+            base = (lo + off) * 64u;
+            end = (a.nseg - base) < 64u ? a.nseg : base + 64u;
             return true;
         }
         ++qi;
