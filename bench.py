@@ -40,6 +40,11 @@ LANES_FAST, LANES_SHIFT = 128, 64
 # (gfx950 code object of cprng_kernels.hip, unroll 16): shift-class
 # (v_lshlrev/v_lshrrev) and everything else.
 CONSUME_MIX = {"v0": (71 / 16, 162 / 16), "v2": (71 / 16, 194 / 16)}
+# The 64-bit-word variant (V1) per generated number, same code object
+# (interleaved tile loop, 32 numbers): 28 v_xor_b32 and 11.25 64-bit shifts
+# and adds (v_lshlrev_b64, v_lshrrev_b64, v_lshl_add_u64).  The issue rate of
+# the 64-bit class is not published; it is taken from the probe of the same run.
+V1_MIX = (896 / 32, (160 + 128 + 72) / 32)
 
 
 def log(msg):
@@ -125,6 +130,16 @@ def run_paper(torch, G, L, args, interleaved, steps=None, warmup=None):
     return ms, wall, numbers, alg_bytes, achieved
 
 
+def v1_alu_roofline(gn, probe):
+    """ALU roofline of V1 (Gnumbers/s): fast class at its published rate, the
+    64-bit class at the slower of the two 64-bit probe rates."""
+    n_fast, n_64 = V1_MIX
+    lanes64 = 64 * min(probe["shift64"], probe["add64"])
+    peak = CU * CLOCK_HZ / (n_fast / LANES_FAST + n_64 / lanes64) / 1e9
+    return {"bound": "alu", "achieved": round(gn, 1), "peak": round(peak, 1), "unit": "Gnumbers/s",
+            "frac": round(gn / peak, 4), "lanes_per_clk_64bit": round(lanes64, 1)}
+
+
 def run_plain(torch, G, variant, args, interleaved=False):
     ns, n = 1 << 20, 1024
     words = {"v0": 5, "v1": 23}[variant]
@@ -170,7 +185,7 @@ def run_valu_probes(torch, L):
     out = torch.empty(n_threads, dtype=torch.int32, device="cuda")
     st = torch.cuda.current_stream().cuda_stream
     res = {}
-    for kind, name in ((0, "xor"), (1, "shift"), (2, "f32_mul_add")):
+    for kind, name in ((0, "xor"), (1, "shift"), (2, "f32_mul_add"), (3, "shift64"), (4, "add64")):
         ms, _ = timed(torch, lambda: L.cprng_probe_valu(kind, out, n_threads, iters, st), 3, 1)
         rate = n_threads / 64 * iters * 32 / (ms / 1e3)
         res[name] = round(rate / CU / CLOCK_HZ, 3)
@@ -279,17 +294,19 @@ def main():
                                     "ms": round(sm_ms, 4), "gnumbers_per_s": round(numbers / (sm_ms / 1e3) / 1e9, 2),
                                     "hbm_gbs": round(sm_ach, 1), "frac_hbm_peak": round(sm_ach / HBM_PEAK_GBS, 4)}
         log(f"[bench] v2 stream-major: {extra['v2_stream_major']}")
+        extra["valu_probe"] = run_valu_probes(torch, L)
+        log(f"[bench] valu probe: {extra['valu_probe']}")
         for variant in ("v0", "v1"):
             for ilv in (True, False):
                 key = f"{variant}_{'interleaved' if ilv else 'stream_major'}"
                 extra[key] = run_plain(torch, G, variant, args, interleaved=ilv)
+                if variant == "v1":
+                    extra[key]["roofline"] = v1_alu_roofline(extra[key]["gnumbers_per_s"], extra["valu_probe"])
                 log(f"[bench] {key}: {extra[key]}")
         extra["ragged"] = run_ragged(torch, G, args, extra["v0_stream_major"]["gnumbers_per_s"])
         log(f"[bench] ragged: {extra['ragged']}")
         extra["consume"] = run_consume(torch, G, args)
         log(f"[bench] consume: {extra['consume']}")
-        extra["valu_probe"] = run_valu_probes(torch, L)
-        log(f"[bench] valu probe: {extra['valu_probe']}")
         extra["fill_probe"] = run_fill_probe(torch, L)
         log(f"[bench] fill probe: {extra['fill_probe']}")
     cpu = None

@@ -335,10 +335,11 @@ int cprng_probe_copy(uint32_t *dst, const uint32_t *src, uint64_t n_words, cprng
 
 /* VALU issue-rate probe: n_threads lanes (a multiple of 256) each run `iters`
  * iterations of 32 instructions of one class -- kind 0 v_xor_b32, 1
- * v_lshlrev_b32, 2 v_mul_f32/v_add_f32 -- on 8 registers with no dependency
- * closer than four instructions, then write one word to out (device,
- * n_threads uint32).  Errors: E_INVAL (kind > 2, n_threads not a positive
- * multiple of 256, out NULL), E_HIP. */
+ * v_lshlrev_b32, 2 v_mul_f32/v_add_f32, 3 v_lshlrev_b64, 4 v_lshl_add_u64 --
+ * on 8 registers (pairs for the 64-bit kinds) with no dependency closer than
+ * four instructions, then write one word to out (device, n_threads uint32).
+ * Errors: E_INVAL (kind > 4, n_threads not a positive multiple of 256, out
+ * NULL), E_HIP. */
 int cprng_probe_valu(uint32_t kind, uint32_t *out, uint32_t n_threads, uint32_t iters, cprng_stream_t stream);
 
 /* ------------------------------------------------------------------------ */

@@ -244,25 +244,25 @@ int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchC
     }
     if (c.store == ST_LDS || c.store == ST_LDS_NT) {
         // LDS tiles hold K >= 16 words per row; block/64 waves x 64 rows x K
-        // words must fit 64 KiB (K <= 256 always fits with block 64).
+        // words must fit a workgroup's LDS (160 KiB on gfx950).
         if (c.unroll < 16) c.unroll = 16;
         if (c.slots != 1 && c.slots != 2 && c.slots != 4) c.slots = 1;
         if (c.exchange < XCH_BPERM || c.exchange > XCH_BPERM2) c.exchange = XCH_BPERM;
-        // tile (+ the exchange buffer) per block must fit 64 KiB
+        // tile (+ the exchange buffer) per block must fit the LDS
         const uint32_t extra = (h->variant == CPRNG_V2_SHMEM && c.exchange == XCH_LDS) ? 1u : 0u;
-        while (c.block > 64 && (uint64_t)c.block * c.slots * (c.unroll + extra) * 4u > 65536u) c.block -= 64;
-        while (c.slots > 1 && (uint64_t)c.block * c.slots * (c.unroll + extra) * 4u > 65536u) c.slots /= 2;
-        if ((uint64_t)c.block * c.slots * (c.unroll + extra) * 4u > 65536u) c.unroll /= 2;
+        while (c.block > 64 && (uint64_t)c.block * c.slots * (c.unroll + extra) * 4u > kMaxLdsBytes) c.block -= 64;
+        while (c.slots > 1 && (uint64_t)c.block * c.slots * (c.unroll + extra) * 4u > kMaxLdsBytes) c.slots /= 2;
+        if ((uint64_t)c.block * c.slots * (c.unroll + extra) * 4u > kMaxLdsBytes) c.unroll /= 2;
     }
     if ((c.store == ST_PIPE || c.store == ST_PIPE_NT) && n >= (1ull << 26)) c.store = ST_LDS;   // 32-bit block offsets
     if (c.store == ST_PIPE || c.store == ST_PIPE_NT) {
-        // two tiles (+ the exchange buffer) per wave must fit 64 KiB
+        // two tiles (+ the exchange buffer) per wave must fit the LDS
         c.block = 64;
         if (c.unroll < 16) c.unroll = 16;
-        if (c.unroll > 128) c.unroll = 128;
+        if (c.unroll > 256) c.unroll = 256;
         if (c.exchange < XCH_BPERM || c.exchange > XCH_BPERM2) c.exchange = XCH_BPERM;
         const uint32_t extra = (h->variant == CPRNG_V2_SHMEM && c.exchange == XCH_LDS) ? 64u : 0u;
-        if ((uint64_t)2 * 64 * c.unroll * 4u + extra * 4u > 65536u) c.unroll /= 2;
+        if ((uint64_t)2 * 64 * c.unroll * 4u + extra * 4u > kMaxLdsBytes) c.unroll /= 2;
         if (!c.grid) c.grid = h->n_cu * 2u;
     }
     int rc = begin_timing(h, st);
@@ -461,7 +461,8 @@ int cprng_probe_copy(uint32_t *dst, const uint32_t *src, uint64_t n_words, cprng
 int cprng_probe_valu(uint32_t kind, uint32_t *out, uint32_t n_threads, uint32_t iters, cprng_stream_t stream)
 {
     if (!out || n_threads == 0 || n_threads % 256) return set_error(CPRNG_E_INVAL, "n_threads must be a positive multiple of 256");
-    if (kind > 2) return set_error(CPRNG_E_INVAL, "kind must be 0 (xor), 1 (shift) or 2 (f32 mul/add)");
+    if (kind > 4)
+        return set_error(CPRNG_E_INVAL, "kind must be 0 (xor), 1 (shift), 2 (f32 mul/add), 3 (64-bit shift) or 4 (64-bit add)");
     HIP_TRY(launch_valu_probe(kind, out, n_threads, iters, (hipStream_t)stream), "VALU probe launch");
     return CPRNG_OK;
 }

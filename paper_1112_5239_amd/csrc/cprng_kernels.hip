@@ -1034,15 +1034,40 @@ __global__ __launch_bounds__(256) void k_copy(uint32_t *dst, const uint32_t *src
 // on 8 registers per lane, ordered (inline assembly, so the compiler keeps
 // the order) so that every instruction depends only on one issued four or
 // more instructions earlier.  KIND 0: v_xor_b32; 1: v_lshlrev_b32; 2:
-// v_mul_f32 / v_add_f32.  On gfx950 the classes issue at different rates,
-// which the ALU roofline of the consumption kernel is weighted by.
+// v_mul_f32 / v_add_f32; 3: v_lshlrev_b64; 4: v_lshl_add_u64 (64-bit add).
+// On gfx950 the classes issue at different rates, which the ALU rooflines of
+// the consumption kernel and of the 64-bit-word variant are weighted by.
 #define CPRNG_PROBE_ROUND(OP)                                                              \
     OP " %0, %0, %1\n" OP " %2, %2, %3\n" OP " %4, %4, %5\n" OP " %6, %6, %7\n"            \
     OP " %1, %1, %2\n" OP " %3, %3, %4\n" OP " %5, %5, %6\n" OP " %7, %7, %0\n"
+#define CPRNG_PROBE_SHL64                                                                  \
+    "v_lshlrev_b64 %0, 3, %1\n v_lshlrev_b64 %2, 3, %3\n v_lshlrev_b64 %4, 3, %5\n"       \
+    "v_lshlrev_b64 %6, 3, %7\n v_lshlrev_b64 %1, 3, %2\n v_lshlrev_b64 %3, 3, %4\n"       \
+    "v_lshlrev_b64 %5, 3, %6\n v_lshlrev_b64 %7, 3, %0\n"
+#define CPRNG_PROBE_ADD64                                                                  \
+    "v_lshl_add_u64 %0, %0, 0, %1\n v_lshl_add_u64 %2, %2, 0, %3\n"                          \
+    "v_lshl_add_u64 %4, %4, 0, %5\n v_lshl_add_u64 %6, %6, 0, %7\n"                          \
+    "v_lshl_add_u64 %1, %1, 0, %2\n v_lshl_add_u64 %3, %3, 0, %4\n"                          \
+    "v_lshl_add_u64 %5, %5, 0, %6\n v_lshl_add_u64 %7, %7, 0, %0\n"
 template <int KIND>
 __global__ __launch_bounds__(256) void k_valu_probe(uint32_t *out, uint32_t iters)
 {
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if constexpr (KIND >= 3) {
+        uint64_t b0 = gid, b1 = gid + 1, b2 = gid + 2, b3 = gid + 3, b4 = gid + 4, b5 = gid + 5, b6 = gid + 6,
+                 b7 = gid + 7;
+        for (uint32_t i = 0; i < iters; ++i) {
+            if constexpr (KIND == 3)
+                asm volatile(CPRNG_PROBE_SHL64 CPRNG_PROBE_SHL64 CPRNG_PROBE_SHL64 CPRNG_PROBE_SHL64
+                             : "+v"(b0), "+v"(b1), "+v"(b2), "+v"(b3), "+v"(b4), "+v"(b5), "+v"(b6), "+v"(b7));
+            else
+                asm volatile(CPRNG_PROBE_ADD64 CPRNG_PROBE_ADD64 CPRNG_PROBE_ADD64 CPRNG_PROBE_ADD64
+                             : "+v"(b0), "+v"(b1), "+v"(b2), "+v"(b3), "+v"(b4), "+v"(b5), "+v"(b6), "+v"(b7));
+        }
+        const uint64_t r = b0 ^ b1 ^ b2 ^ b3 ^ b4 ^ b5 ^ b6 ^ b7;
+        out[gid] = (uint32_t)r ^ (uint32_t)(r >> 32);
+        return;
+    }
     uint32_t a0 = gid, a1 = gid + 1, a2 = gid + 2, a3 = gid + 3, a4 = gid + 4, a5 = gid + 5, a6 = gid + 6,
              a7 = gid + 7;
     for (uint32_t i = 0; i < iters; ++i) {
@@ -1062,6 +1087,8 @@ __global__ __launch_bounds__(256) void k_valu_probe(uint32_t *out, uint32_t iter
     out[gid] = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7;
 }
 #undef CPRNG_PROBE_ROUND
+#undef CPRNG_PROBE_SHL64
+#undef CPRNG_PROBE_ADD64
 
 __global__ void k_tail_words(uint32_t *dst, const uint32_t *src, uint64_t begin, uint64_t end, uint32_t value)
 {
@@ -1089,7 +1116,7 @@ hipError_t tile_launch(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
     size_t lds = (size_t)wpb * 64 * S * K * sizeof(uint32_t);
     const int xm = (VAR == 2) ? (int)c.exchange : XCH_BPERM;
     if (xm == XCH_LDS) lds += (size_t)wpb * 64 * S * sizeof(uint32_t);
-    if (lds > 65536) return hipErrorInvalidValue;   // the host keeps tiles within 64 KiB
+    if (lds > kMaxLdsBytes) return hipErrorInvalidValue;   // the host keeps tiles within a workgroup's LDS
     if (c.lds_bytes > lds) lds = c.lds_bytes;
     if constexpr (VAR == 2) {
         if (xm == XCH_LDS)
@@ -1125,7 +1152,7 @@ hipError_t pipe_launch(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
     if (a.n >= (1ull << 26)) return hipErrorInvalidValue;   // in-block offsets are 32-bit
     const int xm = (VAR == 2) ? (int)c.exchange : XCH_BPERM;
     const size_t lds = (size_t)2 * 64 * K * sizeof(uint32_t) + (xm == XCH_LDS ? 64 * sizeof(uint32_t) : 0);
-    if (lds > 65536) return hipErrorInvalidValue;   // the host keeps both tiles within 64 KiB
+    if (lds > kMaxLdsBytes) return hipErrorInvalidValue;   // the host keeps both tiles within a workgroup's LDS
     if constexpr (VAR == 2) {
         if (xm == XCH_LDS)
             hipLaunchKernelGGL((k_generate_pipe<VAR, T, K, NT, XCH_LDS>), dim3(grid), dim3(64), lds, st, a);
@@ -1183,8 +1210,8 @@ hipError_t gen_by_mode(const GenArgs &a, const LaunchCfg &c, hipStream_t st)
     case ST_GENERIC: if constexpr (small) return gen_launch<VAR, T, K, ST_GENERIC>(a, c, st); break;
     case ST_ILV_TILE: if constexpr (K >= 8 && K <= 64) return ilv_launch<VAR, T, K, false>(a, c, st); break;
     case ST_ILV_TILE_NT: if constexpr (K >= 8 && K <= 64) return ilv_launch<VAR, T, K, true>(a, c, st); break;
-    case ST_PIPE: if constexpr (K >= 16 && K <= 128) return pipe_launch<VAR, T, K, false>(a, c, st); break;
-    case ST_PIPE_NT: if constexpr (K >= 16 && K <= 128) return pipe_launch<VAR, T, K, true>(a, c, st); break;
+    case ST_PIPE: if constexpr (K >= 16) return pipe_launch<VAR, T, K, false>(a, c, st); break;
+    case ST_PIPE_NT: if constexpr (K >= 16) return pipe_launch<VAR, T, K, true>(a, c, st); break;
     default: break;
     }
     return hipErrorInvalidValue;
@@ -1309,6 +1336,8 @@ hipError_t launch_valu_probe(uint32_t kind, uint32_t *out, uint32_t n_threads, u
     case 0: hipLaunchKernelGGL(k_valu_probe<0>, dim3(n_threads / 256), dim3(256), 0, st, out, iters); break;
     case 1: hipLaunchKernelGGL(k_valu_probe<1>, dim3(n_threads / 256), dim3(256), 0, st, out, iters); break;
     case 2: hipLaunchKernelGGL(k_valu_probe<2>, dim3(n_threads / 256), dim3(256), 0, st, out, iters); break;
+    case 3: hipLaunchKernelGGL(k_valu_probe<3>, dim3(n_threads / 256), dim3(256), 0, st, out, iters); break;
+    case 4: hipLaunchKernelGGL(k_valu_probe<4>, dim3(n_threads / 256), dim3(256), 0, st, out, iters); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

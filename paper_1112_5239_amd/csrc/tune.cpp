@@ -107,10 +107,11 @@ LaunchCfg default_cfg(uint32_t variant, bool w32, bool consume)
 
 TuneEntry default_entry(uint32_t variant, bool consume)
 {
-    // Measured on MI355X at 2^20 streams x 1024 outputs (see profiles/):
+    // Measured on MI355X at 2^20 streams x 1024 outputs, stream-major layout:
     // V0 prefers long rows per round (K = 128) with non-temporal stores; V2's
-    // exchange chain needs the occupancy of smaller tiles (K = 32) and reads
-    // its neighbours' words from an LDS copy; V1 is VALU-bound and takes K = 64.
+    // exchange chain needs the occupancy of smaller tiles (K = 32, 4 waves per
+    // workgroup) and reads its neighbours' words from an LDS copy; V1 is
+    // ALU-bound and takes K = 64.
     TuneEntry e;
     e.slots = 1;
     e.exchange = XCH_BPERM;
@@ -122,7 +123,7 @@ TuneEntry default_entry(uint32_t variant, bool consume)
         e.block = 256; e.unroll = 64; e.store = ST_LDS_NT; e.waves = 3;
         break;
     default:
-        e.block = 128; e.unroll = 32; e.store = ST_LDS; e.waves = 0; e.exchange = XCH_LDS;
+        e.block = 256; e.unroll = 32; e.store = ST_LDS; e.waves = 0; e.exchange = XCH_LDS;
         break;
     }
     if (consume) {
@@ -139,7 +140,7 @@ uint32_t lds_for_waves(uint32_t block, uint32_t waves_per_cu)
     if (!waves_per_cu) return 0;
     const uint64_t lds_per_cu = 160ull * 1024;
     uint64_t b = lds_per_cu * (block / 64) / waves_per_cu;
-    if (b > 65536) b = 65536;
+    if (b > kMaxLdsBytes) b = kMaxLdsBytes;
     return (uint32_t)(b & ~15ull);
 }
 
@@ -223,7 +224,7 @@ extern "C" int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n, cprng_s
                 if (!lds_mode && (u > 32 || w || sl > 1 || xm != XCH_BPERM)) continue;   // direct: K <= 32
                 if (h->variant != CPRNG_V2_SHMEM && xm != XCH_BPERM) continue;
                 if (lds_mode && u < 16) continue;
-                if (lds_mode && (size_t)b * sl * (u + (xm == XCH_LDS ? 1 : 0)) * 4 > 65536) continue;
+                if (lds_mode && (size_t)b * sl * (u + (xm == XCH_LDS ? 1 : 0)) * 4 > kMaxLdsBytes) continue;
                 LaunchCfg c{b, u, s, lds_for_waves(b, w), sl, xm};
                 std::vector<float> t;
                 for (int r = 0; r < 4 && rc == CPRNG_OK; ++r) {

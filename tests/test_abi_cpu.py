@@ -66,7 +66,7 @@ def test_invalid_arguments_rejected_before_device_work(L):
     assert lib.cprng_consume_qc(None, None, 4, None) == L.E_INVAL
     assert lib.cprng_state_words(None) == L.E_INVAL
     assert lib.cprng_last_kernel_ms(None) < 0
-    assert lib.cprng_probe_valu(3, 16, 256, 1, None) == L.E_INVAL      # no such class
+    assert lib.cprng_probe_valu(5, 16, 256, 1, None) == L.E_INVAL      # no such class
     assert lib.cprng_probe_valu(0, 16, 100, 1, None) == L.E_INVAL      # not a multiple of 256
     assert lib.cprng_probe_valu(0, None, 256, 1, None) == L.E_INVAL
     lib.cprng_destroy(None)                          # no-op
