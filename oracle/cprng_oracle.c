@@ -22,6 +22,9 @@
  *       V1 NAIVE3 : Listing 1 per stream (Algorithm 3 of Section 6.1),
  *       V2 SHMEM  : Algorithm 4 of Section 6.2 (xor128 per thread, mixed with
  *                   two neighbours' previous words through a combination array);
+ *       V3 BBS    : Algorithm 5 of Section 9.1 (the strategy word assembled from
+ *                   eight small Blum-Blum-Shub generators, mixed with two
+ *                   neighbours' previous words as in Algorithm 4);
  *   - the in-kernel consumption mode (quarter-circle hit counts), a use of the
  *     numbers in the spirit of the "versions without storage" of Section 7.
  *
@@ -36,7 +39,14 @@
  *   - Algorithm 4 reads the neighbours' words of the previous step (all threads
  *     of a group read, then all write), group size C = 32, combination arrays
  *     drawn by Fisher-Yates from SplitMix64 as in orc_comb_tables();
- *   - outputs are stream-major: out[s*n + i] (the printed index collides).
+ *   - outputs are stream-major: out[s*n + i] (the printed index collides);
+ *   - Algorithm 5: the eight moduli of orc_bbs_moduli() (products of two
+ *     primes = 3 mod 4 near 256, each below 2^16 so squares fit 32 bits), one
+ *     per BBS slot; the second array index "8+bbs2&7" read as 8 + (bbs2 & 7);
+ *     the sixteen arrangement arrays drawn as in orc_bbs_comb_tables(); the
+ *     arrays are chosen once per call from the slot-1 and slot-2 states at
+ *     the start of the call, and the slot states rotate (slot k -> k+1, 8 ->
+ *     1) at the end of every call that produces outputs.
  *
  * Parity unpinned: the SplitMix64 multiplier constants (no known-answer value
  * is printed in the paper); everything else is pinned by the test suite.
@@ -52,7 +62,7 @@
 #define ORC_EINVAL (-1)
 #define ORC_ENOMEM (-2)
 
-enum { ORC_V0 = 0, ORC_V1 = 1, ORC_V2 = 2 };
+enum { ORC_V0 = 0, ORC_V1 = 1, ORC_V2 = 2, ORC_V3 = 3 };
 
 /* ------------------------------------------------------------------------ */
 /* SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): a counter that advances by  */
@@ -173,6 +183,7 @@ void orc_ci_step_batch(const uint32_t *x, const uint32_t *S, uint32_t *out, uint
 /*   V2: x128{x,y,z,w}, ci_x, t_prev                            (6 words)    */
 /*   V1: xs{lo,hi}, x128{x,y,z,w}{lo,hi}, xwow{x,y,z,w,v,d}{lo,hi}, ci_x     */
 /*                                                              (23 words)   */
+/*   V3: bbs[8] (slot 1..8), ci_x, t_prev                       (10 words)   */
 /* ------------------------------------------------------------------------ */
 int orc_state_words(int variant)
 {
@@ -180,8 +191,34 @@ int orc_state_words(int variant)
     case ORC_V0: return 5;
     case ORC_V1: return 23;
     case ORC_V2: return 6;
+    case ORC_V3: return 10;
     default: return ORC_EINVAL;
     }
+}
+
+/* Moduli of the eight BBS of Algorithm 5 (Section 9.1): the paper asks for
+ * M = p*q with p, q prime and = 3 mod 4, M < 2^16 so that x^2 fits 32 bits,
+ * "primes around 256", and allows a different M per BBS.  Reading: the
+ * primes 211, 223, 227, 239, 251 (all = 3 mod 4), eight distinct products. */
+static const uint32_t orc_bbs_mod[8] = {251u * 239u, 251u * 227u, 251u * 223u, 251u * 211u,
+                                        239u * 227u, 239u * 223u, 239u * 211u, 227u * 223u};
+
+void orc_bbs_moduli(uint32_t out[8])
+{
+    for (int k = 0; k < 8; ++k) out[k] = orc_bbs_mod[k];
+}
+
+/* One BBS step x <- x^2 mod M of slot k (0-based); returns the new state. */
+uint32_t orc_bbs_step(uint32_t *x, int k)
+{
+    *x = (uint32_t)(((uint64_t)*x * (uint64_t)*x) % orc_bbs_mod[k]);
+    return *x;
+}
+
+static uint64_t gcd64(uint64_t a, uint64_t b)
+{
+    while (b) { uint64_t t = a % b; a = b; b = t; }
+    return a;
 }
 
 static uint64_t get64(const uint32_t *w, int k) { return (uint64_t)w[2 * k] | ((uint64_t)w[2 * k + 1] << 32); }
@@ -192,7 +229,10 @@ static void put64(uint32_t *w, int k, uint64_t v) { w[2 * k] = (uint32_t)v; w[2 
  * all zero), then x, then (V2) the initial neighbour word.  V1 draws the
  * xorshift word (until nonzero), the four xor128 words (until not all zero),
  * the five xorwow words (until not all zero), the Weyl counter d, then x.
- * W = 32 keeps the low 32 bits of each draw (rejection on the kept bits). */
+ * W = 32 keeps the low 32 bits of each draw (rejection on the kept bits).
+ * V3 draws, for slots 1..8 in turn, r = D64 mod M (redrawn until r >= 2 and
+ * gcd(r, M) = 1) and keeps r^2 mod M (a quadratic residue coprime to M, the
+ * usual BBS start); then x, then the initial neighbour word. */
 int orc_seed(int variant, int W, uint64_t sigma, uint64_t first_stream,
              uint64_t n_streams, uint32_t *state)
 {
@@ -203,7 +243,15 @@ int orc_seed(int variant, int W, uint64_t sigma, uint64_t first_stream,
         uint64_t ctr = (sigma << 32) + (first_stream + k);
         uint32_t *st = state + k * (uint64_t)nw;
         memset(st, 0, sizeof(uint32_t) * (size_t)nw);
-        if (variant == ORC_V0 || variant == ORC_V2) {
+        if (variant == ORC_V3) {
+            for (int k = 0; k < 8; ++k) {
+                uint64_t M = orc_bbs_mod[k], r;
+                do { r = sm64_draw(&ctr) % M; } while (r < 2 || gcd64(r, M) != 1);
+                st[k] = (uint32_t)((r * r) % M);
+            }
+            st[8] = (uint32_t)sm64_draw(&ctr);
+            st[9] = (uint32_t)sm64_draw(&ctr);
+        } else if (variant == ORC_V0 || variant == ORC_V2) {
             uint32_t a[4];
             do {
                 for (int j = 0; j < 4; ++j) a[j] = (uint32_t)sm64_draw(&ctr);
@@ -257,6 +305,36 @@ int orc_comb_tables(uint32_t C, uint32_t *comb1, uint32_t *comb2)
         if (ok) return ORC_OK;
     }
     return ORC_EINVAL;
+}
+
+/* The sixteen arrangement arrays of Algorithm 5 (not given in the paper).
+ * Reading: sixteen permutations of [0,C), arrays 0..15 in turn, each drawn by
+ * Fisher-Yates as in orc_comb_tables() from one SplitMix64 counter starting
+ * at 2^64-2 and redrawn (the sequence continuing) until it has no fixed
+ * point, so no thread reads its own word.  out: 16*C entries, array a at
+ * out[a*C .. a*C+C-1]. */
+int orc_bbs_comb_tables(uint32_t C, uint32_t *out)
+{
+    if (C < 3 || C > 4096) return ORC_EINVAL;
+    uint64_t ctr = ~0ull - 1ull;
+    for (int a = 0; a < 16; ++a) {
+        uint32_t *arr = out + (size_t)a * C;
+        int ok = 0;
+        for (int attempt = 0; attempt < 1000000 && !ok; ++attempt) {
+            for (uint32_t j = 0; j < C; ++j) arr[j] = j;
+            for (uint32_t j = C - 1; j >= 1; --j) {
+                uint32_t k = (uint32_t)(sm64_draw(&ctr) % (uint64_t)(j + 1));
+                uint32_t tmp = arr[j];
+                arr[j] = arr[k];
+                arr[k] = tmp;
+            }
+            ok = 1;
+            for (uint32_t j = 0; j < C; ++j)
+                if (arr[j] == j) ok = 0;
+        }
+        if (!ok) return ORC_EINVAL;
+    }
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -346,11 +424,80 @@ static int gen_v2_group(uint32_t *st, uint32_t C, const uint32_t *comb1, const u
     return ORC_OK;
 }
 
+/* Strategy bits of one step of Algorithm 5 for one thread, before the
+ * neighbour mixing: the low four bits of BBS1 .. BBS8 (each stepped once),
+ * shifted in four at a time so BBS1's end up highest; then twice a left
+ * shift by 0..3 bits (taken from BBS3, then BBS7) with that many low bits of
+ * BBS1, then BBS2, put in the vacated positions (array_shift = {0,1,3,7}). */
+uint32_t orc_bbs_word(uint32_t b[8])
+{
+    static const uint32_t array_shift[4] = {0u, 1u, 3u, 7u};
+    uint32_t t = 0;
+    for (int k = 0; k < 8; ++k) {
+        t <<= 4;
+        t |= orc_bbs_step(&b[k], k) & 15u;
+    }
+    uint32_t shift = orc_bbs_step(&b[2], 2) & 3u;
+    t <<= shift;
+    t |= orc_bbs_step(&b[0], 0) & array_shift[shift];
+    shift = orc_bbs_step(&b[6], 6) & 3u;
+    t <<= shift;
+    t |= orc_bbs_step(&b[1], 1) & array_shift[shift];
+    return t;
+}
+
+/* V3: Algorithm 5 on one group of C consecutive streams (10-word states).
+ * At the start of the call thread j takes o1 from array (bbs1 & 7) and o2
+ * from array 8 + (bbs2 & 7); each step it mixes its strategy bits with the
+ * previous words of threads o1, o2 of the group (all read before any write),
+ * x = x xor t; at the end of a call with outputs the slot states rotate. */
+static int gen_v3_group(uint32_t *st, uint32_t C, const uint32_t *combs, uint64_t n, uint32_t *out,
+                        uint32_t *strat, uint64_t stride)
+{
+    uint32_t *o1 = malloc(sizeof(uint32_t) * C), *o2 = malloc(sizeof(uint32_t) * C);
+    uint32_t *tprev = malloc(sizeof(uint32_t) * C), *tnext = malloc(sizeof(uint32_t) * C);
+    if (!o1 || !o2 || !tprev || !tnext) {
+        free(o1); free(o2); free(tprev); free(tnext);
+        return ORC_ENOMEM;
+    }
+    for (uint32_t j = 0; j < C; ++j) {
+        const uint32_t *s = st + (size_t)j * 10;
+        o1[j] = combs[(size_t)(s[0] & 7u) * C + j];
+        o2[j] = combs[(size_t)(8u + (s[1] & 7u)) * C + j];
+        tprev[j] = s[9];
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+        for (uint32_t j = 0; j < C; ++j) tnext[j] = orc_bbs_word(st + (size_t)j * 10);
+        for (uint32_t j = 0; j < C; ++j) tnext[j] ^= tprev[o1[j]] ^ tprev[o2[j]];
+        for (uint32_t j = 0; j < C; ++j) {
+            tprev[j] = tnext[j];
+            uint32_t x = orc_ci_step(st[(size_t)j * 10 + 8], tnext[j]);
+            st[(size_t)j * 10 + 8] = x;
+            if (out) out[j * stride + i] = x;
+            if (strat) strat[j * stride + i] = tnext[j];
+        }
+    }
+    for (uint32_t j = 0; j < C; ++j) {
+        uint32_t *s = st + (size_t)j * 10;
+        if (n > 0) {
+            uint32_t last = s[7];
+            for (int k = 7; k > 0; --k) s[k] = s[k - 1];
+            s[0] = last;
+        }
+        s[9] = tprev[j];
+    }
+    free(o1); free(o2); free(tprev); free(tnext);
+    return ORC_OK;
+}
+
 /* Generate n outputs per stream for n_streams streams whose states are in
  * `state` (updated in place, so a second call continues the streams).
  * out (optional) and strat (optional, the strategy words S^n) are
  * stream-major: [s*n + i].  V2 needs n_streams % C == 0 and the two
- * combination arrays; W only matters for V1. */
+ * combination arrays; V3 needs n_streams % C == 0 and the sixteen arrays of
+ * orc_bbs_comb_tables() in comb1 (16*C entries; comb2 unused); W only
+ * matters for V1.  One call is one call of the paper's kernel (V3 chooses its
+ * arrays at the start and rotates its slots at the end). */
 int orc_generate(int variant, int W, uint64_t n_streams, uint32_t *state, uint64_t n,
                  uint32_t *out, uint32_t *strat, uint32_t C,
                  const uint32_t *comb1, const uint32_t *comb2)
@@ -363,6 +510,15 @@ int orc_generate(int variant, int W, uint64_t n_streams, uint32_t *state, uint64
     } else if (variant == ORC_V1) {
         for (uint64_t s = 0; s < n_streams; ++s)
             gen_v1_stream(state + s * 23, W, n, out ? out + s * n : NULL, strat ? strat + s * n : NULL);
+    } else if (variant == ORC_V3) {
+        if (C == 0 || !comb1 || n_streams % C != 0) return ORC_EINVAL;
+        for (uint32_t j = 0; j < 16 * C; ++j)
+            if (comb1[j] >= C) return ORC_EINVAL;
+        for (uint64_t g0 = 0; g0 < n_streams; g0 += C) {
+            int rc = gen_v3_group(state + g0 * 10, C, comb1, n, out ? out + g0 * n : NULL,
+                                  strat ? strat + g0 * n : NULL, n);
+            if (rc) return rc;
+        }
     } else {
         if (C == 0 || !comb1 || !comb2 || n_streams % C != 0) return ORC_EINVAL;
         for (uint32_t j = 0; j < C; ++j)
@@ -404,7 +560,7 @@ int orc_consume_qc(int variant, int W, uint64_t n_streams, uint32_t *state, uint
 {
     int nw = orc_state_words(variant);
     if (nw < 0 || (n & 1)) return ORC_EINVAL;
-    uint64_t group = (variant == ORC_V2) ? C : 1;
+    uint64_t group = (variant == ORC_V2 || variant == ORC_V3) ? C : 1;
     if (group == 0 || n_streams % group != 0) return ORC_EINVAL;
     uint64_t words = group * n;
     uint32_t *buf = malloc(sizeof(uint32_t) * (size_t)(words > 0 ? words : 1));

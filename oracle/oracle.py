@@ -4,7 +4,7 @@ Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
 import this module.  The product library neither imports nor links it.
 
 All arrays are numpy; states are array-of-structures uint32 words per stream
-(V0: 5 words, V2: 6, V1: 23; layout in cprng_oracle.c).
+(V0: 5 words, V2: 6, V1: 23, V3: 10; layout in cprng_oracle.c).
 """
 import ctypes as C
 import os
@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-V0, V1, V2 = 0, 1, 2
+V0, V1, V2, V3 = 0, 1, 2, 3
 
 _lib = None
 _override = None
@@ -81,6 +81,14 @@ def _bind(L):
     L.orc_consume_qc.argtypes = [i32, i32, u64, p, u64, p, u32, p, p]
     L.orc_qc_hit.restype = i32
     L.orc_qc_hit.argtypes = [u32, u32]
+    L.orc_bbs_moduli.restype = None
+    L.orc_bbs_moduli.argtypes = [p]
+    L.orc_bbs_step.restype = u32
+    L.orc_bbs_step.argtypes = [p, i32]
+    L.orc_bbs_word.restype = u32
+    L.orc_bbs_word.argtypes = [p]
+    L.orc_bbs_comb_tables.restype = i32
+    L.orc_bbs_comb_tables.argtypes = [u32, p]
     return L
 
 
@@ -147,9 +155,51 @@ def comb_tables(Cg: int = 32):
     return c1, c2
 
 
+def bbs_moduli() -> np.ndarray:
+    out = np.zeros(8, dtype=np.uint32)
+    lib().orc_bbs_moduli(_ptr(out))
+    return out
+
+
+def bbs_step(x: int, slot: int) -> int:
+    """One BBS step of slot 0..7; returns the new state."""
+    v = C.c_uint32(x)
+    return int(lib().orc_bbs_step(C.byref(v), slot))
+
+
+def bbs_word(states):
+    """Strategy bits of one step of Algorithm 5 from 8 slot states (before the
+    neighbour mixing).  Returns (word, new states)."""
+    b = np.ascontiguousarray(states, dtype=np.uint32).copy()
+    w = int(lib().orc_bbs_word(_ptr(b)))
+    return w, b
+
+
+def bbs_comb_tables(Cg: int = 32) -> np.ndarray:
+    """The sixteen arrangement arrays, shape (16, C)."""
+    out = np.zeros(16 * Cg, dtype=np.uint32)
+    _check(lib().orc_bbs_comb_tables(Cg, _ptr(out)), "bbs_comb_tables")
+    return out.reshape(16, Cg)
+
+
+def _comb_args(variant, comb):
+    """(C, comb1, comb2) for the C entry points: V2 takes (comb1, comb2), V3 the
+    (16, C) arrangement arrays."""
+    if variant == V2:
+        c1, c2 = comb if comb is not None else comb_tables(32)
+        c1 = np.ascontiguousarray(c1, dtype=np.uint32)
+        c2 = np.ascontiguousarray(c2, dtype=np.uint32)
+        return c1.size, c1, c2
+    if variant == V3:
+        arr = np.ascontiguousarray(comb if comb is not None else bbs_comb_tables(32), dtype=np.uint32)
+        return arr.shape[1], arr.reshape(-1), None
+    return 0, None, None
+
+
 def generate(variant: int, state: np.ndarray, n: int, W: int = 64, comb=None,
              want_out: bool = True, want_strategy: bool = False):
-    """Advance `state` (modified in place) by n steps.
+    """Advance `state` (modified in place) by n steps (one call of the paper's
+    kernel).
 
     Returns (out, strategy), each shape (n_streams, n) or None.
     """
@@ -157,12 +207,7 @@ def generate(variant: int, state: np.ndarray, n: int, W: int = 64, comb=None,
     ns = state.shape[0]
     out = np.zeros((ns, n), dtype=np.uint32) if want_out else None
     strat = np.zeros((ns, n), dtype=np.uint32) if want_strategy else None
-    Cg, c1, c2 = 0, None, None
-    if variant == V2:
-        c1, c2 = comb if comb is not None else comb_tables(32)
-        c1 = np.ascontiguousarray(c1, dtype=np.uint32)
-        c2 = np.ascontiguousarray(c2, dtype=np.uint32)
-        Cg = c1.size
+    Cg, c1, c2 = _comb_args(variant, comb)
     _check(lib().orc_generate(variant, W, ns, _ptr(state), n, _ptr(out), _ptr(strat),
                               Cg, _ptr(c1), _ptr(c2)), "generate")
     return out, strat
@@ -172,12 +217,7 @@ def consume_qc(variant: int, state: np.ndarray, n: int, W: int = 64, comb=None) 
     assert state.dtype == np.uint32 and state.flags.c_contiguous
     ns = state.shape[0]
     counts = np.zeros(ns, dtype=np.uint64)
-    Cg, c1, c2 = 0, None, None
-    if variant == V2:
-        c1, c2 = comb if comb is not None else comb_tables(32)
-        c1 = np.ascontiguousarray(c1, dtype=np.uint32)
-        c2 = np.ascontiguousarray(c2, dtype=np.uint32)
-        Cg = c1.size
+    Cg, c1, c2 = _comb_args(variant, comb)
     _check(lib().orc_consume_qc(variant, W, ns, _ptr(state), n, _ptr(counts), Cg,
                                 _ptr(c1), _ptr(c2)), "consume_qc")
     return counts

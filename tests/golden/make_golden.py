@@ -19,6 +19,12 @@ def main():
         f.write("# written by tests/golden/make_golden.py from the oracle's Fisher-Yates draw.\n")
         f.write("comb1 = " + " ".join(str(int(v)) for v in c1) + "\n")
         f.write("comb2 = " + " ".join(str(int(v)) for v in c2) + "\n")
+    arr = O.bbs_comb_tables(32)
+    with open(os.path.join(HERE, "bbs_comb_tables_c32.txt"), "w") as f:
+        f.write("# Default arrangement arrays of the BBS-based variant (Algorithm 5, group size 32),\n")
+        f.write("# written by tests/golden/make_golden.py from the oracle's Fisher-Yates draw.\n")
+        for a in range(16):
+            f.write(f"array{a} = " + " ".join(str(int(v)) for v in arr[a]) + "\n")
 
 
 if __name__ == "__main__":

@@ -12,6 +12,7 @@ import subprocess
 import pytest
 
 from oracle import oracle as O
+from tests import test_oracle_bbs_pins as B
 from tests import test_oracle_pins as P
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -43,6 +44,16 @@ MUTATIONS = [
     ("splitmix gamma", "#define ORC_SM64_GAMMA 0x9E3779B97F4A7C15ull", "#define ORC_SM64_GAMMA 0x9E3779B97F4A7C17ull"),
     ("splitmix shift 30 -> 31", "z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;", "z = (z ^ (z >> 31)) * 0xBF58476D1CE4E5B9ull;"),
     ("continuation loses state", "    st[4] = x;\n}", "    st[4] = x ^ 1u;\n}"),
+    ("alg5 nibbles BBS8 first", "for (int k = 0; k < 8; ++k) {\n        t <<= 4;", "for (int k = 7; k >= 0; --k) {\n        t <<= 4;"),
+    ("alg5 (8+bbs2)&7 precedence", "combs[(size_t)(8u + (s[1] & 7u)) * C + j]", "combs[(size_t)((8u + s[1]) & 7u) * C + j]"),
+    ("alg5 o1 array from slot 2", "o1[j] = combs[(size_t)(s[0] & 7u) * C + j];", "o1[j] = combs[(size_t)(s[1] & 7u) * C + j];"),
+    ("alg5 rotation backwards",
+     "uint32_t last = s[7];\n            for (int k = 7; k > 0; --k) s[k] = s[k - 1];\n            s[0] = last;",
+     "uint32_t first = s[0];\n            for (int k = 0; k < 7; ++k) s[k] = s[k + 1];\n            s[7] = first;"),
+    ("alg5 shift mask 7 -> 3", "array_shift[4] = {0u, 1u, 3u, 7u}", "array_shift[4] = {0u, 1u, 3u, 3u}"),
+    ("alg5 BBS2 not stepped again", "t |= orc_bbs_step(&b[1], 1) & array_shift[shift];", "t |= b[1] & array_shift[shift];"),
+    ("alg5 modulus 251*239 -> 251*241", "251u * 239u, 251u * 227u", "251u * 241u, 251u * 227u"),
+    ("alg5 seed not squared", "st[k] = (uint32_t)((r * r) % M);", "st[k] = (uint32_t)r;"),
 ]
 # Not listed: dropping the all-zero redraw of the seeding is an equivalent
 # mutant in practice (four zero draws have probability 2^-128); the seeding
@@ -80,6 +91,19 @@ def _pins(orc):
     t.append(lambda: P.test_alg4_group_xor_invariant(orc))
     t.append(lambda: P.test_alg4_equal_combs_reduces_to_v0(orc))
     t.append(lambda: P.test_consume_predicate_edges(orc))
+    t.append(B.test_moduli_are_distinct_blum_integers_below_2_16)
+    t.append(B.test_bbs_step_is_modular_squaring)
+    t.append(B.test_seeded_slots_are_coprime_quadratic_residues)
+    for slot in range(8):
+        t.append(lambda slot=slot: B.test_nibble_of_each_bbs_lands_in_its_place(slot))
+    t.append(B.test_extra_shifts_take_their_bits_from_bbs1_and_bbs2)
+    t.append(B.test_word_from_random_states_matches_the_described_bit_placement)
+    t.append(B.test_neighbour_reads_follow_the_selected_arrays)
+    for n in (0, 1, 3):
+        t.append(lambda n=n: B.test_steps_per_slot_and_rotation_at_call_end(n))
+    t.append(B.test_outputs_are_the_prefix_xor_of_the_strategy)
+    t.append(B.test_arrangement_arrays_are_fixed_point_free_permutations_and_golden)
+    t.append(B.test_monobit)
     return t
 
 
