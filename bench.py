@@ -52,8 +52,14 @@ def log(msg):
 
 
 def kernel_source_sha():
-    with open(os.path.join(ROOT, "paper_1112_5239_amd", "csrc", "cprng_kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of every device source (kernel files, their includes, internal.h)."""
+    csrc = os.path.join(ROOT, "paper_1112_5239_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".inc")) or name == "internal.h":
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profile(kernel_tag):

@@ -50,7 +50,17 @@ enum cprng_variant {
     /* Algorithm 4 (Section 6.2): one xor128 per stream mixed with the previous
      * words of two other streams of its group of C streams, chosen by two
      * combination arrays.  6 state words/stream.  Needs n_streams % C == 0. */
-    CPRNG_V2_SHMEM = 2
+    CPRNG_V2_SHMEM = 2,
+    /* Algorithm 5 (Section 9.1): the strategy word is assembled from eight
+     * Blum-Blum-Shub generators x <- x^2 mod M (M = p*q < 2^16, p, q prime and
+     * 3 mod 4; four bits from each, then two shifts of 0..3 bits filled from
+     * second outputs of BBS1 and BBS2) and mixed as in Algorithm 4 with two
+     * streams of the group chosen, once per call, from 16 arrangement arrays
+     * by the low three bits of BBS1's and BBS2's states; at the end of a call
+     * with outputs the eight BBS states rotate (slot k to k+1, 8 to 1).
+     * 10 state words/stream: BBS slots 1..8 (each < 2^16), x, previous word.
+     * Needs n_streams % C == 0.  Library arrangement arrays only. */
+    CPRNG_V3_BBS = 3
 };
 
 enum cprng_flags {
@@ -73,7 +83,7 @@ typedef struct cprng_params {
     uint32_t struct_size;      /* sizeof(cprng_params_t) */
     uint32_t variant;          /* cprng_variant | cprng_flags */
     uint32_t n_streams;        /* >= 1 */
-    uint32_t group;            /* V2 group size C; 0 = 32.  Must divide 64. */
+    uint32_t group;            /* V2/V3 group size C; 0 = 32.  A power of two in [4, 64]. */
     uint64_t seed;             /* base seed sigma */
     const uint32_t *comb1;     /* host, `group` entries in [0,C); NULL = default */
     const uint32_t *comb2;     /* host, `group` entries in [0,C); NULL = default */
@@ -187,6 +197,11 @@ uint32_t cprng_variant(const cprng_t *h);
  * C dividing 64): two permutations of [0,C) with comb1[j] != j,
  * comb2[j] != j and comb1[j] != comb2[j].  comb1/comb2: host, C entries. */
 int cprng_default_combs(uint32_t C, uint32_t *comb1, uint32_t *comb2);
+
+/* The library's 16 arrangement arrays of the BBS variant for group size C (a
+ * power of two in [4, 64]): permutations of [0,C) without fixed points; array
+ * a at out[a*C .. a*C+C-1] (host, 16*C entries).  Errors: E_INVAL. */
+int cprng_default_bbs_combs(uint32_t C, uint32_t *out);
 
 /* Kernel configuration used by the hot-path entry points.  Zero fields mean
  * "autotuned / default".  store: 0 auto, 1 per-lane direct, 2 LDS-transposed,

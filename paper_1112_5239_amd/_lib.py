@@ -10,7 +10,7 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libcprng.so")
 
-V0_PLAIN, V1_NAIVE3, V2_SHMEM = 0, 1, 2
+V0_PLAIN, V1_NAIVE3, V2_SHMEM, V3_BBS = 0, 1, 2, 3
 F_INTERLEAVED = 1 << 8
 F_V1_W32 = 1 << 9
 
@@ -56,7 +56,7 @@ class Tuning(C.Structure):
 EXPORTED = [
     "cprng_create", "cprng_create_ex", "cprng_destroy", "cprng_generate", "cprng_consume_qc",
     "cprng_generate_ragged", "cprng_generate_requests", "cprng_state_words", "cprng_get_state",
-    "cprng_set_state", "cprng_n_streams", "cprng_variant", "cprng_default_combs",
+    "cprng_set_state", "cprng_n_streams", "cprng_variant", "cprng_default_combs", "cprng_default_bbs_combs",
     "cprng_set_tuning", "cprng_get_tuning", "cprng_autotune", "cprng_autotune_ragged",
     "cprng_enable_timing", "cprng_last_kernel_ms", "cprng_probe_fill", "cprng_probe_copy", "cprng_probe_valu",
     "cprng_strerror", "cprng_last_error", "cprng_now_ns", "cprng_server_create", "cprng_server_submit",
@@ -91,6 +91,7 @@ def lib():
         "cprng_n_streams": (u32, [vp]),
         "cprng_variant": (u32, [vp]),
         "cprng_default_combs": (i32, [u32, vp, vp]),
+        "cprng_default_bbs_combs": (i32, [u32, vp]),
         "cprng_set_tuning": (i32, [vp, C.POINTER(Tuning)]),
         "cprng_get_tuning": (i32, [vp, C.POINTER(Tuning)]),
         "cprng_autotune": (i32, [vp, vp, u64, vp]),
@@ -213,6 +214,13 @@ def cprng_n_streams(h: int) -> int:
 
 def cprng_variant(h: int) -> int:
     return int(lib().cprng_variant(h))
+
+
+def cprng_default_bbs_combs(Cg: int):
+    """The library's 16 arrangement arrays of the BBS variant, as 16 lists of Cg."""
+    arr = (C.c_uint32 * (16 * Cg))()
+    _check(lib().cprng_default_bbs_combs(Cg, C.cast(arr, C.c_void_p)), "cprng_default_bbs_combs")
+    return [list(arr[a * Cg:(a + 1) * Cg]) for a in range(16)]
 
 
 def cprng_default_combs(Cg: int):

@@ -62,6 +62,7 @@ void fill_args(const cprng_t *h, GenArgs &a)
     a.group = h->group ? h->group : 1;
     std::memcpy(a.comb1, h->comb1, 64);
     std::memcpy(a.comb2, h->comb2, 64);
+    std::memcpy(a.combs16, h->combs16, sizeof a.combs16);
 }
 
 int begin_timing(cprng_t *h, hipStream_t st)
@@ -122,6 +123,19 @@ int create_impl(const cprng_params_t *p, cprng_t **out)
             h->comb1[j] = (uint8_t)c1[j % C];
             h->comb2[j] = (uint8_t)c2[j % C];
         }
+    }
+
+    if (var == CPRNG_V3_BBS) {
+        const uint32_t C = p->group ? p->group : 32u;
+        if (!is_pow2(C) || C < 4 || C > 64)
+            return set_error(CPRNG_E_UNSUPPORTED, "V3 group size must be a power of two in [4, 64] (a group lies in one wave)");
+        if (p->n_streams % C != 0) return set_error(CPRNG_E_INVAL, "V3 needs n_streams % group == 0");
+        if (p->comb1 || p->comb2) return set_error(CPRNG_E_UNSUPPORTED, "V3 uses the library's arrangement arrays");
+        uint32_t arr[16 * 64];
+        if (!default_bbs_combs(C, arr)) return set_error(CPRNG_E_INVAL, "no arrangement arrays for this group size");
+        h->group = C;
+        for (uint32_t a = 0; a < 16; ++a)
+            for (uint32_t j = 0; j < 64; ++j) h->combs16[a][j] = (uint8_t)arr[a * C + j % C];
     }
 
     int dev = p->device;
@@ -213,6 +227,11 @@ int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchC
     fill_args(h, a);
     a.out = out;
     a.n = n;
+    // The BBS variant's arrays differ per thread, so the two-steps-per-read
+    // exchange (which follows a neighbour's neighbours) does not apply.
+    if (h->variant == CPRNG_V3_BBS && c.exchange == XCH_BPERM2) c.exchange = XCH_BPERM;
+    // The BBS variant is ALU-bound: its kernels are built for K <= 64 only.
+    if (h->variant == CPRNG_V3_BBS && c.unroll > 64) c.unroll = 64;
     if (h->flags & CPRNG_F_INTERLEAVED) {
         const bool tile_ok = ((uintptr_t)out % 16u) == 0 && (h->ns % 4u) == 0;
         if (!tile_ok || (c.store != ST_ILV_TILE && c.store != ST_ILV_TILE_NT)) c.store = ST_INTERLEAVED;
@@ -229,7 +248,7 @@ int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchC
             if (c.unroll > 64) c.unroll = 64;
             if (c.exchange < XCH_BPERM || c.exchange > XCH_BPERM2) c.exchange = XCH_BPERM;
             if (c.slots != 2) c.slots = 1;      // 2: double-buffered tiles
-            const uint32_t extra = (h->variant == CPRNG_V2_SHMEM && c.exchange == XCH_LDS) ? 1u : 0u;
+            const uint32_t extra = (has_exchange(h->variant) && c.exchange == XCH_LDS) ? 1u : 0u;
             if (c.block == 1024 && c.unroll > 32) c.unroll = 32;
             while ((uint64_t)(c.slots * c.unroll + extra) * c.block * 4u > kMaxLdsBytes) {
                 if (c.unroll > 8) c.unroll /= 2;
@@ -249,7 +268,7 @@ int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchC
         if (c.slots != 1 && c.slots != 2 && c.slots != 4) c.slots = 1;
         if (c.exchange < XCH_BPERM || c.exchange > XCH_BPERM2) c.exchange = XCH_BPERM;
         // tile (+ the exchange buffer) per block must fit the LDS
-        const uint32_t extra = (h->variant == CPRNG_V2_SHMEM && c.exchange == XCH_LDS) ? 1u : 0u;
+        const uint32_t extra = (has_exchange(h->variant) && c.exchange == XCH_LDS) ? 1u : 0u;
         while (c.block > 64 && (uint64_t)c.block * c.slots * (c.unroll + extra) * 4u > kMaxLdsBytes) c.block -= 64;
         while (c.slots > 1 && (uint64_t)c.block * c.slots * (c.unroll + extra) * 4u > kMaxLdsBytes) c.slots /= 2;
         if ((uint64_t)c.block * c.slots * (c.unroll + extra) * 4u > kMaxLdsBytes) c.unroll /= 2;
@@ -261,7 +280,7 @@ int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchC
         if (c.unroll < 16) c.unroll = 16;
         if (c.unroll > 256) c.unroll = 256;
         if (c.exchange < XCH_BPERM || c.exchange > XCH_BPERM2) c.exchange = XCH_BPERM;
-        const uint32_t extra = (h->variant == CPRNG_V2_SHMEM && c.exchange == XCH_LDS) ? 64u : 0u;
+        const uint32_t extra = (has_exchange(h->variant) && c.exchange == XCH_LDS) ? 64u : 0u;
         if ((uint64_t)2 * 64 * c.unroll * 4u + extra * 4u > kMaxLdsBytes) c.unroll /= 2;
         if (!c.grid) c.grid = h->n_cu * 2u;
     }
@@ -378,6 +397,9 @@ int cprng_set_state(cprng_t *h, const uint32_t *host_words, size_t n_words)
             if (w32)
                 for (int k = 1; k < 22; k += 2)
                     if (w[k]) return set_error(CPRNG_E_INVAL, "32-bit-word V1 state has a nonzero high half");
+        } else if (h->variant == CPRNG_V3_BBS) {
+            for (int k = 0; k < 8; ++k)
+                if (w[k] >= 65536u) return set_error(CPRNG_E_INVAL, "BBS slot state must be below 2^16");
         } else if ((w[0] | w[1] | w[2] | w[3]) == 0) {
             return set_error(CPRNG_E_INVAL, "xor128 words all zero");
         }
@@ -388,6 +410,14 @@ int cprng_set_state(cprng_t *h, const uint32_t *host_words, size_t n_words)
         for (uint32_t k = 0; k < h->words; ++k) soa[k * (uint64_t)h->ns + s] = host_words[s * h->words + k];
     HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
     HIP_TRY(hipMemcpy(h->d_state, soa.data(), nw * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy state");
+    return CPRNG_OK;
+}
+
+int cprng_default_bbs_combs(uint32_t C, uint32_t *out)
+{
+    if (!out) return set_error(CPRNG_E_INVAL, "NULL argument");
+    if (C < 4 || C > 64 || !is_pow2(C)) return set_error(CPRNG_E_INVAL, "C must be a power of two in [4, 64]");
+    if (!default_bbs_combs(C, out)) return set_error(CPRNG_E_INVAL, "no arrangement arrays found");
     return CPRNG_OK;
 }
 

@@ -26,6 +26,8 @@ void seed_streams(int variant, bool w32, uint64_t sigma, uint64_t first, uint64_
                   uint32_t *aos);
 // Default combination arrays for a group of C streams (C >= 3).
 bool default_combs(uint32_t C, uint32_t *comb1, uint32_t *comb2);
+// Default 16 arrangement arrays of the BBS variant (out: 16*C entries).
+bool default_bbs_combs(uint32_t C, uint32_t *out);
 
 // ---- GF(2) jump polynomials (gf2.cpp) ------------------------------------
 // Elements of GF(2)[X]/(q) with q the annihilating polynomial of the V0
@@ -75,6 +77,7 @@ struct cprng {
     uint32_t group = 0;         // V2
     uint8_t comb1[64] = {0};
     uint8_t comb2[64] = {0};
+    uint8_t combs16[16][64] = {{0}};   // V3
     uint32_t *d_state = nullptr;        // SoA, words x ns
     uint32_t *d_state_next = nullptr;   // V0 segment kernels: end states
     uint32_t n_cu = 0;

@@ -13,6 +13,15 @@ namespace cprng_impl {
 // LDS a gfx950 workgroup may allocate (the whole 160 KiB of a CU).
 constexpr uint32_t kMaxLdsBytes = 160u * 1024u;
 
+// Moduli of the eight BBS slots of Algorithm 5 (Section 9.1): products of two
+// primes = 3 mod 4 near 256, each below 2^16 so a square of a state below
+// 2^16 fits 32 bits.
+constexpr uint32_t kBbsModuli[8] = {251u * 239u, 251u * 227u, 251u * 223u, 251u * 211u,
+                                    239u * 227u, 239u * 223u, 239u * 211u, 227u * 223u};
+
+// True for the variants that mix neighbours' words (group size C).
+constexpr bool has_exchange(uint32_t variant) { return variant == CPRNG_V2_SHMEM || variant == CPRNG_V3_BBS; }
+
 // Store modes of the plain generate kernel.
 enum StoreMode : int {
     ST_DIRECT = 1,        // each lane stores its own stream's 16-byte quads
@@ -41,9 +50,10 @@ struct GenArgs {
     uint64_t *counts;      // hit counts (consume)
     uint64_t n;            // outputs per stream
     uint32_t ns;           // number of streams
-    uint32_t group;        // V2 group size C (divides 64)
+    uint32_t group;        // V2/V3 group size C (divides 64)
     uint8_t comb1[64];     // V2: comb1[j mod C]
     uint8_t comb2[64];
+    uint8_t combs16[16][64];   // V3: arrangement array a, entry j mod C
 };
 
 struct LaunchCfg {
@@ -61,6 +71,17 @@ hipError_t launch_generate(const GenArgs &a, int variant, int w32, const LaunchC
                            hipStream_t st);
 hipError_t launch_consume(const GenArgs &a, int variant, int w32, const LaunchCfg &c,
                           hipStream_t st);
+
+// Per-variant generate / consume launches, each variant's kernels in a
+// source file of their own (gen_v0.hip .. gen_v3.hip).
+hipError_t launch_generate_v0(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
+hipError_t launch_generate_v1(const GenArgs &a, bool w32, const LaunchCfg &c, hipStream_t st);
+hipError_t launch_generate_v2(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
+hipError_t launch_generate_v3(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
+hipError_t launch_consume_v0(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
+hipError_t launch_consume_v1(const GenArgs &a, bool w32, const LaunchCfg &c, hipStream_t st);
+hipError_t launch_consume_v2(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
+hipError_t launch_consume_v3(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
 
 // A run of consecutive outputs of one stream (a batched stream or a request)
 // for the chunked kernels.  The run is cut into chunks ("segments"):

@@ -34,6 +34,7 @@ int words_per_stream(int variant)
     case CPRNG_V0_PLAIN: return 5;
     case CPRNG_V1_NAIVE3: return 23;
     case CPRNG_V2_SHMEM: return 6;
+    case CPRNG_V3_BBS: return 10;
     default: return -1;
     }
 }
@@ -44,6 +45,9 @@ int words_per_stream(int variant)
 //   V1   : xorshift word (redrawn while zero), xor128 x,y,z,w (redrawn while
 //          all zero), xorwow x,y,z,w,v (redrawn while all zero), xorwow d,
 //          then x.  With 32-bit words each draw keeps its low half.
+//   V3   : for BBS slots 1..8, r = draw mod M (redrawn while r < 2 or r shares
+//          a factor with M), state r^2 mod M; then x, then the initial mixed
+//          word.
 void seed_streams(int variant, bool w32, uint64_t sigma, uint64_t first, uint64_t count,
                   uint32_t *aos)
 {
@@ -53,7 +57,21 @@ void seed_streams(int variant, bool w32, uint64_t sigma, uint64_t first, uint64_
         SplitMix64 r{(sigma << 32) + first + k};
         uint32_t *st = aos + k * (uint64_t)nw;
         std::memset(st, 0, sizeof(uint32_t) * nw);
-        if (variant == CPRNG_V0_PLAIN || variant == CPRNG_V2_SHMEM) {
+        if (variant == CPRNG_V3_BBS) {
+            for (int k = 0; k < 8; ++k) {
+                const uint64_t M = kBbsModuli[k];
+                uint64_t v;
+                for (;;) {
+                    v = r.next() % M;
+                    uint64_t a = v, b = M;        // gcd(v, M)
+                    while (b) { const uint64_t t = a % b; a = b; b = t; }
+                    if (v >= 2 && a == 1) break;
+                }
+                st[k] = (uint32_t)(v * v % M);
+            }
+            st[8] = r.next32();
+            st[9] = r.next32();
+        } else if (variant == CPRNG_V0_PLAIN || variant == CPRNG_V2_SHMEM) {
             uint32_t w[4];
             do {
                 for (int j = 0; j < 4; ++j) w[j] = r.next32();
@@ -106,6 +124,33 @@ bool default_combs(uint32_t C, uint32_t *comb1, uint32_t *comb2)
         if (ok) return true;
     }
     return false;
+}
+
+// The paper leaves Algorithm 5's 16 arrangement arrays unspecified.  The
+// library's default: arrays 0..15 in turn, each a Fisher-Yates shuffle of
+// [0,C) from one SplitMix64 counter starting at 2^64-2, reshuffled
+// (continuing the counter) until no entry maps to itself.
+bool default_bbs_combs(uint32_t C, uint32_t *out)
+{
+    if (C < 3) return false;
+    SplitMix64 r{~0ull - 1ull};
+    for (int a = 0; a < 16; ++a) {
+        uint32_t *arr = out + (size_t)a * C;
+        bool ok = false;
+        for (int attempt = 0; attempt < 1000000 && !ok; ++attempt) {
+            for (uint32_t j = 0; j < C; ++j) arr[j] = j;
+            for (uint32_t j = C - 1; j >= 1; --j) {
+                const uint32_t k = (uint32_t)(r.next() % (uint64_t)(j + 1));
+                const uint32_t t = arr[j];
+                arr[j] = arr[k];
+                arr[k] = t;
+            }
+            ok = true;
+            for (uint32_t j = 0; j < C && ok; ++j) ok = arr[j] != j;
+        }
+        if (!ok) return false;
+    }
+    return true;
 }
 
 }  // namespace cprng_impl

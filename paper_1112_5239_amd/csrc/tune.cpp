@@ -222,7 +222,7 @@ extern "C" int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n, cprng_s
                 for (uint32_t xm : xch_opts) {
                 const bool lds_mode = s == ST_LDS || s == ST_LDS_NT;
                 if (!lds_mode && (u > 32 || w || sl > 1 || xm != XCH_BPERM)) continue;   // direct: K <= 32
-                if (h->variant != CPRNG_V2_SHMEM && xm != XCH_BPERM) continue;
+                if (!has_exchange(h->variant) && xm != XCH_BPERM) continue;
                 if (lds_mode && u < 16) continue;
                 if (lds_mode && (size_t)b * sl * (u + (xm == XCH_LDS ? 1 : 0)) * 4 > kMaxLdsBytes) continue;
                 LaunchCfg c{b, u, s, lds_for_waves(b, w), sl, xm};

@@ -8,7 +8,7 @@ import numpy as np
 from . import _lib as L
 
 _VARIANTS = {"v0": L.V0_PLAIN, "plain": L.V0_PLAIN, "v1": L.V1_NAIVE3, "naive3": L.V1_NAIVE3,
-             "v2": L.V2_SHMEM, "shmem": L.V2_SHMEM}
+             "v2": L.V2_SHMEM, "shmem": L.V2_SHMEM, "v3": L.V3_BBS, "bbs": L.V3_BBS}
 
 
 def _torch():

@@ -83,6 +83,15 @@ def test_default_combs_match_the_oracle_reading(L, orc):
         L.cprng_default_combs(2)
 
 
+def test_default_bbs_arrays_match_the_oracle_reading(L, orc):
+    # Algorithm 5's sixteen arrangement arrays: library and oracle draw them
+    # independently from the same reading.
+    for Cg in (4, 8, 16, 32, 64):
+        assert L.cprng_default_bbs_combs(Cg) == orc.bbs_comb_tables(Cg).tolist()
+    with pytest.raises(L.CprngError):
+        L.cprng_default_bbs_combs(3)
+
+
 def test_header_is_plain_c(tmp_path):
     # The boundary header compiles as C99 on its own (no HIP or torch types).
     src = tmp_path / "t.c"
