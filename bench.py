@@ -32,20 +32,26 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 CU, CLOCK_HZ = 256, 2.4e9      # MI355X compute units, peak engine clock
-# VALU lanes per CU per clock by instruction class on gfx950: xor/add/
-# f32 mul/add issue two wave64 instructions per CU-clock (the rate behind the
-# published 157.3 TFLOP/s fp32 vector peak), 32-bit shifts one.
+# VALU issue limits of gfx950 from its unit counts, in lanes per CU per
+# clock: 4 SIMDs x 16 lanes = 64 for the single-rate instruction classes
+# (left shifts, min/max, int<->float conversions, integer multiplies and
+# 24-bit multiply-adds, three-operand integer ops, bit-field ops and byte
+# permutes, bit counts, 64-bit shifts and adds), and 128 for any VALU
+# instruction (the rate behind the published 157.3 TFLOP/s fp32 vector peak;
+# xor/and/or/add/sub, right shifts and f32 add/mul/fma reach it).  A kernel
+# with N VALU instructions per number, S of them single-rate, produces at most
+# CU * clock * 64 / max(N / 2, S) numbers/s.
 LANES_FAST, LANES_SHIFT = 128, 64
-# VALU instructions per generated number in the consumption kernels' loop
-# (gfx950 code object of cprng_kernels.hip, unroll 16): shift-class
-# (v_lshlrev/v_lshrrev) and everything else.
-CONSUME_MIX = {"v0": (71 / 16, 162 / 16), "v2": (71 / 16, 194 / 16)}
-# The 64-bit-word variant (V1) per generated number, same code object
-# (interleaved tile loop, 32 numbers): 28 v_xor_b32 and 11.25 64-bit shifts
-# and adds (v_lshlrev_b64, v_lshrrev_b64, v_lshl_add_u64).  The issue rate of
-# the 64-bit class is not published; it is taken from the probe of the same run.
-V1_MIX = (896 / 32, (160 + 128 + 72) / 32)
-
+# (N, S) per generated number, counted in the loop body of each kernel in the
+# gfx950 code object (hipcc -S of gen_vN.hip; the unrolled loop of the
+# configuration that runs by default).
+ALU_MIX = {
+    "v0_consume": (233 / 16, 33 / 16),      # k_consume<0, u32, 16>
+    "v2_consume": (265 / 16, 33 / 16),      # k_consume<2, u32, 16>
+    "v1_generate": (1257 / 32, 360 / 32),   # k_generate_ilv<1, u64, 32, 256, NT>: 28 xor + 11.25 64-bit
+    "v3_generate": (2181 / 16, 436 / 16),   # k_generate_ilv<3, u32, 16, 512, NT, LDS exchange>
+    "v3_consume": (2281 / 16, 449 / 16),    # k_consume<3, u32, 16>
+}
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -136,19 +142,18 @@ def run_paper(torch, G, L, args, interleaved, steps=None, warmup=None):
     return ms, wall, numbers, alg_bytes, achieved
 
 
-def v1_alu_roofline(gn, probe):
-    """ALU roofline of V1 (Gnumbers/s): fast class at its published rate, the
-    64-bit class at the slower of the two 64-bit probe rates."""
-    n_fast, n_64 = V1_MIX
-    lanes64 = 64 * min(probe["shift64"], probe["add64"])
-    peak = CU * CLOCK_HZ / (n_fast / LANES_FAST + n_64 / lanes64) / 1e9
+def alu_roofline(gn, key):
+    """ALU roofline (Gnumbers/s) of a kernel from its per-number VALU mix."""
+    n, single = ALU_MIX[key]
+    peak = CU * CLOCK_HZ * 64 / max(n / 2, single) / 1e9
     return {"bound": "alu", "achieved": round(gn, 1), "peak": round(peak, 1), "unit": "Gnumbers/s",
-            "frac": round(gn / peak, 4), "lanes_per_clk_64bit": round(lanes64, 1)}
+            "frac": round(gn / peak, 4), "valu_per_number": round(n, 3),
+            "single_rate_per_number": round(single, 3)}
 
 
 def run_plain(torch, G, variant, args, interleaved=False):
     ns, n = 1 << 20, 1024
-    words = {"v0": 5, "v1": 23}[variant]
+    words = {"v0": 5, "v1": 23, "v3": 10}[variant]
     g = G.Generator(ns, variant, seed=1, interleaved=interleaved)
     shape = (n, ns) if interleaved else (ns, n)
     out = torch.empty(shape, dtype=torch.int32, device="cuda")
@@ -203,18 +208,15 @@ def run_valu_probes(torch, L):
 def run_consume(torch, G, args):
     ns, n = 1 << 20, 1 << 16
     res = {}
-    for variant in ("v2", "v0"):
+    for variant in ("v2", "v0", "v3"):
         g = G.Generator(ns, variant, seed=3)
         counts = torch.empty(ns, dtype=torch.int64, device="cuda")
         ms, _ = timed(torch, lambda: g.consume_qc(n, counts=counts), 3, 1)
         g.close()
         gn = ns * n / (ms / 1e3) / 1e9
-        n_shift, n_fast = CONSUME_MIX[variant]
-        peak = CU * CLOCK_HZ / (n_shift / LANES_SHIFT + n_fast / LANES_FAST) / 1e9
-        res[variant] = {"ms": round(ms, 3), "gnumbers_per_s": round(gn, 1),
-                        "valu_instr_per_number": {"shift": round(n_shift, 3), "other": round(n_fast, 3)},
-                        "roofline": {"bound": "alu", "achieved": round(gn, 1), "peak": round(peak, 1),
-                                     "unit": "Gnumbers/s", "frac": round(gn / peak, 4)}}
+        res[variant] = {"ms": round(ms, 3), "gnumbers_per_s": round(gn, 1)}
+        if f"{variant}_consume" in ALU_MIX:
+            res[variant]["roofline"] = alu_roofline(gn, f"{variant}_consume")
     return {"workload": "2^36 uint32 (2^20 streams x 2^16) -> quarter-circle hit counts, seed 3", **res}
 
 
@@ -302,12 +304,12 @@ def main():
         log(f"[bench] v2 stream-major: {extra['v2_stream_major']}")
         extra["valu_probe"] = run_valu_probes(torch, L)
         log(f"[bench] valu probe: {extra['valu_probe']}")
-        for variant in ("v0", "v1"):
+        for variant in ("v0", "v1", "v3"):
             for ilv in (True, False):
                 key = f"{variant}_{'interleaved' if ilv else 'stream_major'}"
                 extra[key] = run_plain(torch, G, variant, args, interleaved=ilv)
-                if variant == "v1":
-                    extra[key]["roofline"] = v1_alu_roofline(extra[key]["gnumbers_per_s"], extra["valu_probe"])
+                if f"{variant}_generate" in ALU_MIX:
+                    extra[key]["roofline"] = alu_roofline(extra[key]["gnumbers_per_s"], f"{variant}_generate")
                 log(f"[bench] {key}: {extra[key]}")
         extra["ragged"] = run_ragged(torch, G, args, extra["v0_stream_major"]["gnumbers_per_s"])
         log(f"[bench] ragged: {extra['ragged']}")

@@ -222,7 +222,9 @@ typedef struct cprng_tuning {
                                   layout's tiles take 256, 512 or 1024 (streams per tile) */
     uint32_t unroll;           /* outputs per stream per round: 8, 16, 32 (direct);
                                   16..256, powers of two (LDS-transposed; chunk
-                                  kernels 32..256); 16..128 (pipelined) */
+                                  kernels 32..256); 16..128 (pipelined); the
+                                  V3 (BBS) kernels are built for 8..32 only and
+                                  larger values are lowered to 32 */
     uint32_t store;            /* store mode, see above */
     uint32_t chunk;            /* ragged/requests: outputs per chunk (multiple of 64) */
     uint32_t waves_per_cu;     /* ragged/requests (store 1/2/4) and pipelined generate:

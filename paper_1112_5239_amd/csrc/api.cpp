@@ -174,13 +174,18 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
         // over the XCDs in bands.  Measured on MI355X at 2^20 streams x 1024:
         // 1,024 streams x 16 steps, two tile buffers (128 KiB of LDS),
         // non-temporal stores, V2 exchange by cross-lane reads; V1,
-        // VALU-bound, 256 x 32 with one buffer.  Direct store modes select
-        // the per-lane dword kernel.
+        // VALU-bound, 256 x 32 with one buffer; V3, VALU-bound, 512 x 16
+        // with one buffer and the LDS word exchange.  Direct store modes
+        // select the per-lane dword kernel.
         LaunchCfg c{1024, 16, ST_ILV_TILE_NT, 0, 2, XCH_BPERM, 0};
         if (h->variant == CPRNG_V1_NAIVE3) {
             c.block = 256;
             c.unroll = 32;
             c.slots = 1;
+        } else if (h->variant == CPRNG_V3_BBS) {
+            c.block = 512;
+            c.slots = 1;
+            c.exchange = XCH_LDS;
         }
         if (h->tuning.streams_per_lane) c.slots = h->tuning.streams_per_lane;
         if (h->tuning.store == ST_DIRECT || h->tuning.store == ST_DIRECT_NT) c.store = ST_INTERLEAVED;
@@ -230,8 +235,8 @@ int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchC
     // The BBS variant's arrays differ per thread, so the two-steps-per-read
     // exchange (which follows a neighbour's neighbours) does not apply.
     if (h->variant == CPRNG_V3_BBS && c.exchange == XCH_BPERM2) c.exchange = XCH_BPERM;
-    // The BBS variant is ALU-bound: its kernels are built for K <= 64 only.
-    if (h->variant == CPRNG_V3_BBS && c.unroll > 64) c.unroll = 64;
+    // The BBS variant is ALU-bound: its kernels are built for K <= 32 only.
+    if (h->variant == CPRNG_V3_BBS && c.unroll > 32) c.unroll = 32;
     if (h->flags & CPRNG_F_INTERLEAVED) {
         const bool tile_ok = ((uintptr_t)out % 16u) == 0 && (h->ns % 4u) == 0;
         if (!tile_ok || (c.store != ST_ILV_TILE && c.store != ST_ILV_TILE_NT)) c.store = ST_INTERLEAVED;

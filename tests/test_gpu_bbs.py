@@ -66,9 +66,9 @@ def test_exchange_modes(orc, G, exchange, unroll, block, slots):
 
 
 @pytest.mark.parametrize("store", [7, 8])
-@pytest.mark.parametrize("unroll", [16, 64, 128])
+@pytest.mark.parametrize("unroll", [16, 32, 128])
 def test_pipelined_persistent(orc, G, store, unroll):
-    # unroll 128 is capped to 64 for this variant.
+    # unroll 128 is lowered to 32 for this variant.
     _check(orc, G, 4096, (1024, 1000), sigma=33, tuning=dict(store=store, unroll=unroll))
 
 
