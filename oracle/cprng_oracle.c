@@ -25,6 +25,11 @@
  *       V3 BBS    : Algorithm 5 of Section 9.1 (the strategy word assembled from
  *                   eight small Blum-Blum-Shub generators, mixed with two
  *                   neighbours' previous words as in Algorithm 4);
+ *       V4 XOR64  : Algorithm 4 with Marsaglia's xor64 as the per-thread
+ *                   generator, the generator Section 7 names for the
+ *                   optimized versions measured in its first figure;
+ *     and, for V1, the xor64 alternative for Listing 1's "xorshift" (flag
+ *     ORC_F_XOR64);
  *   - the in-kernel consumption mode (quarter-circle hit counts), a use of the
  *     numbers in the spirit of the "versions without storage" of Section 7.
  *
@@ -46,10 +51,16 @@
  *     the sixteen arrangement arrays drawn as in orc_bbs_comb_tables(); the
  *     arrays are chosen once per call from the slot-1 and slot-2 states at
  *     the start of the call, and the slot states rotate (slot k -> k+1, 8 ->
- *     1) at the end of every call that produces outputs.
+ *     1) at the end of every call that produces outputs;
+ *   - xor64 is the 64-bit xorshift with triple (13,7,17) (left, right, left),
+ *     one of Marsaglia's full-period 64-bit triples; V4's 32-bit word is the
+ *     xor of the two 32-bit halves of each 64-bit output, the convention
+ *     Listing 1 applies to its 64-bit generators.
  *
  * Parity unpinned: the SplitMix64 multiplier constants (no known-answer value
- * is printed in the paper); everything else is pinned by the test suite.
+ * is printed in the paper) and the order of the xor64 triple, (13,7,17)
+ * rather than its mirror (17,7,13), which is also full period; everything
+ * else is pinned by the test suite.
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared (no fast-math).
  */
@@ -62,7 +73,10 @@
 #define ORC_EINVAL (-1)
 #define ORC_ENOMEM (-2)
 
-enum { ORC_V0 = 0, ORC_V1 = 1, ORC_V2 = 2, ORC_V3 = 3 };
+enum { ORC_V0 = 0, ORC_V1 = 1, ORC_V2 = 2, ORC_V3 = 3, ORC_V4 = 4 };
+/* V1 modifier: xor64 (13,7,17) in place of the (13,17,5) triple as the first
+ * generator of Listing 1 (64-bit words only). */
+#define ORC_F_XOR64 0x100
 
 /* ------------------------------------------------------------------------ */
 /* SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): a counter that advances by  */
@@ -122,6 +136,11 @@ uint64_t orc_x128_step(uint64_t s[4], int W)
     return s[3];
 }
 
+/* Marsaglia's xor64: the 64-bit xorshift with triple (13,7,17), named by
+ * Section 7 as the generator of the optimized versions.  Returns the new
+ * word. */
+uint64_t orc_xor64_step(uint64_t *y) { return orc_xs_step(y, 13, 7, 17, 64); }
+
 /* Marsaglia's xorwow (third generator of Listing 1).  s = {x,y,z,w,v,d};
  * returns d + v after the Weyl increment of d. */
 uint64_t orc_xwow_step(uint64_t s[6], int W)
@@ -138,7 +157,8 @@ uint64_t orc_xwow_step(uint64_t s[6], int W)
 }
 
 /* n consecutive outputs of one generator from a given state (test helper).
- * kind: 0 = xorshift(13,17,5), 1 = xor128, 2 = xorwow.  State is updated. */
+ * kind: 0 = xorshift(13,17,5), 1 = xor128, 2 = xorwow, 3 = xor64 (W = 64
+ * only).  State is updated. */
 int orc_gen_outputs(int kind, int W, uint64_t *state, uint64_t n, uint64_t *out)
 {
     if (W != 32 && W != 64) return ORC_EINVAL;
@@ -146,6 +166,7 @@ int orc_gen_outputs(int kind, int W, uint64_t *state, uint64_t n, uint64_t *out)
         if (kind == 0)      out[i] = orc_xs_step(state, 13, 17, 5, W);
         else if (kind == 1) out[i] = orc_x128_step(state, W);
         else if (kind == 2) out[i] = orc_xwow_step(state, W);
+        else if (kind == 3 && W == 64) out[i] = orc_xor64_step(state);
         else return ORC_EINVAL;
     }
     return ORC_OK;
@@ -184,14 +205,17 @@ void orc_ci_step_batch(const uint32_t *x, const uint32_t *S, uint32_t *out, uint
 /*   V1: xs{lo,hi}, x128{x,y,z,w}{lo,hi}, xwow{x,y,z,w,v,d}{lo,hi}, ci_x     */
 /*                                                              (23 words)   */
 /*   V3: bbs[8] (slot 1..8), ci_x, t_prev                       (10 words)   */
+/*   V4: xor64{lo,hi}, ci_x, t_prev                             (4 words)    */
 /* ------------------------------------------------------------------------ */
 int orc_state_words(int variant)
 {
-    switch (variant) {
+    if ((variant & ~0xFF) && variant != (ORC_V1 | ORC_F_XOR64)) return ORC_EINVAL;
+    switch (variant & 0xFF) {
     case ORC_V0: return 5;
     case ORC_V1: return 23;
     case ORC_V2: return 6;
     case ORC_V3: return 10;
+    case ORC_V4: return 4;
     default: return ORC_EINVAL;
     }
 }
@@ -232,12 +256,15 @@ static void put64(uint32_t *w, int k, uint64_t v) { w[2 * k] = (uint32_t)v; w[2 
  * W = 32 keeps the low 32 bits of each draw (rejection on the kept bits).
  * V3 draws, for slots 1..8 in turn, r = D64 mod M (redrawn until r >= 2 and
  * gcd(r, M) = 1) and keeps r^2 mod M (a quadratic residue coprime to M, the
- * usual BBS start); then x, then the initial neighbour word. */
+ * usual BBS start); then x, then the initial neighbour word.  V4 draws the
+ * xor64 word (until nonzero), then x, then the initial neighbour word. */
 int orc_seed(int variant, int W, uint64_t sigma, uint64_t first_stream,
              uint64_t n_streams, uint32_t *state)
 {
     int nw = orc_state_words(variant);
     if (nw < 0 || (W != 32 && W != 64)) return ORC_EINVAL;
+    if ((variant & ORC_F_XOR64) && W != 64) return ORC_EINVAL;
+    variant &= 0xFF;
     uint64_t m = wmask(W);
     for (uint64_t k = 0; k < n_streams; ++k) {
         uint64_t ctr = (sigma << 32) + (first_stream + k);
@@ -251,6 +278,12 @@ int orc_seed(int variant, int W, uint64_t sigma, uint64_t first_stream,
             }
             st[8] = (uint32_t)sm64_draw(&ctr);
             st[9] = (uint32_t)sm64_draw(&ctr);
+        } else if (variant == ORC_V4) {
+            uint64_t y;
+            do { y = sm64_draw(&ctr); } while (y == 0);
+            put64(st, 0, y);
+            st[2] = (uint32_t)sm64_draw(&ctr);
+            st[3] = (uint32_t)sm64_draw(&ctr);
         } else if (variant == ORC_V0 || variant == ORC_V2) {
             uint32_t a[4];
             do {
@@ -358,15 +391,16 @@ static void gen_v0_stream(uint32_t *st, uint64_t n, uint32_t *out, uint32_t *str
 
 /* V1: Listing 1 per stream (Algorithm 3).  Each generator steps once per
  * output; S is the xor of the low and high 32-bit halves of the three
- * generator outputs, in the order the listing applies them. */
-static void gen_v1_stream(uint32_t *st, int W, uint64_t n, uint32_t *out, uint32_t *strat)
+ * generator outputs, in the order the listing applies them.  alt: the first
+ * generator is xor64 (13,7,17) instead of the (13,17,5) triple. */
+static void gen_v1_stream(uint32_t *st, int W, int alt, uint64_t n, uint32_t *out, uint32_t *strat)
 {
     uint64_t g1 = get64(st, 0), g2[4], g3[6];
     for (int j = 0; j < 4; ++j) g2[j] = get64(st, 1 + j);
     for (int j = 0; j < 6; ++j) g3[j] = get64(st, 5 + j);
     uint32_t x = st[22];
     for (uint64_t i = 0; i < n; ++i) {
-        uint64_t t1 = orc_xs_step(&g1, 13, 17, 5, W);
+        uint64_t t1 = alt ? orc_xor64_step(&g1) : orc_xs_step(&g1, 13, 17, 5, W);
         uint64_t t2 = orc_x128_step(g2, W);
         uint64_t t3 = orc_xwow_step(g3, W);
         uint32_t S = 0;
@@ -421,6 +455,46 @@ static int gen_v2_group(uint32_t *st, uint32_t C, const uint32_t *comb1, const u
         st[j * 6 + 5] = tprev[j];
     }
     free(g); free(tprev); free(tnext); free(u);
+    return ORC_OK;
+}
+
+/* V4: Algorithm 4 with xor64 as each thread's generator (Section 7).  The
+ * thread's word is the xor of the two 32-bit halves of its xor64 output; the
+ * exchange is V2's: thread j mixes the previous-step words of threads
+ * comb1[j] and comb2[j] of its group, all reads before any write. */
+static int gen_v4_group(uint32_t *st, uint32_t C, const uint32_t *comb1, const uint32_t *comb2,
+                        uint64_t n, uint32_t *out, uint32_t *strat, uint64_t stride)
+{
+    uint64_t *y = malloc(sizeof(uint64_t) * C);
+    uint32_t *tprev = malloc(sizeof(uint32_t) * C);
+    uint32_t *tnext = malloc(sizeof(uint32_t) * C);
+    if (!y || !tprev || !tnext) {
+        free(y); free(tprev); free(tnext);
+        return ORC_ENOMEM;
+    }
+    for (uint32_t j = 0; j < C; ++j) {
+        y[j] = get64(st + (size_t)j * 4, 0);
+        tprev[j] = st[j * 4 + 3];
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+        for (uint32_t j = 0; j < C; ++j) {
+            uint64_t v = orc_xor64_step(&y[j]);
+            tnext[j] = (uint32_t)v ^ (uint32_t)(v >> 32);
+        }
+        for (uint32_t j = 0; j < C; ++j) tnext[j] ^= tprev[comb1[j]] ^ tprev[comb2[j]];
+        for (uint32_t j = 0; j < C; ++j) {
+            tprev[j] = tnext[j];
+            uint32_t x = orc_ci_step(st[j * 4 + 2], tnext[j]);
+            st[j * 4 + 2] = x;
+            if (out) out[j * stride + i] = x;
+            if (strat) strat[j * stride + i] = tnext[j];
+        }
+    }
+    for (uint32_t j = 0; j < C; ++j) {
+        put64(st + (size_t)j * 4, 0, y[j]);
+        st[j * 4 + 3] = tprev[j];
+    }
+    free(y); free(tprev); free(tnext);
     return ORC_OK;
 }
 
@@ -493,7 +567,7 @@ static int gen_v3_group(uint32_t *st, uint32_t C, const uint32_t *combs, uint64_
 /* Generate n outputs per stream for n_streams streams whose states are in
  * `state` (updated in place, so a second call continues the streams).
  * out (optional) and strat (optional, the strategy words S^n) are
- * stream-major: [s*n + i].  V2 needs n_streams % C == 0 and the two
+ * stream-major: [s*n + i].  V2 and V4 need n_streams % C == 0 and the two
  * combination arrays; V3 needs n_streams % C == 0 and the sixteen arrays of
  * orc_bbs_comb_tables() in comb1 (16*C entries; comb2 unused); W only
  * matters for V1.  One call is one call of the paper's kernel (V3 chooses its
@@ -504,12 +578,15 @@ int orc_generate(int variant, int W, uint64_t n_streams, uint32_t *state, uint64
 {
     int nw = orc_state_words(variant);
     if (nw < 0 || (W != 32 && W != 64)) return ORC_EINVAL;
+    const int alt = (variant & ORC_F_XOR64) != 0;
+    if (alt && W != 64) return ORC_EINVAL;
+    variant &= 0xFF;
     if (variant == ORC_V0) {
         for (uint64_t s = 0; s < n_streams; ++s)
             gen_v0_stream(state + s * 5, n, out ? out + s * n : NULL, strat ? strat + s * n : NULL);
     } else if (variant == ORC_V1) {
         for (uint64_t s = 0; s < n_streams; ++s)
-            gen_v1_stream(state + s * 23, W, n, out ? out + s * n : NULL, strat ? strat + s * n : NULL);
+            gen_v1_stream(state + s * 23, W, alt, n, out ? out + s * n : NULL, strat ? strat + s * n : NULL);
     } else if (variant == ORC_V3) {
         if (C == 0 || !comb1 || n_streams % C != 0) return ORC_EINVAL;
         for (uint32_t j = 0; j < 16 * C; ++j)
@@ -524,8 +601,11 @@ int orc_generate(int variant, int W, uint64_t n_streams, uint32_t *state, uint64
         for (uint32_t j = 0; j < C; ++j)
             if (comb1[j] >= C || comb2[j] >= C) return ORC_EINVAL;
         for (uint64_t g0 = 0; g0 < n_streams; g0 += C) {
-            int rc = gen_v2_group(state + g0 * 6, C, comb1, comb2, n,
-                                  out ? out + g0 * n : NULL, strat ? strat + g0 * n : NULL, n);
+            int rc = variant == ORC_V4
+                ? gen_v4_group(state + g0 * 4, C, comb1, comb2, n,
+                               out ? out + g0 * n : NULL, strat ? strat + g0 * n : NULL, n)
+                : gen_v2_group(state + g0 * 6, C, comb1, comb2, n,
+                               out ? out + g0 * n : NULL, strat ? strat + g0 * n : NULL, n);
             if (rc) return rc;
         }
     }
@@ -560,7 +640,8 @@ int orc_consume_qc(int variant, int W, uint64_t n_streams, uint32_t *state, uint
 {
     int nw = orc_state_words(variant);
     if (nw < 0 || (n & 1)) return ORC_EINVAL;
-    uint64_t group = (variant == ORC_V2 || variant == ORC_V3) ? C : 1;
+    const int base = variant & 0xFF;
+    uint64_t group = (base == ORC_V2 || base == ORC_V3 || base == ORC_V4) ? C : 1;
     if (group == 0 || n_streams % group != 0) return ORC_EINVAL;
     uint64_t words = group * n;
     uint32_t *buf = malloc(sizeof(uint32_t) * (size_t)(words > 0 ? words : 1));

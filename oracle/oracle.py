@@ -4,7 +4,7 @@ Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
 import this module.  The product library neither imports nor links it.
 
 All arrays are numpy; states are array-of-structures uint32 words per stream
-(V0: 5 words, V2: 6, V1: 23, V3: 10; layout in cprng_oracle.c).
+(V0: 5 words, V2: 6, V1: 23, V3: 10, V4: 4; layout in cprng_oracle.c).
 """
 import ctypes as C
 import os
@@ -14,7 +14,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-V0, V1, V2, V3 = 0, 1, 2, 3
+V0, V1, V2, V3, V4 = 0, 1, 2, 3, 4
+F_XOR64 = 0x100        # V1 modifier: xor64 (13,7,17) as Listing 1's first generator
 
 _lib = None
 _override = None
@@ -185,7 +186,7 @@ def bbs_comb_tables(Cg: int = 32) -> np.ndarray:
 def _comb_args(variant, comb):
     """(C, comb1, comb2) for the C entry points: V2 takes (comb1, comb2), V3 the
     (16, C) arrangement arrays."""
-    if variant == V2:
+    if (variant & 0xFF) in (V2, V4):
         c1, c2 = comb if comb is not None else comb_tables(32)
         c1 = np.ascontiguousarray(c1, dtype=np.uint32)
         c2 = np.ascontiguousarray(c2, dtype=np.uint32)

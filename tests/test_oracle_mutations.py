@@ -14,6 +14,7 @@ import pytest
 from oracle import oracle as O
 from tests import test_oracle_bbs_pins as B
 from tests import test_oracle_pins as P
+from tests import test_oracle_xor64_pins as X
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "cprng_oracle.c")
@@ -54,10 +55,18 @@ MUTATIONS = [
     ("alg5 BBS2 not stepped again", "t |= orc_bbs_step(&b[1], 1) & array_shift[shift];", "t |= b[1] & array_shift[shift];"),
     ("alg5 modulus 251*239 -> 251*241", "251u * 239u, 251u * 227u", "251u * 241u, 251u * 227u"),
     ("alg5 seed not squared", "st[k] = (uint32_t)((r * r) % M);", "st[k] = (uint32_t)r;"),
+    ("xor64 triple 7 -> 8", "orc_xs_step(y, 13, 7, 17, 64)", "orc_xs_step(y, 13, 8, 17, 64)"),
+    ("v4 word is the low half only", "tnext[j] = (uint32_t)v ^ (uint32_t)(v >> 32);", "tnext[j] = (uint32_t)v;"),
+    ("v4 reads comb1 twice", "tnext[j] ^= tprev[comb1[j]] ^ tprev[comb2[j]];", "tnext[j] ^= tprev[comb1[j]] ^ tprev[comb1[j]];"),
+    ("v4 loses t at call end", "st[j * 4 + 3] = tprev[j];", "st[j * 4 + 3] = tprev[j] ^ 1u;"),
+    ("v1 alternative ignored", "alt ? orc_xor64_step(&g1) : orc_xs_step(&g1, 13, 17, 5, W)", "orc_xs_step(&g1, 13, 17, 5, W)"),
 ]
 # Not listed: dropping the all-zero redraw of the seeding is an equivalent
 # mutant in practice (four zero draws have probability 2^-128); the seeding
 # draw order is a documented convention, checked by oracle/library agreement.
+# Nor the mirrored xor64 triple (17,7,13): it is also a full-period xor64, so
+# no property the paper fixes separates it from (13,7,17); the order is the
+# reading's convention (Marsaglia lists the triple as (13,7,17)).
 
 
 def _pins(orc):
@@ -104,6 +113,13 @@ def _pins(orc):
     t.append(B.test_outputs_are_the_prefix_xor_of_the_strategy)
     t.append(B.test_arrangement_arrays_are_fixed_point_free_permutations_and_golden)
     t.append(B.test_monobit)
+    t.append(lambda: X.test_xor64_primitive_degree_64(orc))
+    for Cg in (32, 5):
+        t.append(lambda Cg=Cg: X.test_v4_lockstep_simulation(orc, Cg))
+    t.append(lambda: X.test_v4_equal_combs_reduce_to_xor64_halves(orc))
+    t.append(lambda: X.test_v4_prefix_xor_and_group_invariant(orc))
+    t.append(lambda: X.test_v4_superposition_and_continuation(orc))
+    t.append(lambda: X.test_v1_xor64_alternative_composition(orc))
     return t
 
 
