@@ -60,14 +60,25 @@ enum cprng_variant {
      * with outputs the eight BBS states rotate (slot k to k+1, 8 to 1).
      * 10 state words/stream: BBS slots 1..8 (each < 2^16), x, previous word.
      * Needs n_streams % C == 0.  Library arrangement arrays only. */
-    CPRNG_V3_BBS = 3
+    CPRNG_V3_BBS = 3,
+    /* Algorithm 4 with Marsaglia's xor64 as each stream's generator (the
+     * generator Section 7 names for its optimized versions): 64-bit word y,
+     * y ^= y << 13, y ^= y >> 7, y ^= y << 17; the stream's word is the xor of
+     * y's two 32-bit halves, mixed with two streams of its group as in V2.
+     * 4 state words/stream: y (low, high), x, previous word.  Needs
+     * n_streams % C == 0; combination arrays as for V2. */
+    CPRNG_V4_XOR64 = 4
 };
 
 enum cprng_flags {
     /* Output i of stream s goes to out[i * n_streams + s]. */
     CPRNG_F_INTERLEAVED = 1u << 8,
     /* V1 only: the three generators use 32-bit words (high halves are 0). */
-    CPRNG_F_V1_W32 = 1u << 9
+    CPRNG_F_V1_W32 = 1u << 9,
+    /* V1 only, 64-bit words: Listing 1's first generator is xor64 (triple
+     * 13, 7, 17) instead of Algorithm 2's triple (13, 17, 5) on the 64-bit
+     * word.  Same state layout and seeding. */
+    CPRNG_F_V1_XOR64 = 1u << 10
 };
 
 enum cprng_status {

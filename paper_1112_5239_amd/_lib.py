@@ -10,9 +10,10 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libcprng.so")
 
-V0_PLAIN, V1_NAIVE3, V2_SHMEM, V3_BBS = 0, 1, 2, 3
+V0_PLAIN, V1_NAIVE3, V2_SHMEM, V3_BBS, V4_XOR64 = 0, 1, 2, 3, 4
 F_INTERLEAVED = 1 << 8
 F_V1_W32 = 1 << 9
+F_V1_XOR64 = 1 << 10
 
 OK, E_INVAL, E_NOMEM, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4
 

@@ -63,6 +63,9 @@ void fill_args(const cprng_t *h, GenArgs &a)
     std::memcpy(a.comb1, h->comb1, 64);
     std::memcpy(a.comb2, h->comb2, 64);
     std::memcpy(a.combs16, h->combs16, sizeof a.combs16);
+    const bool xor64 = (h->flags & CPRNG_F_V1_XOR64) != 0;
+    a.xs_b = xor64 ? 7u : 17u;
+    a.xs_c = xor64 ? 17u : 5u;
 }
 
 int begin_timing(cprng_t *h, hipStream_t st)
@@ -89,10 +92,12 @@ int create_impl(const cprng_params_t *p, cprng_t **out)
     const uint32_t var = p->variant & 0xffu;
     const uint32_t flags = p->variant & ~0xffu;
     if (words_per_stream((int)var) < 0) return set_error(CPRNG_E_INVAL, "unknown variant");
-    if (flags & ~(uint32_t)(CPRNG_F_INTERLEAVED | CPRNG_F_V1_W32))
+    if (flags & ~(uint32_t)(CPRNG_F_INTERLEAVED | CPRNG_F_V1_W32 | CPRNG_F_V1_XOR64))
         return set_error(CPRNG_E_INVAL, "unknown flag bits");
     if ((flags & CPRNG_F_V1_W32) && var != CPRNG_V1_NAIVE3)
         return set_error(CPRNG_E_INVAL, "CPRNG_F_V1_W32 applies to the V1 variant only");
+    if ((flags & CPRNG_F_V1_XOR64) && (var != CPRNG_V1_NAIVE3 || (flags & CPRNG_F_V1_W32)))
+        return set_error(CPRNG_E_INVAL, "CPRNG_F_V1_XOR64 applies to the V1 variant with 64-bit words only");
     if (p->n_streams == 0) return set_error(CPRNG_E_INVAL, "n_streams must be >= 1");
 
     std::unique_ptr<cprng> h(new cprng());
@@ -101,11 +106,11 @@ int create_impl(const cprng_params_t *p, cprng_t **out)
     h->ns = p->n_streams;
     h->words = (uint32_t)words_per_stream((int)var);
 
-    if (var == CPRNG_V2_SHMEM) {
+    if (var == CPRNG_V2_SHMEM || var == CPRNG_V4_XOR64) {
         const uint32_t C = p->group ? p->group : 32u;
         if (!is_pow2(C) || C > 64)
-            return set_error(CPRNG_E_UNSUPPORTED, "V2 group size must be a power of two <= 64 (a group lies in one wave)");
-        if (p->n_streams % C != 0) return set_error(CPRNG_E_INVAL, "V2 needs n_streams % group == 0");
+            return set_error(CPRNG_E_UNSUPPORTED, "V2/V4 group size must be a power of two <= 64 (a group lies in one wave)");
+        if (p->n_streams % C != 0) return set_error(CPRNG_E_INVAL, "V2/V4 need n_streams % group == 0");
         uint32_t c1[64], c2[64];
         if (p->comb1 || p->comb2) {
             if (!p->comb1 || !p->comb2) return set_error(CPRNG_E_INVAL, "give both comb1 and comb2");
@@ -405,6 +410,8 @@ int cprng_set_state(cprng_t *h, const uint32_t *host_words, size_t n_words)
         } else if (h->variant == CPRNG_V3_BBS) {
             for (int k = 0; k < 8; ++k)
                 if (w[k] >= 65536u) return set_error(CPRNG_E_INVAL, "BBS slot state must be below 2^16");
+        } else if (h->variant == CPRNG_V4_XOR64) {
+            if ((w[0] | w[1]) == 0) return set_error(CPRNG_E_INVAL, "xor64 word is zero");
         } else if ((w[0] | w[1] | w[2] | w[3]) == 0) {
             return set_error(CPRNG_E_INVAL, "xor128 words all zero");
         }

@@ -437,6 +437,7 @@ hipError_t launch_generate(const GenArgs &a, int variant, int w32, const LaunchC
     case 1: return launch_generate_v1(a, w32 != 0, c, st);
     case 2: return launch_generate_v2(a, c, st);
     case 3: return launch_generate_v3(a, c, st);
+    case 4: return launch_generate_v4(a, c, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -449,6 +450,7 @@ hipError_t launch_consume(const GenArgs &a, int variant, int w32, const LaunchCf
     case 1: return launch_consume_v1(a, w32 != 0, c, st);
     case 2: return launch_consume_v2(a, c, st);
     case 3: return launch_consume_v3(a, c, st);
+    case 4: return launch_consume_v4(a, c, st);
     default: return hipErrorInvalidValue;
     }
 }

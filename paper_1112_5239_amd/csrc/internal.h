@@ -20,7 +20,10 @@ constexpr uint32_t kBbsModuli[8] = {251u * 239u, 251u * 227u, 251u * 223u, 251u 
                                     239u * 227u, 239u * 223u, 239u * 211u, 227u * 223u};
 
 // True for the variants that mix neighbours' words (group size C).
-constexpr bool has_exchange(uint32_t variant) { return variant == CPRNG_V2_SHMEM || variant == CPRNG_V3_BBS; }
+constexpr bool has_exchange(uint32_t variant)
+{
+    return variant == CPRNG_V2_SHMEM || variant == CPRNG_V3_BBS || variant == CPRNG_V4_XOR64;
+}
 
 // Store modes of the plain generate kernel.
 enum StoreMode : int {
@@ -50,8 +53,9 @@ struct GenArgs {
     uint64_t *counts;      // hit counts (consume)
     uint64_t n;            // outputs per stream
     uint32_t ns;           // number of streams
-    uint32_t group;        // V2/V3 group size C (divides 64)
-    uint8_t comb1[64];     // V2: comb1[j mod C]
+    uint32_t group;        // V2/V3/V4 group size C (divides 64)
+    uint32_t xs_b, xs_c;   // V1: right and second left shift of the first generator
+    uint8_t comb1[64];     // V2/V4: comb1[j mod C]
     uint8_t comb2[64];
     uint8_t combs16[16][64];   // V3: arrangement array a, entry j mod C
 };
@@ -82,6 +86,8 @@ hipError_t launch_consume_v0(const GenArgs &a, const LaunchCfg &c, hipStream_t s
 hipError_t launch_consume_v1(const GenArgs &a, bool w32, const LaunchCfg &c, hipStream_t st);
 hipError_t launch_consume_v2(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
 hipError_t launch_consume_v3(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
+hipError_t launch_generate_v4(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
+hipError_t launch_consume_v4(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
 
 // A run of consecutive outputs of one stream (a batched stream or a request)
 // for the chunked kernels.  The run is cut into chunks ("segments"):

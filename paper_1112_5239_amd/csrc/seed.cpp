@@ -35,6 +35,7 @@ int words_per_stream(int variant)
     case CPRNG_V1_NAIVE3: return 23;
     case CPRNG_V2_SHMEM: return 6;
     case CPRNG_V3_BBS: return 10;
+    case CPRNG_V4_XOR64: return 4;
     default: return -1;
     }
 }
@@ -48,6 +49,7 @@ int words_per_stream(int variant)
 //   V3   : for BBS slots 1..8, r = draw mod M (redrawn while r < 2 or r shares
 //          a factor with M), state r^2 mod M; then x, then the initial mixed
 //          word.
+//   V4   : xor64 word (redrawn while zero), x, then the initial mixed word.
 void seed_streams(int variant, bool w32, uint64_t sigma, uint64_t first, uint64_t count,
                   uint32_t *aos)
 {
@@ -71,6 +73,13 @@ void seed_streams(int variant, bool w32, uint64_t sigma, uint64_t first, uint64_
             }
             st[8] = r.next32();
             st[9] = r.next32();
+        } else if (variant == CPRNG_V4_XOR64) {
+            uint64_t y;
+            do { y = r.next(); } while (y == 0);
+            st[0] = (uint32_t)y;
+            st[1] = (uint32_t)(y >> 32);
+            st[2] = r.next32();
+            st[3] = r.next32();
         } else if (variant == CPRNG_V0_PLAIN || variant == CPRNG_V2_SHMEM) {
             uint32_t w[4];
             do {

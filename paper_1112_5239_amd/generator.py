@@ -8,7 +8,8 @@ import numpy as np
 from . import _lib as L
 
 _VARIANTS = {"v0": L.V0_PLAIN, "plain": L.V0_PLAIN, "v1": L.V1_NAIVE3, "naive3": L.V1_NAIVE3,
-             "v2": L.V2_SHMEM, "shmem": L.V2_SHMEM, "v3": L.V3_BBS, "bbs": L.V3_BBS}
+             "v2": L.V2_SHMEM, "shmem": L.V2_SHMEM, "v3": L.V3_BBS, "bbs": L.V3_BBS,
+             "v4": L.V4_XOR64, "xor64": L.V4_XOR64}
 
 
 def _torch():
@@ -26,13 +27,15 @@ def _stream(stream):
 
 class Generator:
     def __init__(self, n_streams: int, variant="v0", seed: int = 0, group: int = 0, comb=None,
-                 interleaved: bool = False, w32: bool = False, device: int = -1):
+                 interleaved: bool = False, w32: bool = False, v1_xor64: bool = False, device: int = -1):
         _torch()
         v = _VARIANTS[variant] if isinstance(variant, str) else int(variant)
         if interleaved:
             v |= L.F_INTERLEAVED
         if w32:
             v |= L.F_V1_W32
+        if v1_xor64:
+            v |= L.F_V1_XOR64
         c1, c2 = (comb if comb is not None else (None, None))
         self.h = L.cprng_create_ex(v, n_streams, seed, group=group, comb1=c1, comb2=c2, device=device)
         self.n_streams = n_streams

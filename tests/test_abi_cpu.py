@@ -59,6 +59,15 @@ def test_invalid_arguments_rejected_before_device_work(L):
         L.cprng_create(0, 64, L.V0_PLAIN | L.F_V1_W32)  # W32 flag on V0
     assert e.value.status == L.E_INVAL
     with pytest.raises(L.CprngError) as e:
+        L.cprng_create(0, 64, L.V1_NAIVE3 | L.F_V1_W32 | L.F_V1_XOR64)  # xor64 needs 64-bit words
+    assert e.value.status == L.E_INVAL
+    with pytest.raises(L.CprngError) as e:
+        L.cprng_create(0, 64, L.V4_XOR64 | L.F_V1_XOR64)  # V1 flag on V4
+    assert e.value.status == L.E_INVAL
+    with pytest.raises(L.CprngError) as e:
+        L.cprng_create(0, 100, L.V4_XOR64)           # 100 % 32 != 0
+    assert e.value.status == L.E_INVAL
+    with pytest.raises(L.CprngError) as e:
         L.cprng_create_ex(L.V2_SHMEM, 64, 0, group=4, comb1=[1, 2, 3, 9], comb2=[2, 3, 0, 1])
     assert e.value.status == L.E_INVAL
     lib = L.lib()
