@@ -244,8 +244,17 @@ typedef struct cprng_tuning {
     uint32_t streams_per_lane; /* LDS-transposed generate: 1, 2 or 4 streams per lane;
                                   interleaved tiles: 2 = two tile buffers, so each
                                   round's stores overlap the next round's steps */
-    uint32_t exchange;         /* V2, LDS-transposed generate: 1 cross-lane reads,
-                                  2 LDS word buffer, 3 two steps per read round */
+    uint32_t exchange;         /* V2/V3/V4 tile kernels (stream-major, pipelined,
+                                  interleaved) and consumption: 1 cross-lane reads,
+                                  2 LDS word buffer, 3 two steps per read round
+                                  (V2 only), 4 DPP row rotations.  4 applies to
+                                  V2/V4 handles created with group 16,
+                                  comb1[j] = (j + 1) % 16 and
+                                  comb2[j] = (j + 4) % 16 (the pattern two DPP
+                                  rotations of a 16-lane row implement; tile
+                                  kernels and consumption only); other handles
+                                  and kernels use 1.  Every choice gives the same
+                                  words. */
     uint32_t reserved;
 } cprng_tuning_t;
 

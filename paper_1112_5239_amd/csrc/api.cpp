@@ -231,12 +231,25 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
 
 namespace cprng_impl {
 
+bool dpp_pattern(const cprng_t *h)
+{
+    if ((h->variant != CPRNG_V2_SHMEM && h->variant != CPRNG_V4_XOR64) || h->group != kDppGroup) return false;
+    for (uint32_t j = 0; j < 64; ++j) {
+        const uint32_t r = j % kDppGroup;
+        if (h->comb1[j] != (r + kDppOff1) % kDppGroup || h->comb2[j] != (r + kDppOff2) % kDppGroup) return false;
+    }
+    return true;
+}
+
 int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchCfg c)
 {
     GenArgs a;
     fill_args(h, a);
     a.out = out;
     a.n = n;
+    // The DPP exchange implements one pair of arrays; any other handle gets
+    // the cross-lane reads, which produce the same words.
+    if (c.exchange == XCH_DPP && !dpp_pattern(h)) c.exchange = XCH_BPERM;
     // The BBS variant's arrays differ per thread, so the two-steps-per-read
     // exchange (which follows a neighbour's neighbours) does not apply.
     if (h->variant == CPRNG_V3_BBS && c.exchange == XCH_BPERM2) c.exchange = XCH_BPERM;
@@ -359,7 +372,8 @@ int cprng_consume_qc(cprng_t *h, uint64_t *counts, uint64_t n_per_stream, cprng_
     fill_args(h, a);
     a.counts = counts;
     a.n = n_per_stream;
-    const LaunchCfg c = resolve_cfg(h, n_per_stream, true);
+    LaunchCfg c = resolve_cfg(h, n_per_stream, true);
+    if (c.exchange == XCH_DPP && !dpp_pattern(h)) c.exchange = XCH_BPERM;
     int rc = begin_timing(h, (hipStream_t)stream);
     if (rc) return rc;
     HIP_TRY(launch_consume(a, (int)h->variant, (h->flags & CPRNG_F_V1_W32) != 0, c, (hipStream_t)stream),
@@ -455,7 +469,7 @@ int cprng_set_tuning(cprng_t *h, const cprng_tuning_t *t)
     if (t->waves_per_cu > 32) return set_error(CPRNG_E_INVAL, "waves_per_cu must be <= 32");
     if (t->streams_per_lane && t->streams_per_lane != 1 && t->streams_per_lane != 2 && t->streams_per_lane != 4)
         return set_error(CPRNG_E_INVAL, "streams_per_lane must be 1, 2 or 4");
-    if (t->exchange > 3) return set_error(CPRNG_E_INVAL, "exchange must be 0..3");
+    if (t->exchange > 4) return set_error(CPRNG_E_INVAL, "exchange must be 0..4");
     h->tuning = *t;
     return CPRNG_OK;
 }

@@ -43,8 +43,14 @@ enum StoreMode : int {
 enum ExchangeMode : int {
     XCH_BPERM = 1,        // two cross-lane reads (ds_bpermute) per step
     XCH_LDS = 2,          // per-wave LDS word buffer: one write, two reads per step
-    XCH_BPERM2 = 3        // two steps per round of eight cross-lane reads
+    XCH_BPERM2 = 3,       // two steps per round of eight cross-lane reads
+    XCH_DPP = 4           // two DPP row rotations per step (one fixed pattern, groups of 16)
 };
+
+// The combination arrays the DPP exchange implements: within each row of 16
+// lanes, stream j reads streams (j + 1) mod 16 and (j + 4) mod 16 (a DPP
+// row_ror:r hands lane i the value of lane (i - r) mod 16 of its row).
+constexpr uint32_t kDppGroup = 16, kDppOff1 = 1, kDppOff2 = 4;
 
 // Kernel arguments of the plain generate / consume kernels.
 struct GenArgs {

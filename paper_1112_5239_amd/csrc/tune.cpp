@@ -208,7 +208,7 @@ extern "C" int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n, cprng_s
     const uint32_t stores[] = {ST_DIRECT, ST_LDS, ST_LDS_NT};
     const uint32_t caps[] = {0, 4, 8};
     const uint32_t slot_opts[] = {1, 2, 4};
-    const uint32_t xch_opts[] = {XCH_BPERM, XCH_LDS};
+    const uint32_t xch_opts[] = {XCH_BPERM, XCH_LDS, XCH_DPP};
     float best = 1e30f;
     TuneEntry best_e;
     const bool saved_timing = h->timing;
@@ -223,6 +223,7 @@ extern "C" int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n, cprng_s
                 const bool lds_mode = s == ST_LDS || s == ST_LDS_NT;
                 if (!lds_mode && (u > 32 || w || sl > 1 || xm != XCH_BPERM)) continue;   // direct: K <= 32
                 if (!has_exchange(h->variant) && xm != XCH_BPERM) continue;
+                if (xm == XCH_DPP && !dpp_pattern(h)) continue;
                 if (lds_mode && u < 16) continue;
                 if (lds_mode && (size_t)b * sl * (u + (xm == XCH_LDS ? 1 : 0)) * 4 > kMaxLdsBytes) continue;
                 LaunchCfg c{b, u, s, lds_for_waves(b, w), sl, xm};

@@ -24,5 +24,7 @@ bool tune_cache_lookup_key(const std::string &key, TuneEntry *e);
 void tune_cache_store(const std::string &key, const TuneEntry &e);
 
 int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchCfg c);
+// True for V2/V4 handles whose arrays are the pattern the DPP exchange implements.
+bool dpp_pattern(const cprng_t *h);
 
 }  // namespace cprng_impl
