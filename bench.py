@@ -153,7 +153,7 @@ def alu_roofline(gn, key):
 
 def run_plain(torch, G, variant, args, interleaved=False):
     ns, n = 1 << 20, 1024
-    words = {"v0": 5, "v1": 23, "v3": 10}[variant]
+    words = {"v0": 5, "v1": 23, "v3": 10, "v4": 4}[variant]
     g = G.Generator(ns, variant, seed=1, interleaved=interleaved)
     shape = (n, ns) if interleaved else (ns, n)
     out = torch.empty(shape, dtype=torch.int32, device="cuda")
@@ -218,6 +218,35 @@ def run_consume(torch, G, args):
         if f"{variant}_consume" in ALU_MIX:
             res[variant]["roofline"] = alu_roofline(gn, f"{variant}_consume")
     return {"workload": "2^36 uint32 (2^20 streams x 2^16) -> quarter-circle hit counts, seed 3", **res}
+
+
+def run_dpp_study(torch, G):
+    """V2 with the arrays two DPP row rotations implement (groups of 16,
+    neighbours j+1 and j+4): the same words through cross-lane reads (1), the
+    LDS word buffer (2) and DPP (4), in the consumption kernel (ALU-bound) and
+    the interleaved generate kernel (store-bound)."""
+    import numpy as np
+    c1 = np.array([(j + 1) % 16 for j in range(16)], dtype=np.uint32)
+    c2 = np.array([(j + 4) % 16 for j in range(16)], dtype=np.uint32)
+    ns = 1 << 20
+    res = {"workload": "V2, groups of 16 with the DPP arrays, 2^20 streams, seed 4"}
+    g = G.Generator(ns, "v2", seed=4, group=16, comb=(c1, c2))
+    counts = torch.empty(ns, dtype=torch.int64, device="cuda")
+    for xm in (1, 2, 4):
+        g.set_tuning(exchange=xm)
+        ms, _ = timed(torch, lambda: g.consume_qc(1 << 16, counts=counts), 3, 1)
+        res[f"consume_2^16_xch{xm}_gnumbers_per_s"] = round(ns * 65536 / (ms / 1e3) / 1e9, 1)
+    g.close()
+    del counts
+    g = G.Generator(ns, "v2", seed=4, group=16, comb=(c1, c2), interleaved=True)
+    out = torch.empty((1024, ns), dtype=torch.int32, device="cuda")
+    for xm in (1, 2, 4):
+        g.set_tuning(exchange=xm)
+        ms, _ = timed(torch, lambda: g.generate(1024, out=out), 20, 10)
+        res[f"interleaved_1024_xch{xm}_ms"] = round(ms, 4)
+    g.close()
+    del out
+    return res
 
 
 def run_fill_probe(torch, L):
@@ -304,7 +333,7 @@ def main():
         log(f"[bench] v2 stream-major: {extra['v2_stream_major']}")
         extra["valu_probe"] = run_valu_probes(torch, L)
         log(f"[bench] valu probe: {extra['valu_probe']}")
-        for variant in ("v0", "v1", "v3"):
+        for variant in ("v0", "v1", "v3", "v4"):
             for ilv in (True, False):
                 key = f"{variant}_{'interleaved' if ilv else 'stream_major'}"
                 extra[key] = run_plain(torch, G, variant, args, interleaved=ilv)
@@ -315,6 +344,8 @@ def main():
         log(f"[bench] ragged: {extra['ragged']}")
         extra["consume"] = run_consume(torch, G, args)
         log(f"[bench] consume: {extra['consume']}")
+        extra["dpp_study"] = run_dpp_study(torch, G)
+        log(f"[bench] dpp study: {extra['dpp_study']}")
         extra["fill_probe"] = run_fill_probe(torch, L)
         log(f"[bench] fill probe: {extra['fill_probe']}")
     cpu = None

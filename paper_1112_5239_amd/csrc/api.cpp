@@ -178,11 +178,13 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
         // Interleaved layout: LDS tiles of K steps x block streams, spread
         // over the XCDs in bands.  Measured on MI355X at 2^20 streams x 1024:
         // 1,024 streams x 16 steps, two tile buffers (128 KiB of LDS),
-        // non-temporal stores, V2 exchange by cross-lane reads; V1,
+        // non-temporal stores, V2/V4 exchange through the LDS word buffer
+        // (as fast as cross-lane reads with the default arrays, and faster
+        // with others, e.g. 0.68 vs 0.76 ms with the DPP arrays); V1,
         // VALU-bound, 256 x 32 with one buffer; V3, VALU-bound, 512 x 16
         // with one buffer and the LDS word exchange.  Direct store modes
         // select the per-lane dword kernel.
-        LaunchCfg c{1024, 16, ST_ILV_TILE_NT, 0, 2, XCH_BPERM, 0};
+        LaunchCfg c{1024, 16, ST_ILV_TILE_NT, 0, 2, XCH_LDS, 0};
         if (h->variant == CPRNG_V1_NAIVE3) {
             c.block = 256;
             c.unroll = 32;
