@@ -148,18 +148,25 @@ int cprng_generate(cprng_t *h, uint32_t *out, uint64_t n_per_stream, cprng_strea
  * Errors: E_INVAL, E_HIP. */
 int cprng_consume_qc(cprng_t *h, uint64_t *counts, uint64_t n_per_stream, cprng_stream_t stream);
 
-/* Batched uneven streams (V0 only).  Stream s writes its next lengths[s]
- * outputs to out[offsets[s] .. offsets[s] + lengths[s]) (device, 4-byte
- * aligned, no other alignment needed); offsets == NULL means the exclusive
- * prefix sum of lengths.  lengths/offsets: host, n_streams entries each.
- * Long streams are split into chunks that start from a jumped-ahead state:
- * the strategy generator and the x chain are linear over GF(2), so the state
- * after J steps is a polynomial in the one-step map (x^J modulo the minimal
- * polynomial), and the x chain is the prefix-xor of the strategy words
- * (construction X of Section 8).  The call runs as one hipGraph launch of a
- * persistent kernel; the graph is built on the first call with a given
- * (lengths, offsets, out) and replayed afterwards.  Results equal those of
- * each stream generated alone.  Errors: E_INVAL, E_UNSUPPORTED (V1, V2,
+/* Batched uneven streams (V0, and the exchange variants V2 and V4).  Stream
+ * s writes its next lengths[s] outputs to out[offsets[s] .. offsets[s] +
+ * lengths[s]) (device, 4-byte aligned, no other alignment needed); offsets
+ * == NULL means the exclusive prefix sum of lengths.  lengths/offsets: host,
+ * n_streams entries each.  Long streams are split into chunks that start
+ * from a jumped-ahead state: the strategy generator and the x chain are
+ * linear over GF(2), so the state after J steps is a polynomial in the
+ * one-step map (x^J modulo the minimal polynomial), and the x chain is the
+ * prefix-xor of the strategy words (construction X of Section 8).
+ * V0: one hipGraph launch of a persistent kernel; the graph is built on the
+ * first call with a given (lengths, offsets, out) and replayed afterwards.
+ * V2/V4: the C streams of a group advance together (Algorithm 4), so lengths
+ * must be equal within each group; the jump is taken by the whole group (its
+ * one-step map on all C states is linear; its minimal polynomial is found
+ * once per handle); chunk length from tuning.chunk (0 = automatic); the call
+ * waits for earlier work on `stream` before reusing its buffers and then
+ * launches a state copy, the chunk kernel and the commit.  Results equal
+ * those of each stream (V0) or group (V2/V4) generated alone.  Errors:
+ * E_INVAL (unequal lengths within a group), E_UNSUPPORTED (V1, V3,
  * interleaved flag), E_NOMEM, E_HIP. */
 int cprng_generate_ragged(cprng_t *h, uint32_t *out, const uint64_t *lengths,
                           const uint64_t *offsets, cprng_stream_t stream);

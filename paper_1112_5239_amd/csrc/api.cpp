@@ -233,6 +233,10 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
 
 namespace cprng_impl {
 
+void fill_gen_args(const cprng_t *h, GenArgs &a) { fill_args(h, a); }
+int timing_begin(cprng_t *h, hipStream_t st) { return begin_timing(h, st); }
+int timing_end(cprng_t *h, hipStream_t st) { return end_timing(h, st); }
+
 bool dpp_pattern(const cprng_t *h)
 {
     if ((h->variant != CPRNG_V2_SHMEM && h->variant != CPRNG_V4_XOR64) || h->group != kDppGroup) return false;
@@ -345,6 +349,7 @@ void cprng_destroy(cprng_t *h)
     if (h->d_state_next) (void)hipFree(h->d_state_next);
     if (h->d_counter) (void)hipFree(h->d_counter);
     destroy_req_slots(h);
+    destroy_group_buffers(h);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;

@@ -525,6 +525,15 @@ hipError_t launch_valu_probe(uint32_t kind, uint32_t *out, uint32_t n_threads, u
     return hipGetLastError();
 }
 
+hipError_t launch_group_chunks(const GroupJumpArgs &a, int variant, hipStream_t st)
+{
+    switch (variant) {
+    case 2: return launch_group_chunks_v2(a, st);
+    case 4: return launch_group_chunks_v4(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_fill(uint32_t *dst, uint64_t n_words, uint32_t value, hipStream_t st)
 {
     const uint64_t nq = n_words / 4;

@@ -23,4 +23,9 @@ hipError_t launch_consume_v2(const GenArgs &a, const LaunchCfg &c, hipStream_t s
     return consume_by_unroll<2, uint32_t>(a, c, st);
 }
 
+hipError_t launch_group_chunks_v2(const GroupJumpArgs &a, hipStream_t st)
+{
+    return group_chunks_launch<2>(a, st);
+}
+
 }  // namespace cprng_impl

@@ -24,4 +24,9 @@ hipError_t launch_consume_v4(const GenArgs &a, const LaunchCfg &c, hipStream_t s
     return consume_by_unroll<4, uint32_t>(a, c, st);
 }
 
+hipError_t launch_group_chunks_v4(const GroupJumpArgs &a, hipStream_t st)
+{
+    return group_chunks_launch<4>(a, st);
+}
+
 }  // namespace cprng_impl

@@ -1,0 +1,392 @@
+// groupjump.cpp -- batched uneven runs of the exchange variants (V2, V4):
+// group-level jump-ahead and the chunked launch.
+//
+// A group of C streams of Algorithm 4 advances in lockstep, and every
+// operation of one step -- the xor-shift generator (xor128 on 32-bit words
+// for V2, xor64 for V4), the mixing with two neighbours' previous words, the
+// chaotic update x ^= t -- is a xor or a shift.  So the group's one-step map
+// A is linear over GF(2) on the concatenated states (generator words, x, t
+// of every stream), and A^J = r(A) with r = X^J mod q for any q with
+// q(A) = 0.  A chunk of a group that starts J steps in therefore starts from
+// sum_k r_k A^k s0: deg(q) steps of the group with a masked accumulate.
+//
+// q is the minimal polynomial of A, found per handle (it depends on C and the
+// combination arrays): Berlekamp-Massey on random parities of the simulated
+// group state gives the minimal polynomials of those sequences; their least
+// common multiple is q with high probability, and q(A) v = 0 is then checked
+// on random states before use.
+#include <algorithm>
+#include <cstring>
+#include <random>
+
+#include "host.h"
+#include "tune.h"
+
+#define HIP_TRY(call, what)                                    \
+    do {                                                       \
+        hipError_t _e = (call);                                \
+        if (_e != hipSuccess) return hip_error(_e, what);      \
+    } while (0)
+
+namespace cprng_impl {
+
+namespace {
+
+using Poly = std::vector<uint64_t>;   // bit i = coefficient of X^i
+
+int pdeg(const Poly &p)
+{
+    for (int i = (int)p.size() - 1; i >= 0; --i)
+        if (p[i]) return i * 64 + 63 - __builtin_clzll(p[i]);
+    return -1;
+}
+bool pbit(const Poly &p, int i) { return (size_t)(i >> 6) < p.size() && ((p[i >> 6] >> (i & 63)) & 1u); }
+void pflip(Poly &p, int i)
+{
+    if ((size_t)(i >> 6) >= p.size()) p.resize((i >> 6) + 1, 0);
+    p[i >> 6] ^= 1ull << (i & 63);
+}
+void ptrim(Poly &p)
+{
+    while (!p.empty() && !p.back()) p.pop_back();
+}
+// a ^= b << s
+void pxor_shift(Poly &a, const Poly &b, int s)
+{
+    const int db = pdeg(b);
+    if (db < 0) return;
+    const size_t need = (size_t)((db + s) >> 6) + 1;
+    if (a.size() < need) a.resize(need, 0);
+    const int ws = s >> 6, bs = s & 63;
+    for (size_t i = 0; i < b.size(); ++i) {
+        if (!b[i]) continue;
+        a[i + ws] ^= b[i] << bs;
+        if (bs && i + ws + 1 < a.size()) a[i + ws + 1] ^= b[i] >> (64 - bs);
+    }
+}
+// a mod m (m != 0), in place.
+void pmod(Poly &a, const Poly &m)
+{
+    const int dm = pdeg(m);
+    for (int d = pdeg(a); d >= dm; d = pdeg(a)) pxor_shift(a, m, d - dm);
+    ptrim(a);
+}
+Poly pmul(const Poly &a, const Poly &b)
+{
+    Poly r;
+    const int da = pdeg(a);
+    for (int i = 0; i <= da; ++i)
+        if (pbit(a, i)) pxor_shift(r, b, i);
+    ptrim(r);
+    return r;
+}
+Poly pmulmod(const Poly &a, const Poly &b, const Poly &m)
+{
+    Poly r = pmul(a, b);
+    pmod(r, m);
+    return r;
+}
+// quotient and remainder of a / b
+void pdivmod(Poly a, const Poly &b, Poly &q, Poly &r)
+{
+    q.clear();
+    const int db = pdeg(b);
+    for (int d = pdeg(a); d >= db; d = pdeg(a)) {
+        pflip(q, d - db);
+        pxor_shift(a, b, d - db);
+    }
+    ptrim(a);
+    ptrim(q);
+    r = a;
+}
+Poly pgcd(Poly a, Poly b)
+{
+    ptrim(a);
+    ptrim(b);
+    while (pdeg(b) >= 0) {
+        Poly q, r;
+        pdivmod(a, b, q, r);
+        a = b;
+        b = r;
+    }
+    return a;
+}
+Poly plcm(const Poly &a, const Poly &b)
+{
+    Poly q, r;
+    pdivmod(pmul(a, b), pgcd(a, b), q, r);
+    return q;
+}
+// X^e mod m
+Poly pxpow(uint64_t e, const Poly &m)
+{
+    Poly r{1}, base;
+    pflip(base, 1);
+    pmod(r, m);
+    pmod(base, m);
+    while (e) {
+        if (e & 1) r = pmulmod(r, base, m);
+        base = pmulmod(base, base, m);
+        e >>= 1;
+    }
+    return r;
+}
+
+// Berlekamp-Massey over GF(2): minimal polynomial (reciprocal of the
+// connection polynomial, as a polynomial in X) of the sequence s, and its
+// linear complexity.
+Poly berlekamp_massey(const std::vector<uint8_t> &s, int *L_out)
+{
+    const size_t n = s.size();
+    std::vector<uint8_t> C(n + 1, 0), B(n + 1, 0), T;
+    C[0] = B[0] = 1;
+    int L = 0, m = 1;
+    for (size_t i = 0; i < n; ++i) {
+        uint8_t d = s[i];
+        for (int j = 1; j <= L; ++j) d ^= C[j] & s[i - j];
+        if (!d) {
+            ++m;
+        } else if (2 * L <= (int)i) {
+            T = C;
+            for (size_t j = 0; j + m <= n; ++j) C[j + m] ^= B[j];
+            L = (int)i + 1 - L;
+            B = T;
+            m = 1;
+        } else {
+            for (size_t j = 0; j + m <= n; ++j) C[j + m] ^= B[j];
+            ++m;
+        }
+    }
+    // connection C(X) = 1 + c1 X + ... + cL X^L; minimal polynomial X^L C(1/X)
+    Poly p;
+    for (int j = 0; j <= L; ++j)
+        if (C[j]) pflip(p, L - j);
+    *L_out = L;
+    return p;
+}
+
+// The group of C streams, simulated on the host: words per stream in the
+// library's state order (V2: xor128 x,y,z,w, x, t; V4: y lo, y hi, x, t).
+struct GroupSim {
+    uint32_t variant, C;
+    const uint8_t *c1, *c2;
+    std::vector<uint32_t> w;   // C * words
+    uint32_t words() const { return variant == CPRNG_V2_SHMEM ? 6u : 4u; }
+    void step()
+    {
+        const uint32_t nw = words();
+        std::vector<uint32_t> u(C), tprev(C);
+        for (uint32_t j = 0; j < C; ++j) {
+            uint32_t *s = &w[j * nw];
+            if (variant == CPRNG_V2_SHMEM) {
+                const uint32_t t = s[0] ^ (s[0] << 11);
+                s[0] = s[1];
+                s[1] = s[2];
+                s[2] = s[3];
+                s[3] = (s[3] ^ (s[3] >> 19)) ^ (t ^ (t >> 8));
+                u[j] = s[3];
+            } else {
+                uint64_t y = (uint64_t)s[0] | ((uint64_t)s[1] << 32);
+                y ^= y << 13;
+                y ^= y >> 7;
+                y ^= y << 17;
+                s[0] = (uint32_t)y;
+                s[1] = (uint32_t)(y >> 32);
+                u[j] = s[0] ^ s[1];
+            }
+            tprev[j] = s[nw - 1];
+        }
+        for (uint32_t j = 0; j < C; ++j) {
+            uint32_t *s = &w[j * nw];
+            const uint32_t t = u[j] ^ tprev[c1[j]] ^ tprev[c2[j]];
+            s[nw - 1] = t;
+            s[nw - 2] ^= t;
+        }
+    }
+};
+
+// q(A) v == 0 for a few random states v.
+bool check_annihilates(GroupSim g, const Poly &q, std::mt19937_64 &rng)
+{
+    const int d = pdeg(q);
+    for (int trial = 0; trial < 3; ++trial) {
+        for (auto &x : g.w) x = (uint32_t)rng();
+        std::vector<uint32_t> acc(g.w.size(), 0);
+        for (int k = 0; k <= d; ++k) {
+            if (pbit(q, k))
+                for (size_t i = 0; i < acc.size(); ++i) acc[i] ^= g.w[i];
+            g.step();
+        }
+        for (uint32_t x : acc)
+            if (x) return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+int group_minpoly(cprng_t *h)
+{
+    if (h->gj_deg > 0) return CPRNG_OK;
+    GroupSim g{h->variant, h->group, h->comb1, h->comb2, {}};
+    const uint32_t nw = g.words();
+    g.w.assign((size_t)h->group * nw, 0);
+    std::mt19937_64 rng(0x5eed5eedull);
+    // Observations: parities of random masks of the state, one per step.
+    const int n_obs = 24;
+    for (int len = 2048; len <= 32768; len *= 2) {
+        for (auto &x : g.w) x = (uint32_t)rng();
+        std::vector<std::vector<uint32_t>> masks(n_obs, std::vector<uint32_t>(g.w.size()));
+        for (auto &m : masks)
+            for (auto &x : m) x = (uint32_t)rng();
+        std::vector<std::vector<uint8_t>> seq(n_obs, std::vector<uint8_t>(len));
+        GroupSim s = g;
+        for (int i = 0; i < len; ++i) {
+            for (int o = 0; o < n_obs; ++o) {
+                uint32_t acc = 0;
+                for (size_t k = 0; k < s.w.size(); ++k) acc ^= s.w[k] & masks[o][k];
+                seq[o][i] = (uint8_t)(__builtin_popcount(acc) & 1);
+            }
+            s.step();
+        }
+        Poly q{1};
+        bool long_enough = true;
+        for (int o = 0; o < n_obs; ++o) {
+            int L = 0;
+            Poly p = berlekamp_massey(seq[o], &L);
+            if (2 * L + 64 > len) long_enough = false;
+            q = plcm(q, p);
+        }
+        if (!long_enough) continue;
+        if (!check_annihilates(g, q, rng)) continue;
+        h->gj_q = q;
+        h->gj_deg = pdeg(q);
+        return CPRNG_OK;
+    }
+    return set_error(CPRNG_E_HIP, "group jump-ahead: no annihilating polynomial found");
+}
+
+void group_jump_rows(const cprng_t *h, uint64_t chunk, uint32_t rows, std::vector<uint32_t> &out)
+{
+    const uint32_t W = (uint32_t)((h->gj_deg + 31) / 32);
+    out.assign((size_t)rows * W, 0);
+    const Poly base = pxpow(chunk, h->gj_q);
+    Poly r{1};
+    pmod(r, h->gj_q);
+    for (uint32_t c = 0; c < rows; ++c) {
+        for (int k = 0; k < h->gj_deg; ++k)
+            if (pbit(r, k)) out[(size_t)c * W + (k >> 5)] |= 1u << (k & 31);
+        r = pmulmod(r, base, h->gj_q);
+    }
+}
+
+namespace {
+
+template <typename T>
+int ensure_buf(T **p, size_t *cap, size_t n)
+{
+    if (*cap >= n && *p) return CPRNG_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    if (hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess)
+        return set_error(CPRNG_E_NOMEM, "hipMalloc of group-jump buffers failed");
+    *cap = n;
+    return CPRNG_OK;
+}
+
+}  // namespace
+
+int ragged_groups(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets,
+                  hipStream_t st)
+{
+    const uint32_t C = h->group;
+    for (uint32_t g0 = 0; g0 < h->ns; g0 += C)
+        for (uint32_t j = 1; j < C; ++j)
+            if (lengths[g0 + j] != lengths[g0])
+                return set_error(CPRNG_E_INVAL, "V2/V4: lengths must be equal within each group of C streams");
+    int rc = group_minpoly(h);
+    if (rc) return rc;
+    const uint32_t n_groups = h->ns / C;
+    uint64_t group_steps = 0, max_len = 0;
+    for (uint32_t g = 0; g < n_groups; ++g) {
+        group_steps += lengths[(size_t)g * C];
+        max_len = std::max(max_len, lengths[(size_t)g * C]);
+    }
+    if (group_steps == 0) return CPRNG_OK;
+    // Chunk: a power of two giving about 16 items per CU (items per wave =
+    // 64 / C), at least 16 x the jump's length, at most 2^20.
+    uint64_t chunk = h->tuning.chunk ? h->tuning.chunk : 0;
+    if (!chunk) {
+        const uint64_t target = group_steps / ((uint64_t)h->n_cu * 16u) + 1;
+        chunk = 1;
+        while (chunk < target) chunk <<= 1;
+        chunk = std::max<uint64_t>(chunk, 16ull * (uint64_t)h->gj_deg);
+        chunk = std::min<uint64_t>(chunk, 1ull << 20);
+    }
+    std::vector<GroupItem> items;
+    for (uint32_t g = 0; g < n_groups; ++g) {
+        const uint64_t L = lengths[(size_t)g * C];
+        for (uint64_t a = 0, c = 0; a < L; a += chunk, ++c) {
+            GroupItem it{};
+            it.group = g;
+            it.row = (uint32_t)c;
+            it.start = a;
+            it.len = std::min(chunk, L - a);
+            it.last = (a + chunk >= L) ? 1u : 0u;
+            items.push_back(it);
+        }
+    }
+    const uint32_t n_rows = (uint32_t)((max_len + chunk - 1) / chunk);
+    std::vector<uint32_t> rows;
+    group_jump_rows(h, chunk, n_rows, rows);
+    std::vector<uint64_t> offs(h->ns);
+    uint64_t acc = 0;
+    for (uint32_t s = 0; s < h->ns; ++s) {
+        offs[s] = offsets ? offsets[s] : acc;
+        acc += lengths[s];
+    }
+    // The buffers are reused by the next call: wait for the previous one.
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    const size_t nwords = (size_t)h->ns * h->words;
+    if ((rc = ensure_buf(&h->d_gj_next, &h->gj_next_cap, nwords))) return rc;
+    if ((rc = ensure_buf(&h->d_gj_items, &h->gj_items_cap, items.size()))) return rc;
+    if ((rc = ensure_buf(&h->d_gj_rows, &h->gj_rows_cap, rows.size()))) return rc;
+    if ((rc = ensure_buf(&h->d_gj_offsets, &h->gj_offsets_cap, offs.size()))) return rc;
+    HIP_TRY(hipMemcpy(h->d_gj_items, items.data(), items.size() * sizeof(GroupItem), hipMemcpyHostToDevice),
+            "hipMemcpy items");
+    HIP_TRY(hipMemcpy(h->d_gj_rows, rows.data(), rows.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
+            "hipMemcpy jump rows");
+    HIP_TRY(hipMemcpy(h->d_gj_offsets, offs.data(), offs.size() * sizeof(uint64_t), hipMemcpyHostToDevice),
+            "hipMemcpy offsets");
+    GroupJumpArgs a;
+    fill_gen_args(h, a.g);
+    a.state_next = h->d_gj_next;
+    a.items = h->d_gj_items;
+    a.n_items = (uint32_t)items.size();
+    a.rows = h->d_gj_rows;
+    a.row_words = (uint32_t)((h->gj_deg + 31) / 32);
+    a.deg = (uint32_t)h->gj_deg;
+    a.out = out;
+    a.offsets = h->d_gj_offsets;
+    int trc = timing_begin(h, st);
+    if (trc) return trc;
+    HIP_TRY(launch_copy(h->d_gj_next, h->d_state, nwords, st), "state copy");
+    HIP_TRY(launch_group_chunks(a, (int)h->variant, st), "group chunk kernel launch");
+    HIP_TRY(launch_copy(h->d_state, h->d_gj_next, nwords, st), "state commit");
+    return timing_end(h, st);
+}
+
+void destroy_group_buffers(cprng_t *h)
+{
+    if (h->d_gj_next) (void)hipFree(h->d_gj_next);
+    if (h->d_gj_items) (void)hipFree(h->d_gj_items);
+    if (h->d_gj_rows) (void)hipFree(h->d_gj_rows);
+    if (h->d_gj_offsets) (void)hipFree(h->d_gj_offsets);
+    h->d_gj_next = nullptr;
+    h->d_gj_items = nullptr;
+    h->d_gj_rows = nullptr;
+    h->d_gj_offsets = nullptr;
+}
+
+}  // namespace cprng_impl

@@ -97,4 +97,17 @@ struct cprng {
     // jump tables X^(h + k*chunk) for requests, per chunk length
     std::unordered_map<uint32_t, uint32_t> req_poly_kcap;
     std::unordered_map<uint32_t, uint32_t *> d_req_poly_tables;
+
+    // group jump-ahead (V2/V4 batched uneven runs): minimal polynomial of the
+    // group's one-step map and grow-only work buffers
+    std::vector<uint64_t> gj_q;
+    int gj_deg = 0;
+    uint32_t *d_gj_next = nullptr;
+    size_t gj_next_cap = 0;
+    cprng_impl::GroupItem *d_gj_items = nullptr;
+    size_t gj_items_cap = 0;
+    uint32_t *d_gj_rows = nullptr;
+    size_t gj_rows_cap = 0;
+    uint64_t *d_gj_offsets = nullptr;
+    size_t gj_offsets_cap = 0;
 };

@@ -66,6 +66,30 @@ struct GenArgs {
     uint8_t combs16[16][64];   // V3: arrangement array a, entry j mod C
 };
 
+// One chunk of a group's run (V2/V4 batched uneven runs): the group's C
+// streams generate steps [start, start + len) from the state reached by the
+// jump polynomial of row `row`; the last chunk writes the end states.
+struct GroupItem {
+    uint32_t group;
+    uint32_t row;
+    uint64_t start;
+    uint64_t len;
+    uint32_t last;
+    uint32_t pad;
+};
+
+struct GroupJumpArgs {
+    GenArgs g;                  // the call's start states, ns, group, arrays
+    uint32_t *state_next;       // end states (groups with a last chunk)
+    const GroupItem *items;
+    uint32_t n_items;
+    uint32_t row_words;         // 32-bit words per jump row
+    uint32_t deg;               // degree of the group's minimal polynomial
+    const uint32_t *rows;       // row r: coefficients of X^(r * chunk) mod q
+    uint32_t *out;
+    const uint64_t *offsets;    // per stream
+};
+
 struct LaunchCfg {
     uint32_t block;        // threads per block
     uint32_t unroll;       // outputs per lane per round
@@ -94,6 +118,10 @@ hipError_t launch_consume_v2(const GenArgs &a, const LaunchCfg &c, hipStream_t s
 hipError_t launch_consume_v3(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
 hipError_t launch_generate_v4(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
 hipError_t launch_consume_v4(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
+// Chunks of V2/V4 group runs (groupjump.cpp plans them).
+hipError_t launch_group_chunks(const GroupJumpArgs &a, int variant, hipStream_t st);
+hipError_t launch_group_chunks_v2(const GroupJumpArgs &a, hipStream_t st);
+hipError_t launch_group_chunks_v4(const GroupJumpArgs &a, hipStream_t st);
 
 // A run of consecutive outputs of one stream (a batched stream or a request)
 // for the chunked kernels.  The run is cut into chunks ("segments"):

@@ -306,8 +306,9 @@ int check_ragged_args(cprng_t *h, uint32_t *out, const uint64_t *lengths, const 
                       uint64_t *total, uint64_t *max_len)
 {
     if (!h || !out || !lengths) return set_error(CPRNG_E_INVAL, "NULL argument");
-    if (h->variant != CPRNG_V0_PLAIN)
-        return set_error(CPRNG_E_UNSUPPORTED, "batched uneven streams need the V0 variant (GF(2)-linear jump-ahead)");
+    if (h->variant != CPRNG_V0_PLAIN && h->variant != CPRNG_V2_SHMEM && h->variant != CPRNG_V4_XOR64)
+        return set_error(CPRNG_E_UNSUPPORTED,
+                         "batched uneven streams need a GF(2)-linear variant (V0, V2 or V4) for the jump-ahead");
     if (h->flags & CPRNG_F_INTERLEAVED) return set_error(CPRNG_E_UNSUPPORTED, "interleaved layout has no ragged form");
     if ((uintptr_t)out % 4u) return set_error(CPRNG_E_INVAL, "out must be 4-byte aligned");
     uint64_t acc = 0, mx = 0;
@@ -406,6 +407,7 @@ extern "C" int cprng_generate_ragged(cprng_t *h, uint32_t *out, const uint64_t *
     int rc = check_ragged_args(h, out, lengths, offsets, &total, &max_len);
     if (rc) return rc;
     DevGuard g(h->device);
+    if (h->variant != CPRNG_V0_PLAIN) return ragged_groups(h, out, lengths, offsets, (hipStream_t)stream);
     rc = ensure_common(h);
     if (rc) return rc;
     const SegCfg c = resolve_seg_cfg(h, total, max_len);
@@ -418,6 +420,8 @@ extern "C" int cprng_autotune_ragged(cprng_t *h, uint32_t *out, const uint64_t *
     uint64_t total = 0, max_len = 0;
     int rc = check_ragged_args(h, out, lengths, offsets, &total, &max_len);
     if (rc) return rc;
+    if (h->variant != CPRNG_V0_PLAIN)
+        return set_error(CPRNG_E_UNSUPPORTED, "the ragged autotuner covers the V0 kernels only");
     DevGuard g(h->device);
     rc = ensure_common(h);
     if (rc) return rc;

@@ -26,5 +26,14 @@ void tune_cache_store(const std::string &key, const TuneEntry &e);
 int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchCfg c);
 // True for V2/V4 handles whose arrays are the pattern the DPP exchange implements.
 bool dpp_pattern(const cprng_t *h);
+// Kernel arguments of a handle, and the per-call timing events (api.cpp).
+void fill_gen_args(const cprng_t *h, GenArgs &a);
+int timing_begin(cprng_t *h, hipStream_t st);
+int timing_end(cprng_t *h, hipStream_t st);
+// Batched uneven runs of V2/V4 through the group jump-ahead (groupjump.cpp).
+int group_minpoly(cprng_t *h);
+void group_jump_rows(const cprng_t *h, uint64_t chunk, uint32_t rows, std::vector<uint32_t> &out);
+int ragged_groups(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets, hipStream_t st);
+void destroy_group_buffers(cprng_t *h);
 
 }  // namespace cprng_impl
