@@ -189,6 +189,27 @@ def run_ragged(torch, G, args, ref_v0_gn):
             "ratio_to_plain_v0": round(gn / ref_v0_gn, 4) if ref_v0_gn else None}
 
 
+def run_ragged_groups(torch, G, args, ref_gn):
+    """Batched uneven runs of the exchange variant: 128 groups of 32 streams,
+    group lengths log-uniform in [1e3, 1e7] (equal within a group), seed 2;
+    ratio against plain V2 in the stream-major layout."""
+    import numpy as np
+    rng = np.random.default_rng(2)
+    gl = np.exp(rng.uniform(np.log(1e3), np.log(1e7), size=128)).astype(np.uint64)
+    lengths = np.repeat(gl, 32).astype(np.uint64)
+    total = int(lengths.sum())
+    g = G.Generator(lengths.size, "v2", seed=2)
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    ms, _ = timed(torch, lambda: g.generate_ragged(lengths, out=out), max(5, args.steps // 10), 3)
+    g.close()
+    del out
+    gn = total / (ms / 1e3) / 1e9
+    return {"workload": f"V2, 128 groups x 32 streams, group lengths log-uniform [1e3,1e7] (total {total}), "
+                        "seed 2", "ms": round(ms, 4), "gnumbers_per_s": round(gn, 2),
+            "hbm_gbs": round(total * 4 / (ms / 1e3) / 1e9, 1),
+            "ratio_to_plain_v2_stream_major": round(gn / ref_gn, 4) if ref_gn else None}
+
+
 def run_valu_probes(torch, L):
     """Issue rates (wave64 instructions per CU per clock at the peak clock) of
     the three probe classes, with every CU holding its full complement of waves."""
@@ -342,6 +363,8 @@ def main():
                 log(f"[bench] {key}: {extra[key]}")
         extra["ragged"] = run_ragged(torch, G, args, extra["v0_stream_major"]["gnumbers_per_s"])
         log(f"[bench] ragged: {extra['ragged']}")
+        extra["ragged_groups_v2"] = run_ragged_groups(torch, G, args, extra["v2_stream_major"]["gnumbers_per_s"])
+        log(f"[bench] ragged groups (V2): {extra['ragged_groups_v2']}")
         extra["consume"] = run_consume(torch, G, args)
         log(f"[bench] consume: {extra['consume']}")
         extra["dpp_study"] = run_dpp_study(torch, G)

@@ -314,11 +314,12 @@ int ragged_groups(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint
         max_len = std::max(max_len, lengths[(size_t)g * C]);
     }
     if (group_steps == 0) return CPRNG_OK;
-    // Chunk: a power of two giving about 16 items per CU (items per wave =
-    // 64 / C), at least 16 x the jump's length, at most 2^20.
+    // Chunk: a power of two giving about 8 items per CU (items per wave =
+    // 64 / C; fewer, longer runs in flight store better), at least 16 x the
+    // jump's length, at most 2^20.
     uint64_t chunk = h->tuning.chunk ? h->tuning.chunk : 0;
     if (!chunk) {
-        const uint64_t target = group_steps / ((uint64_t)h->n_cu * 16u) + 1;
+        const uint64_t target = group_steps / ((uint64_t)h->n_cu * 8u) + 1;
         chunk = 1;
         while (chunk < target) chunk <<= 1;
         chunk = std::max<uint64_t>(chunk, 16ull * (uint64_t)h->gj_deg);
