@@ -148,7 +148,7 @@ int cprng_generate(cprng_t *h, uint32_t *out, uint64_t n_per_stream, cprng_strea
  * Errors: E_INVAL, E_HIP. */
 int cprng_consume_qc(cprng_t *h, uint64_t *counts, uint64_t n_per_stream, cprng_stream_t stream);
 
-/* Batched uneven streams (V0, and the exchange variants V2 and V4).  Stream
+/* Batched uneven streams (V0, V1, and the exchange variants V2 and V4).  Stream
  * s writes its next lengths[s] outputs to out[offsets[s] .. offsets[s] +
  * lengths[s]) (device, 4-byte aligned, no other alignment needed); offsets
  * == NULL means the exclusive prefix sum of lengths.  lengths/offsets: host,
@@ -164,10 +164,14 @@ int cprng_consume_qc(cprng_t *h, uint64_t *counts, uint64_t n_per_stream, cprng_
  * one-step map on all C states is linear; its minimal polynomial is found
  * once per handle); chunk length from tuning.chunk (0 = automatic); the call
  * waits for earlier work on `stream` before reusing its buffers and then
- * launches a state copy, the chunk kernel and the commit.  Results equal
- * those of each stream (V0) or group (V2/V4) generated alone.  Errors:
- * E_INVAL (unequal lengths within a group), E_UNSUPPORTED (V1, V3,
- * interleaved flag), E_NOMEM, E_HIP. */
+ * launches a state copy, the chunk kernel and the commit.
+ * V1: the three generators jump by their own polynomials (xorwow's Weyl
+ * counter by J * 362437); x does not (xorwow's d + v is not linear), so an
+ * aggregate pass xors each chunk's strategy words and each chunk starts from
+ * x_0 xor the aggregates of the chunks before it; same buffers, copies and
+ * waits as V2/V4.  Results equal those of each stream (V0, V1) or group
+ * (V2/V4) generated alone.  Errors: E_INVAL (unequal lengths within a group),
+ * E_UNSUPPORTED (V3, interleaved flag), E_NOMEM, E_HIP. */
 int cprng_generate_ragged(cprng_t *h, uint32_t *out, const uint64_t *lengths,
                           const uint64_t *offsets, cprng_stream_t stream);
 

@@ -23,4 +23,9 @@ hipError_t launch_consume_v1(const GenArgs &a, bool w32, const LaunchCfg &c, hip
     return w32 ? consume_by_unroll<1, uint32_t>(a, c, st) : consume_by_unroll<1, uint64_t>(a, c, st);
 }
 
+hipError_t launch_v1_chunks(const V1ChunkArgs &a, bool w32, hipStream_t st)
+{
+    return w32 ? v1_chunks_launch<uint32_t>(a, st) : v1_chunks_launch<uint64_t>(a, st);
+}
+
 }  // namespace cprng_impl

@@ -1,5 +1,5 @@
-// groupjump.cpp -- batched uneven runs of the exchange variants (V2, V4):
-// group-level jump-ahead and the chunked launch.
+// groupjump.cpp -- batched uneven runs of the exchange variants (V2, V4)
+// and of V1: jump-ahead polynomials and the chunked launches.
 //
 // A group of C streams of Algorithm 4 advances in lockstep, and every
 // operation of one step -- the xor-shift generator (xor128 on 32-bit words
@@ -17,6 +17,9 @@
 // on random states before use.
 #include <algorithm>
 #include <cstring>
+#include <functional>
+#include <map>
+#include <mutex>
 #include <random>
 
 #include "host.h"
@@ -223,6 +226,103 @@ bool check_annihilates(GroupSim g, const Poly &q, std::mt19937_64 &rng)
     return true;
 }
 
+// Minimal polynomial of a linear map on `nwords` words of W bits (mask) given
+// its one-step function, found and checked as for the group map.
+bool linear_minpoly(size_t nwords, uint64_t mask, const std::function<void(std::vector<uint64_t> &)> &step,
+                    std::mt19937_64 &rng, Poly &q)
+{
+    const int n_obs = 12;
+    for (int len = 1024; len <= 8192; len *= 2) {
+        std::vector<uint64_t> s(nwords);
+        for (auto &x : s) x = rng() & mask;
+        std::vector<std::vector<uint64_t>> masks(n_obs, std::vector<uint64_t>(nwords));
+        for (auto &m : masks)
+            for (auto &x : m) x = rng() & mask;
+        std::vector<std::vector<uint8_t>> seq(n_obs, std::vector<uint8_t>(len));
+        for (int i = 0; i < len; ++i) {
+            for (int o = 0; o < n_obs; ++o) {
+                uint64_t acc = 0;
+                for (size_t k = 0; k < nwords; ++k) acc ^= s[k] & masks[o][k];
+                seq[o][i] = (uint8_t)(__builtin_popcountll(acc) & 1);
+            }
+            step(s);
+        }
+        Poly p{1};
+        bool long_enough = true;
+        for (int o = 0; o < n_obs; ++o) {
+            int L = 0;
+            Poly b = berlekamp_massey(seq[o], &L);
+            if (2 * L + 64 > len) long_enough = false;
+            p = plcm(p, b);
+        }
+        if (!long_enough) continue;
+        bool annihilates = true;
+        const int d = pdeg(p);
+        for (int trial = 0; trial < 3 && annihilates; ++trial) {
+            std::vector<uint64_t> v(nwords), acc(nwords, 0);
+            for (auto &x : v) x = rng() & mask;
+            for (int k = 0; k <= d; ++k) {
+                if (pbit(p, k))
+                    for (size_t i = 0; i < nwords; ++i) acc[i] ^= v[i];
+                step(v);
+            }
+            for (uint64_t x : acc)
+                if (x) annihilates = false;
+        }
+        if (!annihilates) continue;
+        q = p;
+        return true;
+    }
+    return false;
+}
+
+// The minimal polynomials of V1's three generators for one word width and
+// first-generator triple, computed once per process.
+struct V1Polys {
+    Poly q[3];
+    int deg[3] = {0, 0, 0};
+    bool ok = false;
+};
+
+const V1Polys &v1_polys(int W, uint32_t sb, uint32_t sc)
+{
+    static std::mutex mu;
+    static std::map<uint64_t, V1Polys> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const uint64_t key = ((uint64_t)W << 16) | (sb << 8) | sc;
+    auto f = cache.find(key);
+    if (f != cache.end()) return f->second;
+    V1Polys &r = cache[key];
+    const uint64_t m = W == 64 ? ~0ull : 0xFFFFFFFFull;
+    std::mt19937_64 rng(0x1e5eed11ull);
+    auto g1 = [&](std::vector<uint64_t> &s) {
+        uint64_t a = s[0];
+        a ^= (a << 13) & m;
+        a ^= a >> sb;
+        a ^= (a << sc) & m;
+        s[0] = a;
+    };
+    auto g2 = [&](std::vector<uint64_t> &s) {
+        const uint64_t t = s[0] ^ ((s[0] << 11) & m);
+        s[0] = s[1];
+        s[1] = s[2];
+        s[2] = s[3];
+        s[3] = (s[3] ^ (s[3] >> 19)) ^ (t ^ (t >> 8));
+    };
+    auto g3 = [&](std::vector<uint64_t> &s) {
+        const uint64_t u = s[0] ^ (s[0] >> 2);
+        s[0] = s[1];
+        s[1] = s[2];
+        s[2] = s[3];
+        s[3] = s[4];
+        s[4] = (s[4] ^ ((s[4] << 4) & m)) ^ (u ^ ((u << 1) & m));
+    };
+    r.ok = linear_minpoly(1, m, g1, rng, r.q[0]) && linear_minpoly(4, m, g2, rng, r.q[1]) &&
+           linear_minpoly(5, m, g3, rng, r.q[2]);
+    for (int k = 0; k < 3; ++k) r.deg[k] = pdeg(r.q[k]);
+    return r;
+}
+
 }  // namespace
 
 int group_minpoly(cprng_t *h)
@@ -378,8 +478,113 @@ int ragged_groups(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint
     return timing_end(h, st);
 }
 
+int ragged_v1(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets, hipStream_t st)
+{
+    const bool w32 = (h->flags & CPRNG_F_V1_W32) != 0;
+    const bool xor64 = (h->flags & CPRNG_F_V1_XOR64) != 0;
+    const V1Polys &P = v1_polys(w32 ? 32 : 64, xor64 ? 7u : 17u, xor64 ? 17u : 5u);
+    if (!P.ok) return set_error(CPRNG_E_HIP, "V1 jump-ahead: no annihilating polynomial found");
+    uint64_t total = 0, max_len = 0;
+    for (uint32_t s = 0; s < h->ns; ++s) {
+        total += lengths[s];
+        max_len = std::max(max_len, lengths[s]);
+    }
+    if (total == 0) return CPRNG_OK;
+    const uint64_t jump_steps = (uint64_t)(P.deg[0] + P.deg[1] + P.deg[2]);
+    // Chunk: a power of two giving about 256 chunks (4 waves) per CU, at least
+    // 16 x the jump's steps, at most 2^20.
+    uint64_t chunk = h->tuning.chunk ? h->tuning.chunk : 0;
+    if (!chunk) {
+        const uint64_t target = total / ((uint64_t)h->n_cu * 256u) + 1;
+        chunk = 1;
+        while (chunk < target) chunk <<= 1;
+        chunk = std::max<uint64_t>(chunk, 16ull * jump_steps);
+        chunk = std::min<uint64_t>(chunk, 1ull << 20);
+    }
+    std::vector<V1Item> items;
+    for (uint32_t s = 0; s < h->ns; ++s) {
+        const uint32_t first = (uint32_t)items.size();
+        for (uint64_t a = 0, c = 0; a < lengths[s]; a += chunk, ++c) {
+            V1Item it{};
+            it.stream = s;
+            it.row = (uint32_t)c;
+            it.start = a;
+            it.len = std::min(chunk, lengths[s] - a);
+            it.last = (a + chunk >= lengths[s]) ? 1u : 0u;
+            it.first = first;
+            items.push_back(it);
+        }
+    }
+    if (items.size() > 0xFFFFFFFFull) return set_error(CPRNG_E_INVAL, "too many chunks");
+    const uint32_t n_rows = (uint32_t)((max_len + chunk - 1) / chunk);
+    uint32_t wk[3], off[3];
+    uint32_t row_words = 0;
+    for (int k = 0; k < 3; ++k) {
+        wk[k] = (uint32_t)((P.deg[k] + 31) / 32);
+        off[k] = row_words;
+        row_words += wk[k];
+    }
+    std::vector<uint32_t> rows((size_t)n_rows * row_words, 0);
+    for (int k = 0; k < 3; ++k) {
+        const Poly base = pxpow(chunk, P.q[k]);
+        Poly r{1};
+        pmod(r, P.q[k]);
+        for (uint32_t c = 0; c < n_rows; ++c) {
+            for (int b = 0; b < P.deg[k]; ++b)
+                if (pbit(r, b)) rows[(size_t)c * row_words + off[k] + (b >> 5)] |= 1u << (b & 31);
+            r = pmulmod(r, base, P.q[k]);
+        }
+    }
+    std::vector<uint64_t> offs(h->ns);
+    uint64_t acc = 0;
+    for (uint32_t s = 0; s < h->ns; ++s) {
+        offs[s] = offsets ? offsets[s] : acc;
+        acc += lengths[s];
+    }
+    // The buffers are reused by the next call: wait for the previous one.
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    const size_t nwords = (size_t)h->ns * h->words;
+    int rc;
+    if ((rc = ensure_buf(&h->d_gj_next, &h->gj_next_cap, nwords))) return rc;
+    if ((rc = ensure_buf(&h->d_v1_items, &h->v1_items_cap, items.size()))) return rc;
+    if ((rc = ensure_buf(&h->d_v1_agg, &h->v1_agg_cap, items.size()))) return rc;
+    if ((rc = ensure_buf(&h->d_gj_rows, &h->gj_rows_cap, rows.size()))) return rc;
+    if ((rc = ensure_buf(&h->d_gj_offsets, &h->gj_offsets_cap, offs.size()))) return rc;
+    HIP_TRY(hipMemcpy(h->d_v1_items, items.data(), items.size() * sizeof(V1Item), hipMemcpyHostToDevice),
+            "hipMemcpy items");
+    HIP_TRY(hipMemcpy(h->d_gj_rows, rows.data(), rows.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
+            "hipMemcpy jump rows");
+    HIP_TRY(hipMemcpy(h->d_gj_offsets, offs.data(), offs.size() * sizeof(uint64_t), hipMemcpyHostToDevice),
+            "hipMemcpy offsets");
+    V1ChunkArgs a;
+    fill_gen_args(h, a.g);
+    a.state_next = h->d_gj_next;
+    a.items = h->d_v1_items;
+    a.n_items = (uint32_t)items.size();
+    a.row_words = row_words;
+    a.deg1 = (uint32_t)P.deg[0];
+    a.deg2 = (uint32_t)P.deg[1];
+    a.deg3 = (uint32_t)P.deg[2];
+    a.off2 = off[1];
+    a.off3 = off[2];
+    a.rows = h->d_gj_rows;
+    a.agg = h->d_v1_agg;
+    a.out = out;
+    a.offsets = h->d_gj_offsets;
+    int trc = timing_begin(h, st);
+    if (trc) return trc;
+    HIP_TRY(launch_copy(h->d_gj_next, h->d_state, nwords, st), "state copy");
+    HIP_TRY(launch_v1_chunks(a, w32, st), "V1 chunk kernels launch");
+    HIP_TRY(launch_copy(h->d_state, h->d_gj_next, nwords, st), "state commit");
+    return timing_end(h, st);
+}
+
 void destroy_group_buffers(cprng_t *h)
 {
+    if (h->d_v1_items) (void)hipFree(h->d_v1_items);
+    if (h->d_v1_agg) (void)hipFree(h->d_v1_agg);
+    h->d_v1_items = nullptr;
+    h->d_v1_agg = nullptr;
     if (h->d_gj_next) (void)hipFree(h->d_gj_next);
     if (h->d_gj_items) (void)hipFree(h->d_gj_items);
     if (h->d_gj_rows) (void)hipFree(h->d_gj_rows);

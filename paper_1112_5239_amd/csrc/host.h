@@ -110,4 +110,8 @@ struct cprng {
     size_t gj_rows_cap = 0;
     uint64_t *d_gj_offsets = nullptr;
     size_t gj_offsets_cap = 0;
+    cprng_impl::V1Item *d_v1_items = nullptr;
+    size_t v1_items_cap = 0;
+    uint32_t *d_v1_agg = nullptr;
+    size_t v1_agg_cap = 0;
 };

@@ -90,6 +90,32 @@ struct GroupJumpArgs {
     const uint64_t *offsets;    // per stream
 };
 
+// One chunk of a V1 run: stream `stream` generates steps [start, start +
+// len); `row` selects the jump polynomials of J = start; items of a stream
+// are consecutive, its chunk 0 at index `first`.
+struct V1Item {
+    uint32_t stream;
+    uint32_t row;
+    uint64_t start;
+    uint64_t len;
+    uint32_t last;
+    uint32_t first;
+};
+
+struct V1ChunkArgs {
+    GenArgs g;                  // the call's start states, ns, first generator's shifts
+    uint32_t *state_next;       // end states (streams with a last chunk)
+    const V1Item *items;
+    uint32_t n_items;
+    uint32_t row_words;         // 32-bit words per row: xorshift | xor128 | xorwow polynomials
+    uint32_t deg1, deg2, deg3;  // degrees of the three minimal polynomials
+    uint32_t off2, off3;        // word offsets of the xor128 and xorwow polynomials in a row
+    const uint32_t *rows;
+    uint32_t *agg;              // per chunk: xor of its strategy words
+    uint32_t *out;
+    const uint64_t *offsets;    // per stream
+};
+
 struct LaunchCfg {
     uint32_t block;        // threads per block
     uint32_t unroll;       // outputs per lane per round
@@ -118,6 +144,9 @@ hipError_t launch_consume_v2(const GenArgs &a, const LaunchCfg &c, hipStream_t s
 hipError_t launch_consume_v3(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
 hipError_t launch_generate_v4(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
 hipError_t launch_consume_v4(const GenArgs &a, const LaunchCfg &c, hipStream_t st);
+// Chunks of V1 runs: aggregate pass, then generating pass (groupjump.cpp
+// plans them); w32 selects 32-bit words.
+hipError_t launch_v1_chunks(const V1ChunkArgs &a, bool w32, hipStream_t st);
 // Chunks of V2/V4 group runs (groupjump.cpp plans them).
 hipError_t launch_group_chunks(const GroupJumpArgs &a, int variant, hipStream_t st);
 hipError_t launch_group_chunks_v2(const GroupJumpArgs &a, hipStream_t st);

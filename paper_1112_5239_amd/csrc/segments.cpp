@@ -306,9 +306,8 @@ int check_ragged_args(cprng_t *h, uint32_t *out, const uint64_t *lengths, const 
                       uint64_t *total, uint64_t *max_len)
 {
     if (!h || !out || !lengths) return set_error(CPRNG_E_INVAL, "NULL argument");
-    if (h->variant != CPRNG_V0_PLAIN && h->variant != CPRNG_V2_SHMEM && h->variant != CPRNG_V4_XOR64)
-        return set_error(CPRNG_E_UNSUPPORTED,
-                         "batched uneven streams need a GF(2)-linear variant (V0, V2 or V4) for the jump-ahead");
+    if (h->variant == CPRNG_V3_BBS)
+        return set_error(CPRNG_E_UNSUPPORTED, "batched uneven streams: the BBS variant has no jump-ahead");
     if (h->flags & CPRNG_F_INTERLEAVED) return set_error(CPRNG_E_UNSUPPORTED, "interleaved layout has no ragged form");
     if ((uintptr_t)out % 4u) return set_error(CPRNG_E_INVAL, "out must be 4-byte aligned");
     uint64_t acc = 0, mx = 0;
@@ -407,6 +406,7 @@ extern "C" int cprng_generate_ragged(cprng_t *h, uint32_t *out, const uint64_t *
     int rc = check_ragged_args(h, out, lengths, offsets, &total, &max_len);
     if (rc) return rc;
     DevGuard g(h->device);
+    if (h->variant == CPRNG_V1_NAIVE3) return ragged_v1(h, out, lengths, offsets, (hipStream_t)stream);
     if (h->variant != CPRNG_V0_PLAIN) return ragged_groups(h, out, lengths, offsets, (hipStream_t)stream);
     rc = ensure_common(h);
     if (rc) return rc;

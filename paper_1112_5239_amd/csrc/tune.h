@@ -34,6 +34,8 @@ int timing_end(cprng_t *h, hipStream_t st);
 int group_minpoly(cprng_t *h);
 void group_jump_rows(const cprng_t *h, uint64_t chunk, uint32_t rows, std::vector<uint32_t> &out);
 int ragged_groups(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets, hipStream_t st);
+// Batched uneven runs of V1: per-generator jumps and an aggregate pass.
+int ragged_v1(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets, hipStream_t st);
 void destroy_group_buffers(cprng_t *h);
 
 }  // namespace cprng_impl

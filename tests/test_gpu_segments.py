@@ -100,10 +100,11 @@ def test_ragged_graph_replay_continues_streams(orc, G, torch):
     _check_ragged(orc, G, torch, rng.integers(1, 40000, 64), calls=3, tuning=dict(chunk=2048))
 
 
-def test_ragged_rejects_other_variants(G):
+def test_ragged_rejects_bbs_and_interleaved(G):
+    # The BBS variant has no jump-ahead; the interleaved layout no ragged form.
     from paper_1112_5239_amd import CprngError
-    for v in ("v1", "v2"):
-        g = G.Generator(64, v, seed=0)
+    for v, kw in (("v3", {}), ("v0", {"interleaved": True})):
+        g = G.Generator(64, v, seed=0, **kw)
         try:
             with pytest.raises(CprngError) as e:
                 g.generate_ragged(np.full(64, 10, dtype=np.uint64))

@@ -1,0 +1,77 @@
+"""GPU parity of batched uneven runs for V1 (Listing 1).
+
+Long runs are split into chunks; each chunk jumps the three generators ahead
+(GF(2) jump polynomials, the Weyl counter arithmetically) and starts its x
+from an aggregate pass over the earlier chunks of its stream.  Every run and
+end state is compared bit for bit with the oracle generating each stream
+alone, with chunk lengths small enough to cross many chunk boundaries.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def G(torch):
+    from paper_1112_5239_amd import generator
+    return generator
+
+
+def _lengths(ns, seed, cap):
+    rng = np.random.default_rng(seed)
+    base = np.array([0, 1, 3, 31, 32, 33, 63, 64, 65, 1000, cap], dtype=np.uint64)
+    extra = rng.integers(0, cap + 1, size=ns - base.size).astype(np.uint64)
+    return rng.permutation(np.concatenate([base, extra]))
+
+
+def _run(orc, G, kw, ov, W, ns, lengths, sigma, chunk, offsets=None, calls=2):
+    g = G.Generator(ns, "v1", seed=sigma, **kw)
+    try:
+        if chunk:
+            g.set_tuning(chunk=chunk)
+        st = orc.seed(ov, sigma, 0, ns, W=W)
+        offs = offsets if offsets is not None else np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.uint64)
+        for _ in range(calls):
+            out = G.as_u32(g.generate_ragged(lengths, offsets=offsets))
+            for s in range(ns):
+                one = st[s:s + 1].copy()
+                want, _ = orc.generate(ov, one, int(lengths[s]), W=W)
+                st[s] = one[0]
+                got = out[int(offs[s]):int(offs[s]) + int(lengths[s])]
+                assert np.array_equal(got, want[0]), f"stream {s} (length {int(lengths[s])})"
+            assert np.array_equal(g.get_state(), st), "end states differ"
+    finally:
+        g.close()
+
+
+CASES = [({}, 1, 64), ({"v1_xor64": True}, None, 64), ({"w32": True}, 1, 32)]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("chunk", [64, 1024, 0])
+def test_v1_ragged_matches_the_oracle(orc, G, case, chunk):
+    kw, ov, W = CASES[case]
+    if ov is None:
+        ov = 1 | orc.F_XOR64
+    lengths = _lengths(128, 91, 5000)
+    _run(orc, G, kw, ov, W, 128, lengths, sigma=91, chunk=chunk)
+
+
+def test_v1_ragged_offsets_and_a_long_run(orc, G):
+    lengths = _lengths(64, 92, 3000)
+    lengths[7] = 150000                           # 147 chunks of 1,024
+    offs = np.zeros(64, dtype=np.uint64)
+    pos = 0
+    for s in reversed(range(64)):
+        offs[s] = pos
+        pos += int(lengths[s]) + 3
+    _run(orc, G, {}, 1, 64, 64, lengths, sigma=92, chunk=1024, offsets=offs, calls=1)
