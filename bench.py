@@ -210,6 +210,24 @@ def run_ragged_groups(torch, G, args, ref_gn):
             "ratio_to_plain_v2_stream_major": round(gn / ref_gn, 4) if ref_gn else None}
 
 
+def run_ragged_v1(torch, G, args, ref_gn):
+    """Batched uneven runs of V1 on the batched workload's lengths (4,096
+    streams, log-uniform [1e3, 1e7], seed 2); ratio against plain V1 in the
+    stream-major layout."""
+    from paper_1112_5239_amd import workloads
+    lengths = workloads.ragged_lengths()
+    total = int(lengths.sum())
+    g = G.Generator(lengths.size, "v1", seed=2)
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    ms, _ = timed(torch, lambda: g.generate_ragged(lengths, out=out), max(3, args.steps // 20), 2)
+    g.close()
+    del out
+    gn = total / (ms / 1e3) / 1e9
+    return {"workload": f"V1, 4096 streams, log-uniform lengths [1e3,1e7] (total {total}), seed 2",
+            "ms": round(ms, 4), "gnumbers_per_s": round(gn, 2),
+            "ratio_to_plain_v1_stream_major": round(gn / ref_gn, 4) if ref_gn else None}
+
+
 def run_valu_probes(torch, L):
     """Issue rates (wave64 instructions per CU per clock at the peak clock) of
     the three probe classes, with every CU holding its full complement of waves."""
@@ -365,6 +383,8 @@ def main():
         log(f"[bench] ragged: {extra['ragged']}")
         extra["ragged_groups_v2"] = run_ragged_groups(torch, G, args, extra["v2_stream_major"]["gnumbers_per_s"])
         log(f"[bench] ragged groups (V2): {extra['ragged_groups_v2']}")
+        extra["ragged_v1"] = run_ragged_v1(torch, G, args, extra["v1_stream_major"]["gnumbers_per_s"])
+        log(f"[bench] ragged (V1): {extra['ragged_v1']}")
         extra["consume"] = run_consume(torch, G, args)
         log(f"[bench] consume: {extra['consume']}")
         extra["dpp_study"] = run_dpp_study(torch, G)
