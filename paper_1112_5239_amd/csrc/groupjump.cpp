@@ -491,11 +491,12 @@ int ragged_v1(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t
     }
     if (total == 0) return CPRNG_OK;
     const uint64_t jump_steps = (uint64_t)(P.deg[0] + P.deg[1] + P.deg[2]);
-    // Chunk: a power of two giving about 256 chunks (4 waves) per CU, at least
-    // 16 x the jump's steps, at most 2^20.
+    // Chunk: a power of two giving about 2,048 chunks (32 waves) per CU --
+    // one lane per chunk, and the generators' serial chains need many waves
+    // -- at least 16 x the jump's steps, at most 2^20.
     uint64_t chunk = h->tuning.chunk ? h->tuning.chunk : 0;
     if (!chunk) {
-        const uint64_t target = total / ((uint64_t)h->n_cu * 256u) + 1;
+        const uint64_t target = total / ((uint64_t)h->n_cu * 2048u) + 1;
         chunk = 1;
         while (chunk < target) chunk <<= 1;
         chunk = std::max<uint64_t>(chunk, 16ull * jump_steps);
