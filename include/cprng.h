@@ -75,10 +75,13 @@ enum cprng_flags {
     CPRNG_F_INTERLEAVED = 1u << 8,
     /* V1 only: the three generators use 32-bit words (high halves are 0). */
     CPRNG_F_V1_W32 = 1u << 9,
+    /* Seeds hold n_streams entries: stream s's SplitMix64 counter starts at
+     * seeds[s] (the single-seed rule is the case seeds[s] = sigma*2^32 + s). */
+    CPRNG_F_SEED_PER_STREAM = 1u << 10,
     /* V1 only, 64-bit words: Listing 1's first generator is xor64 (triple
      * 13, 7, 17) instead of Algorithm 2's triple (13, 17, 5) on the 64-bit
      * word.  Same state layout and seeding. */
-    CPRNG_F_V1_XOR64 = 1u << 10
+    CPRNG_F_V1_XOR64 = 1u << 11
 };
 
 enum cprng_status {
@@ -100,6 +103,8 @@ typedef struct cprng_params {
     const uint32_t *comb2;     /* host, `group` entries in [0,C); NULL = default */
     int32_t device;            /* HIP device ordinal; -1 = current device */
     uint32_t reserved;
+    const uint64_t *seeds;     /* host, n_streams entries with CPRNG_F_SEED_PER_STREAM
+                                  (seed is then ignored); NULL otherwise */
 } cprng_params_t;
 
 /* ------------------------------------------------------------------------ */
@@ -107,7 +112,8 @@ typedef struct cprng_params {
 /* ------------------------------------------------------------------------ */
 
 /* Create a generator of n_streams streams on the current HIP device.
- * seeds: host, one uint64 base seed sigma.  Stream s is initialised from
+ * seeds: host, one uint64 base seed sigma (n_streams seeds with
+ * CPRNG_F_SEED_PER_STREAM in variant).  Stream s is initialised from
  * SplitMix64 draws whose counter starts at sigma*2^32 + s (the paper seeds
  * per-thread parameters on the host with ISAAC, Section 6.1); generator
  * words that would all be zero are redrawn.  V2 uses group size 32 and the
@@ -198,8 +204,14 @@ int cprng_generate_requests(cprng_t *h, const cprng_request_t *reqs, uint32_t co
 
 /* 32-bit words of state per stream: V0 5 {x128 x,y,z,w, x}, V2 6 {x128
  * x,y,z,w, x, previous mixed word}, V1 23 {xorshift lo,hi; xor128 x,y,z,w
- * as lo,hi; xorwow x,y,z,w,v,d as lo,hi; x}.  Returns < 0 on a bad handle. */
+ * as lo,hi; xorwow x,y,z,w,v,d as lo,hi; x}, V3 10 {BBS slots 1..8, x,
+ * previous mixed word}, V4 4 {xor64 lo,hi, x, previous mixed word}.
+ * Returns < 0 on a bad handle. */
 int cprng_state_words(const cprng_t *h);
+
+/* Bytes of all stream states (n_streams * state_words * 4); 0 on a bad
+ * handle. */
+size_t cprng_state_bytes(const cprng_t *h);
 
 /* Copy all states to / from host memory, stream after stream, each stream's
  * words in the order above (host, n_streams * state_words uint32).  These

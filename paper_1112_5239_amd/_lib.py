@@ -13,7 +13,8 @@ LIB_PATH = os.path.join(PKG, "libcprng.so")
 V0_PLAIN, V1_NAIVE3, V2_SHMEM, V3_BBS, V4_XOR64 = 0, 1, 2, 3, 4
 F_INTERLEAVED = 1 << 8
 F_V1_W32 = 1 << 9
-F_V1_XOR64 = 1 << 10
+F_SEED_PER_STREAM = 1 << 10
+F_V1_XOR64 = 1 << 11
 
 OK, E_INVAL, E_NOMEM, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4
 
@@ -29,7 +30,8 @@ class CprngError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("variant", C.c_uint32), ("n_streams", C.c_uint32),
                 ("group", C.c_uint32), ("seed", C.c_uint64), ("comb1", C.POINTER(C.c_uint32)),
-                ("comb2", C.POINTER(C.c_uint32)), ("device", C.c_int32), ("reserved", C.c_uint32)]
+                ("comb2", C.POINTER(C.c_uint32)), ("device", C.c_int32), ("reserved", C.c_uint32),
+                ("seeds", C.POINTER(C.c_uint64))]
 
 
 class Request(C.Structure):
@@ -56,7 +58,7 @@ class Tuning(C.Structure):
 
 EXPORTED = [
     "cprng_create", "cprng_create_ex", "cprng_destroy", "cprng_generate", "cprng_consume_qc",
-    "cprng_generate_ragged", "cprng_generate_requests", "cprng_state_words", "cprng_get_state",
+    "cprng_generate_ragged", "cprng_generate_requests", "cprng_state_words", "cprng_state_bytes", "cprng_get_state",
     "cprng_set_state", "cprng_n_streams", "cprng_variant", "cprng_default_combs", "cprng_default_bbs_combs",
     "cprng_set_tuning", "cprng_get_tuning", "cprng_autotune", "cprng_autotune_ragged",
     "cprng_enable_timing", "cprng_last_kernel_ms", "cprng_probe_fill", "cprng_probe_copy", "cprng_probe_valu",
@@ -87,6 +89,7 @@ def lib():
         "cprng_generate_ragged": (i32, [vp, vp, vp, vp, vp]),
         "cprng_generate_requests": (i32, [vp, C.POINTER(Request), u32, vp]),
         "cprng_state_words": (i32, [vp]),
+        "cprng_state_bytes": (C.c_size_t, [vp]),
         "cprng_get_state": (i32, [vp, vp, C.c_size_t]),
         "cprng_set_state": (i32, [vp, vp, C.c_size_t]),
         "cprng_n_streams": (u32, [vp]),
@@ -149,7 +152,9 @@ def cprng_create(seed: int, n_streams: int, variant: int) -> int:
 
 
 def cprng_create_ex(variant: int, n_streams: int, seed: int, group: int = 0, comb1=None, comb2=None,
-                    device: int = -1) -> int:
+                    device: int = -1, seeds=None) -> int:
+    """seeds: optional n_streams per-stream SplitMix64 start counters (sets
+    F_SEED_PER_STREAM)."""
     p = Params()
     p.struct_size = C.sizeof(Params)
     p.variant = variant
@@ -164,6 +169,11 @@ def cprng_create_ex(variant: int, n_streams: int, seed: int, group: int = 0, com
         keep += [a1, a2]
         p.comb1 = C.cast(a1, C.POINTER(C.c_uint32))
         p.comb2 = C.cast(a2, C.POINTER(C.c_uint32))
+    if seeds is not None:
+        sa = (C.c_uint64 * len(seeds))(*[int(v) for v in seeds])
+        keep.append(sa)
+        p.seeds = C.cast(sa, C.POINTER(C.c_uint64))
+        p.variant = variant | F_SEED_PER_STREAM
     h = C.c_void_p()
     _check(lib().cprng_create_ex(C.byref(p), C.byref(h)), "cprng_create_ex")
     return h.value
@@ -195,6 +205,10 @@ def cprng_generate_requests(h: int, reqs, stream=None) -> None:
         arr[i].length = n
         arr[i].out = _addr(o)
     _check(lib().cprng_generate_requests(h, arr, len(reqs), _addr(stream)), "cprng_generate_requests")
+
+
+def cprng_state_bytes(h: int) -> int:
+    return int(lib().cprng_state_bytes(h))
 
 
 def cprng_state_words(h: int) -> int:

@@ -92,8 +92,10 @@ int create_impl(const cprng_params_t *p, cprng_t **out)
     const uint32_t var = p->variant & 0xffu;
     const uint32_t flags = p->variant & ~0xffu;
     if (words_per_stream((int)var) < 0) return set_error(CPRNG_E_INVAL, "unknown variant");
-    if (flags & ~(uint32_t)(CPRNG_F_INTERLEAVED | CPRNG_F_V1_W32 | CPRNG_F_V1_XOR64))
+    if (flags & ~(uint32_t)(CPRNG_F_INTERLEAVED | CPRNG_F_V1_W32 | CPRNG_F_V1_XOR64 | CPRNG_F_SEED_PER_STREAM))
         return set_error(CPRNG_E_INVAL, "unknown flag bits");
+    if ((flags & CPRNG_F_SEED_PER_STREAM) && !p->seeds)
+        return set_error(CPRNG_E_INVAL, "CPRNG_F_SEED_PER_STREAM needs the seeds array");
     if ((flags & CPRNG_F_V1_W32) && var != CPRNG_V1_NAIVE3)
         return set_error(CPRNG_E_INVAL, "CPRNG_F_V1_W32 applies to the V1 variant only");
     if ((flags & CPRNG_F_V1_XOR64) && (var != CPRNG_V1_NAIVE3 || (flags & CPRNG_F_V1_W32)))
@@ -155,7 +157,10 @@ int create_impl(const cprng_params_t *p, cprng_t **out)
     // Seed on the host, pack SoA, upload.
     const uint64_t nwords = (uint64_t)h->ns * h->words;
     std::vector<uint32_t> aos(nwords), soa(nwords);
-    seed_streams((int)var, (flags & CPRNG_F_V1_W32) != 0, p->seed, 0, h->ns, aos.data());
+    if (flags & CPRNG_F_SEED_PER_STREAM)
+        seed_streams_at((int)var, (flags & CPRNG_F_V1_W32) != 0, p->seeds, h->ns, aos.data());
+    else
+        seed_streams((int)var, (flags & CPRNG_F_V1_W32) != 0, p->seed, 0, h->ns, aos.data());
     for (uint64_t s = 0; s < h->ns; ++s)
         for (uint32_t k = 0; k < h->words; ++k) soa[k * (uint64_t)h->ns + s] = aos[s * h->words + k];
     if (hipMalloc(&h->d_state, nwords * sizeof(uint32_t)) != hipSuccess)
@@ -334,6 +339,7 @@ int cprng_create(const uint64_t *seeds, uint32_t n_streams, uint32_t variant, cp
     p.n_streams = n_streams;
     p.seed = seeds[0];
     p.device = -1;
+    if (variant & CPRNG_F_SEED_PER_STREAM) p.seeds = seeds;
     return create_impl(&p, out);
 }
 
@@ -392,6 +398,12 @@ int cprng_state_words(const cprng_t *h)
 {
     if (!h) return set_error(CPRNG_E_INVAL, "NULL handle");
     return (int)h->words;
+}
+
+size_t cprng_state_bytes(const cprng_t *h)
+{
+    if (!h) return 0;
+    return (size_t)h->ns * h->words * sizeof(uint32_t);
 }
 
 uint32_t cprng_n_streams(const cprng_t *h) { return h ? h->ns : 0u; }

@@ -24,6 +24,8 @@ int words_per_stream(int variant);
 // Fill AoS words (n_streams x words) for streams [first, first+count).
 void seed_streams(int variant, bool w32, uint64_t sigma, uint64_t first, uint64_t count,
                   uint32_t *aos);
+// The same from an explicit SplitMix64 start counter per stream.
+void seed_streams_at(int variant, bool w32, const uint64_t *counters, uint64_t count, uint32_t *aos);
 // Default combination arrays for a group of C streams (C >= 3).
 bool default_combs(uint32_t C, uint32_t *comb1, uint32_t *comb2);
 // Default 16 arrangement arrays of the BBS variant (out: 16*C entries).

@@ -53,10 +53,17 @@ int words_per_stream(int variant)
 void seed_streams(int variant, bool w32, uint64_t sigma, uint64_t first, uint64_t count,
                   uint32_t *aos)
 {
+    std::vector<uint64_t> ctr(count);
+    for (uint64_t k = 0; k < count; ++k) ctr[k] = (sigma << 32) + first + k;
+    seed_streams_at(variant, w32, ctr.data(), count, aos);
+}
+
+void seed_streams_at(int variant, bool w32, const uint64_t *counters, uint64_t count, uint32_t *aos)
+{
     const int nw = words_per_stream(variant);
     const uint64_t mask = w32 ? 0xFFFFFFFFull : ~0ull;
     for (uint64_t k = 0; k < count; ++k) {
-        SplitMix64 r{(sigma << 32) + first + k};
+        SplitMix64 r{counters[k]};
         uint32_t *st = aos + k * (uint64_t)nw;
         std::memset(st, 0, sizeof(uint32_t) * nw);
         if (variant == CPRNG_V3_BBS) {

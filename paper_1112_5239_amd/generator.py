@@ -27,7 +27,8 @@ def _stream(stream):
 
 class Generator:
     def __init__(self, n_streams: int, variant="v0", seed: int = 0, group: int = 0, comb=None,
-                 interleaved: bool = False, w32: bool = False, v1_xor64: bool = False, device: int = -1):
+                 interleaved: bool = False, w32: bool = False, v1_xor64: bool = False, device: int = -1,
+                 seeds=None):
         _torch()
         v = _VARIANTS[variant] if isinstance(variant, str) else int(variant)
         if interleaved:
@@ -37,7 +38,10 @@ class Generator:
         if v1_xor64:
             v |= L.F_V1_XOR64
         c1, c2 = (comb if comb is not None else (None, None))
-        self.h = L.cprng_create_ex(v, n_streams, seed, group=group, comb1=c1, comb2=c2, device=device)
+        if seeds is not None and len(seeds) != n_streams:
+            raise ValueError("seeds needs one entry per stream")
+        self.h = L.cprng_create_ex(v, n_streams, seed, group=group, comb1=c1, comb2=c2, device=device,
+                                   seeds=seeds)
         self.n_streams = n_streams
         self.variant = v & 0xFF
         self.flags = v & ~0xFF

@@ -68,6 +68,10 @@ def test_invalid_arguments_rejected_before_device_work(L):
         L.cprng_create(0, 100, L.V4_XOR64)           # 100 % 32 != 0
     assert e.value.status == L.E_INVAL
     with pytest.raises(L.CprngError) as e:
+        L.cprng_create_ex(L.V0_PLAIN | L.F_SEED_PER_STREAM, 64, 0)   # flag without the seeds array
+    assert e.value.status == L.E_INVAL
+    assert L.lib().cprng_state_bytes(None) == 0
+    with pytest.raises(L.CprngError) as e:
         L.cprng_create_ex(L.V2_SHMEM, 64, 0, group=4, comb1=[1, 2, 3, 9], comb2=[2, 3, 0, 1])
     assert e.value.status == L.E_INVAL
     lib = L.lib()
