@@ -189,12 +189,15 @@ typedef struct cprng_request {
     uint32_t *out;             /* device, 4-byte aligned, `length` uint32 */
 } cprng_request_t;
 
-/* Serve a batch of requests (V0 only): request r receives the next `length`
- * outputs of its stream; several requests of one stream are served in array
- * order, one after the other.  Streams without a request keep their state.
- * reqs: host, count entries.  Same chunking and jump-ahead as
- * cprng_generate_ragged, one kernel launch per call.  Errors: E_INVAL,
- * E_UNSUPPORTED (V1, V2), E_NOMEM, E_HIP. */
+/* Serve a batch of requests (V0 and V1): request r receives the next
+ * `length` outputs of its stream; several requests of one stream are served
+ * in array order, one after the other.  Streams without a request keep their
+ * state.  reqs: host, count entries.  Same chunking and jump-ahead as
+ * cprng_generate_ragged: V0 in one kernel launch per call; V1 as one batched
+ * uneven call per round, round j serving the j-th request of every stream
+ * (so it waits for earlier work on `stream` like that call).  Errors:
+ * E_INVAL, E_UNSUPPORTED (V2, V3, V4: their streams advance by groups),
+ * E_NOMEM, E_HIP. */
 int cprng_generate_requests(cprng_t *h, const cprng_request_t *reqs, uint32_t count,
                             cprng_stream_t stream);
 

@@ -551,8 +551,8 @@ extern "C" int cprng_generate_requests(cprng_t *h, const cprng_request_t *reqs, 
                                        cprng_stream_t stream)
 {
     if (!h || (!reqs && count)) return set_error(CPRNG_E_INVAL, "NULL argument");
-    if (h->variant != CPRNG_V0_PLAIN)
-        return set_error(CPRNG_E_UNSUPPORTED, "requests need the V0 variant (GF(2)-linear jump-ahead)");
+    if (h->variant != CPRNG_V0_PLAIN && h->variant != CPRNG_V1_NAIVE3)
+        return set_error(CPRNG_E_UNSUPPORTED, "requests need the V0 or V1 variant (per-stream jump-ahead)");
     if (count == 0) return CPRNG_OK;
     uint64_t total = 0, max_len = 0;
     for (uint32_t r = 0; r < count; ++r) {
@@ -565,6 +565,33 @@ extern "C" int cprng_generate_requests(cprng_t *h, const cprng_request_t *reqs, 
     }
     if (total == 0) return CPRNG_OK;
     DevGuard g(h->device);
+    if (h->variant == CPRNG_V1_NAIVE3) {
+        // Round j serves the j-th non-empty request of every stream as one
+        // batched uneven call; outputs are addressed from the lowest request
+        // address.
+        std::unordered_map<uint32_t, uint32_t> seen;
+        std::vector<std::vector<const cprng_request_t *>> rounds;
+        uintptr_t lo = ~(uintptr_t)0;
+        for (uint32_t r = 0; r < count; ++r) {
+            if (reqs[r].length == 0) continue;
+            const uint32_t j = seen[reqs[r].stream]++;
+            if (j >= rounds.size()) rounds.emplace_back();
+            rounds[j].push_back(&reqs[r]);
+            lo = std::min(lo, (uintptr_t)reqs[r].out);
+        }
+        std::vector<uint64_t> lengths(h->ns), offs(h->ns);
+        for (const auto &rd : rounds) {
+            std::fill(lengths.begin(), lengths.end(), 0);
+            std::fill(offs.begin(), offs.end(), 0);
+            for (const cprng_request_t *q : rd) {
+                lengths[q->stream] = q->length;
+                offs[q->stream] = ((uintptr_t)q->out - lo) / 4u;
+            }
+            const int rc = ragged_v1(h, (uint32_t *)lo, lengths.data(), offs.data(), (hipStream_t)stream);
+            if (rc) return rc;
+        }
+        return CPRNG_OK;
+    }
     int rc = ensure_common(h);
     if (rc) return rc;
     SegCfg c = resolve_seg_cfg(h, total, max_len);

@@ -75,3 +75,45 @@ def test_v1_ragged_offsets_and_a_long_run(orc, G):
         offs[s] = pos
         pos += int(lengths[s]) + 3
     _run(orc, G, {}, 1, 64, 64, lengths, sigma=92, chunk=1024, offsets=offs, calls=1)
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_v1_requests_multiple_per_stream_and_misaligned(orc, G, torch, case):
+    kw, ov, W = CASES[case]
+    if ov is None:
+        ov = 1 | orc.F_XOR64
+    ns = 24
+    g = G.Generator(ns, "v1", seed=12, **kw)
+    try:
+        g.set_tuning(chunk=256)
+        rng = np.random.default_rng(6)
+        st = orc.seed(ov, 12, 0, ns, W=W)
+        for call in range(2):
+            reqs, bufs, plan = [], [], []
+            for r in range(40):
+                s = int(rng.integers(0, ns // 2))        # streams >= ns/2 stay untouched
+                L = int(rng.integers(0, 3000))
+                b = torch.zeros(L + 8, dtype=torch.int32, device="cuda")
+                shift = int(rng.integers(0, 4))
+                reqs.append((s, L, b.data_ptr() + 4 * shift))
+                bufs.append((b, shift))
+                plan.append((s, L))
+            g.generate_requests(reqs)
+            torch.cuda.synchronize()
+            per_stream = {}
+            for s, L in plan:
+                per_stream.setdefault(s, []).append(L)
+            want_by_stream = {}
+            for s, Ls in per_stream.items():
+                o, _ = orc.generate(ov, st[s:s + 1], sum(Ls), W=W)
+                want_by_stream[s] = o[0]
+            cursor = {s: 0 for s in per_stream}
+            for (s, L), (b, shift) in zip(plan, bufs):
+                got = G.as_u32(b)
+                c = cursor[s]
+                assert np.array_equal(got[shift:shift + L], want_by_stream[s][c:c + L]), f"call {call} stream {s}"
+                assert not got[:shift].any() and not got[shift + L:].any()
+                cursor[s] = c + L
+        assert np.array_equal(g.get_state(), st)
+    finally:
+        g.close()
