@@ -303,7 +303,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=50,
                     help="untimed steps; the first ~50 launches after the GPU has been idle run slower")
-    ap.add_argument("--workload", default="paper", choices=["paper", "ragged", "serving"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "ragged", "serving", "consume"])
     ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -328,6 +328,16 @@ def main():
         from paper_1112_5239_amd import serving
         res = serving.bench_line(args)
         print(json.dumps(res), flush=True)
+        return
+    if args.workload == "consume":
+        # The in-kernel consumption kernels alone (ALU-bound), for profiling.
+        res = run_consume(torch, G, args)
+        log(f"[bench] consume: {res}")
+        print(json.dumps({"metric": "in-kernel consumption: Gnumbers/s against the ALU roofline",
+                          "value": res["v2"]["gnumbers_per_s"], "unit": "Gnumbers/s", "n_gpus": 1,
+                          "ms_per_step": res["v2"]["ms"], "higher_is_better": True, "dtype": "u32",
+                          "data": "synthetic", "config": {"workload": res["workload"]},
+                          "consume": res}), flush=True)
         return
     if args.workload == "ragged":
         # The batched half of the metric alone, for profiling: uneven streams
