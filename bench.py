@@ -125,6 +125,33 @@ def cpu_baseline_paper(budget_s=12.0):
                       f"{elapsed:.1f} s of single-thread CPU time"}
 
 
+def cpu_baseline_all_cores(budget_s=8.0):
+    """The same oracle run by one thread per host core on disjoint slices of
+    exchange groups (ctypes releases the GIL inside the oracle's C code)."""
+    import concurrent.futures as cf
+    from oracle import oracle as O
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    comb = O.comb_tables(32)
+    batch = 2048
+    O.generate(2, O.seed(2, 1, 0, 32), 16, comb=comb)
+    def work(tid):
+        done, first = 0, tid * batch
+        t1 = time.perf_counter()
+        while time.perf_counter() - t1 < budget_s and first < (1 << 20):
+            st = O.seed(2, 1, first, batch)
+            O.generate(2, st, 1024, comb=comb)
+            done += batch
+            first += threads * batch
+        return done
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        done = sum(ex.map(work, range(threads)))
+    wall = time.perf_counter() - t0
+    return {"value": done * 1024 / wall / 1e9, "unit": "Gnumbers/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} of the 2^20 streams x 1024 outputs (exchange variant, seed 1), "
+                      f"{threads} threads, {wall:.1f} s wall"}
+
+
 def run_paper(torch, G, L, args, interleaved, steps=None, warmup=None):
     ns, n = 1 << 20, 1024
     log(f"[bench] paper workload: V2, {ns} streams x {n}, seed 1, "
@@ -405,6 +432,11 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_paper()
         log(f"[bench] cpu baseline: {cpu}")
+        if not args.no_extra:
+            extra["cpu_baseline_all_cores"] = cpu_baseline_all_cores()
+            log(f"[bench] cpu baseline, all cores: {extra['cpu_baseline_all_cores']}")
+    if "fill_probe" in extra:
+        extra["headline_vs_fill_probe"] = round(achieved / extra["fill_probe"]["gbs"], 4)
     line = {
         "metric": "Gnumbers/s (uint32 to HBM) at 1 GPU, % HBM write peak; plain vs batched",
         "value": round(value, 3),

@@ -462,3 +462,19 @@ def test_consume_predicate_edges(orc):
     v = np.float32(V) * np.float32(2.0 ** -24)
     assert (u * u) + (v * v) == np.float32(1.0)
     assert not orc.qc_hit(U << 8, V << 8)
+
+
+def test_consume_float_predicate_vs_exact_integer_predicate(orc):
+    # The binary32 predicate against the exact one, U^2 + V^2 < 2^48 on
+    # U = r1 >> 8, V = r2 >> 8 (power-of-two scaling is exact): they can only
+    # disagree within about 2^-23 of the unit circle, so over ~2M pairs the
+    # disagreement count is tiny; it is reported, not assumed zero.
+    st = orc.seed(0, 21, 0, 32)
+    out, _ = orc.generate(0, st.copy(), 1 << 17)
+    counts = orc.consume_qc(0, st, 1 << 17)
+    U = (out[:, 0::2] >> 8).astype(np.int64)
+    V = (out[:, 1::2] >> 8).astype(np.int64)
+    exact = (U * U + V * V < (1 << 48)).sum(axis=1)
+    diff = int(np.abs(counts.astype(np.int64) - exact).sum())
+    print(f"float vs exact integer predicate: {diff} of {U.size} pairs differ")
+    assert diff <= 8
