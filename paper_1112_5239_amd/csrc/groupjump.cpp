@@ -208,11 +208,12 @@ struct GroupSim {
     }
 };
 
-// q(A) v == 0 for a few random states v.
+// q(A) v == 0 for 24 random states v (if q(A) != 0, its kernel is a proper
+// subspace, which holds a random v with probability at most 1/2 per trial).
 bool check_annihilates(GroupSim g, const Poly &q, std::mt19937_64 &rng)
 {
     const int d = pdeg(q);
-    for (int trial = 0; trial < 3; ++trial) {
+    for (int trial = 0; trial < 24; ++trial) {
         for (auto &x : g.w) x = (uint32_t)rng();
         std::vector<uint32_t> acc(g.w.size(), 0);
         for (int k = 0; k <= d; ++k) {
@@ -227,7 +228,8 @@ bool check_annihilates(GroupSim g, const Poly &q, std::mt19937_64 &rng)
 }
 
 // Minimal polynomial of a linear map on `nwords` words of W bits (mask) given
-// its one-step function, found and checked as for the group map.
+// its one-step function, found and checked (24 random states) as for the
+// group map.
 bool linear_minpoly(size_t nwords, uint64_t mask, const std::function<void(std::vector<uint64_t> &)> &step,
                     std::mt19937_64 &rng, Poly &q)
 {
@@ -258,7 +260,7 @@ bool linear_minpoly(size_t nwords, uint64_t mask, const std::function<void(std::
         if (!long_enough) continue;
         bool annihilates = true;
         const int d = pdeg(p);
-        for (int trial = 0; trial < 3 && annihilates; ++trial) {
+        for (int trial = 0; trial < 24 && annihilates; ++trial) {
             std::vector<uint64_t> v(nwords), acc(nwords, 0);
             for (auto &x : v) x = rng() & mask;
             for (int k = 0; k <= d; ++k) {
