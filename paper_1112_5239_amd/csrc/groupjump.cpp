@@ -120,6 +120,38 @@ Poly plcm(const Poly &a, const Poly &b)
     pdivmod(pmul(a, b), pgcd(a, b), q, r);
     return q;
 }
+// sum_{i=1..n} X^i mod m, by doubling: S(2k) = S(k) + X^k S(k),
+// S(k+1) = S(k) + X^(k+1).
+Poly pgeomsum(uint64_t n, const Poly &m)
+{
+    Poly S, P{1}, X;
+    pflip(X, 1);
+    pmod(P, m);
+    pmod(X, m);
+    bool started = false;                           // past the leading zero bits of n
+    for (int b = 63; b >= 0; --b) {
+        if (started) {
+            Poly PS = pmulmod(P, S, m);
+            for (size_t i = 0; i < PS.size(); ++i) {
+                if (i >= S.size()) S.resize(i + 1, 0);
+                S[i] ^= PS[i];
+            }
+            ptrim(S);
+            P = pmulmod(P, P, m);
+        }
+        if ((n >> b) & 1u) {
+            started = true;
+            P = pmulmod(P, X, m);
+            for (size_t i = 0; i < P.size(); ++i) {
+                if (i >= S.size()) S.resize(i + 1, 0);
+                S[i] ^= P[i];
+            }
+            ptrim(S);
+        }
+    }
+    return S;
+}
+
 // X^e mod m
 Poly pxpow(uint64_t e, const Poly &m)
 {
@@ -527,7 +559,15 @@ int ragged_v1(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t
         off[k] = row_words;
         row_words += wk[k];
     }
-    std::vector<uint32_t> rows((size_t)n_rows * row_words, 0);
+    // rows 0..n_rows-1: X^(c * chunk) per generator; row n_rows: the sums
+    // sum_{i=1..chunk} X^i of the xorshift and xor128 maps (full chunks'
+    // aggregates)
+    std::vector<uint32_t> rows((size_t)(n_rows + 1) * row_words, 0);
+    for (int k = 0; k < 2; ++k) {
+        const Poly g = pgeomsum(chunk, P.q[k]);
+        for (int b = 0; b < P.deg[k]; ++b)
+            if (pbit(g, b)) rows[(size_t)n_rows * row_words + off[k] + (b >> 5)] |= 1u << (b & 31);
+    }
     for (int k = 0; k < 3; ++k) {
         const Poly base = pxpow(chunk, P.q[k]);
         Poly r{1};
@@ -544,12 +584,21 @@ int ragged_v1(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t
         offs[s] = offsets ? offsets[s] : acc;
         acc += lengths[s];
     }
+    // aggregate pass order: full chunks, then the shorter last ones
+    std::vector<uint32_t> order;
+    order.reserve(items.size());
+    for (int pass = 0; pass < 2; ++pass)
+        for (uint32_t i = 0; i < (uint32_t)items.size(); ++i)
+            if ((items[i].len == chunk) == (pass == 0)) order.push_back(i);
     // The buffers are reused by the next call: wait for the previous one.
     HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
     const size_t nwords = (size_t)h->ns * h->words;
     int rc;
     if ((rc = ensure_buf(&h->d_gj_next, &h->gj_next_cap, nwords))) return rc;
     if ((rc = ensure_buf(&h->d_v1_items, &h->v1_items_cap, items.size()))) return rc;
+    if ((rc = ensure_buf(&h->d_v1_order, &h->v1_order_cap, order.size()))) return rc;
+    HIP_TRY(hipMemcpy(h->d_v1_order, order.data(), order.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
+            "hipMemcpy order");
     if ((rc = ensure_buf(&h->d_v1_agg, &h->v1_agg_cap, items.size()))) return rc;
     if ((rc = ensure_buf(&h->d_gj_rows, &h->gj_rows_cap, rows.size()))) return rc;
     if ((rc = ensure_buf(&h->d_gj_offsets, &h->gj_offsets_cap, offs.size()))) return rc;
@@ -574,6 +623,10 @@ int ragged_v1(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t
     a.agg = h->d_v1_agg;
     a.out = out;
     a.offsets = h->d_gj_offsets;
+    a.chunk = chunk;
+    a.sum_row = n_rows;
+    a.pad = 0;
+    a.order = h->d_v1_order;
     int trc = timing_begin(h, st);
     if (trc) return trc;
     HIP_TRY(launch_copy(h->d_gj_next, h->d_state, nwords, st), "state copy");
@@ -586,8 +639,10 @@ void destroy_group_buffers(cprng_t *h)
 {
     if (h->d_v1_items) (void)hipFree(h->d_v1_items);
     if (h->d_v1_agg) (void)hipFree(h->d_v1_agg);
+    if (h->d_v1_order) (void)hipFree(h->d_v1_order);
     h->d_v1_items = nullptr;
     h->d_v1_agg = nullptr;
+    h->d_v1_order = nullptr;
     if (h->d_gj_next) (void)hipFree(h->d_gj_next);
     if (h->d_gj_items) (void)hipFree(h->d_gj_items);
     if (h->d_gj_rows) (void)hipFree(h->d_gj_rows);

@@ -116,4 +116,6 @@ struct cprng {
     size_t v1_items_cap = 0;
     uint32_t *d_v1_agg = nullptr;
     size_t v1_agg_cap = 0;
+    uint32_t *d_v1_order = nullptr;
+    size_t v1_order_cap = 0;
 };

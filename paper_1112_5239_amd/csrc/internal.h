@@ -114,6 +114,10 @@ struct V1ChunkArgs {
     uint32_t *agg;              // per chunk: xor of its strategy words
     uint32_t *out;
     const uint64_t *offsets;    // per stream
+    uint64_t chunk;             // length of a full chunk
+    uint32_t sum_row;           // row of sum_{i=1..chunk} X^i (xorshift and xor128 parts)
+    uint32_t pad;
+    const uint32_t *order;      // aggregate pass: full chunks first, then the shorter last ones
 };
 
 struct LaunchCfg {
