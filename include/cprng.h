@@ -266,7 +266,10 @@ typedef struct cprng_tuning {
     uint32_t chunk;            /* ragged/requests: outputs per chunk (multiple of 64) */
     uint32_t waves_per_cu;     /* ragged/requests (store 1/2/4) and pipelined generate:
                                   persistent waves per CU (0 = default); LDS-transposed
-                                  generate and ragged store 7/8: residency cap (0 = none) */
+                                  generate and ragged store 7/8: residency cap (0 = none);
+                                  interleaved tiles: persistent workgroups per CU, each
+                                  taking tiles of its XCD's band in turn (0 = one
+                                  workgroup per tile, the default) */
     uint32_t streams_per_lane; /* LDS-transposed generate: 1, 2 or 4 streams per lane;
                                   interleaved tiles: 2 = two tile buffers, so each
                                   round's stores overlap the next round's steps */

@@ -206,6 +206,9 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
         if (h->tuning.block) c.block = h->tuning.block;
         if (h->tuning.unroll) c.unroll = h->tuning.unroll;
         if (h->tuning.exchange) c.exchange = h->tuning.exchange;
+        // waves_per_cu: persistent workgroups per CU (a multiple of 8 overall
+        // keeps each workgroup's tiles in its XCD's band); 0 = one per tile
+        if (h->tuning.waves_per_cu) c.grid = h->n_cu * h->tuning.waves_per_cu;
         return c;
     }
     LaunchCfg c = default_cfg(h->variant, (h->flags & CPRNG_F_V1_W32) != 0, consume);

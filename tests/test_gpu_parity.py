@@ -352,3 +352,12 @@ def test_consume_paper_scale_sampled(orc, G, torch):
         assert abs(pi_est - np.pi) < 6 * sigma
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("name,variant", [("v2", 2), ("v0", 0), ("v4", 4)])
+def test_interleaved_persistent_workgroups(orc, G, name, variant):
+    # 2^17 streams in 512 tiles of 256 on one persistent workgroup per CU:
+    # each workgroup takes two tiles (its XCD band), rounds plus a tail.
+    ns, n = 1 << 17, 200
+    _ilv_check(orc, G, name, variant, ns, n, sigma=28,
+               tuning=dict(block=256, unroll=16, store=4, streams_per_lane=2, waves_per_cu=1), calls=2)
