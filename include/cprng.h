@@ -181,6 +181,17 @@ int cprng_consume_qc(cprng_t *h, uint64_t *counts, uint64_t n_per_stream, cprng_
 int cprng_generate_ragged(cprng_t *h, uint32_t *out, const uint64_t *lengths,
                           const uint64_t *offsets, cprng_stream_t stream);
 
+/* Host-only self-test of the jump-ahead used by cprng_generate_ragged (no
+ * device work, no handle).  variant: CPRNG_V2_SHMEM or CPRNG_V4_XOR64 (a
+ * group of C streams, comb1/comb2 host arrays of C entries or NULL for the
+ * library's defaults) or CPRNG_V1_NAIVE3 with its flags (C, comb1, comb2
+ * unused).  Finds the minimal polynomials as a handle would, then checks on
+ * random states that the jump polynomial X^J mod q reproduces J steps of the
+ * map (for V1 also the closed-form sum of the first J outputs).  Returns
+ * CPRNG_OK, E_INVAL for bad arguments, E_HIP when a check fails. */
+int cprng_jump_selftest(uint32_t variant, uint32_t C, const uint32_t *comb1, const uint32_t *comb2,
+                        uint64_t J);
+
 /* One request of cprng_generate_requests(). */
 typedef struct cprng_request {
     uint32_t stream;           /* stream id < n_streams */

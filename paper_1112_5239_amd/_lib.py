@@ -59,7 +59,7 @@ class Tuning(C.Structure):
 EXPORTED = [
     "cprng_create", "cprng_create_ex", "cprng_destroy", "cprng_generate", "cprng_consume_qc",
     "cprng_generate_ragged", "cprng_generate_requests", "cprng_state_words", "cprng_state_bytes", "cprng_get_state",
-    "cprng_set_state", "cprng_n_streams", "cprng_variant", "cprng_default_combs", "cprng_default_bbs_combs",
+    "cprng_set_state", "cprng_n_streams", "cprng_variant", "cprng_default_combs", "cprng_default_bbs_combs", "cprng_jump_selftest",
     "cprng_set_tuning", "cprng_get_tuning", "cprng_autotune", "cprng_autotune_ragged",
     "cprng_enable_timing", "cprng_last_kernel_ms", "cprng_probe_fill", "cprng_probe_copy", "cprng_probe_valu",
     "cprng_strerror", "cprng_last_error", "cprng_now_ns", "cprng_server_create", "cprng_server_submit",
@@ -96,6 +96,7 @@ def lib():
         "cprng_variant": (u32, [vp]),
         "cprng_default_combs": (i32, [u32, vp, vp]),
         "cprng_default_bbs_combs": (i32, [u32, vp]),
+        "cprng_jump_selftest": (i32, [u32, u32, vp, vp, u64]),
         "cprng_set_tuning": (i32, [vp, C.POINTER(Tuning)]),
         "cprng_get_tuning": (i32, [vp, C.POINTER(Tuning)]),
         "cprng_autotune": (i32, [vp, vp, u64, vp]),
@@ -229,6 +230,18 @@ def cprng_n_streams(h: int) -> int:
 
 def cprng_variant(h: int) -> int:
     return int(lib().cprng_variant(h))
+
+
+def cprng_jump_selftest(variant: int, Cg: int = 0, comb1=None, comb2=None, J: int = 1000) -> None:
+    """Host-only check of the jump-ahead (raises CprngError on failure)."""
+    keep = []
+    p1 = p2 = None
+    if comb1 is not None:
+        a1 = (C.c_uint32 * len(comb1))(*[int(v) for v in comb1])
+        a2 = (C.c_uint32 * len(comb2))(*[int(v) for v in comb2])
+        keep += [a1, a2]
+        p1, p2 = C.cast(a1, C.c_void_p), C.cast(a2, C.c_void_p)
+    _check(lib().cprng_jump_selftest(variant, Cg, p1, p2, J), "cprng_jump_selftest")
 
 
 def cprng_default_bbs_combs(Cg: int):

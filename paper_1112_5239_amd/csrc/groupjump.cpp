@@ -635,6 +635,110 @@ int ragged_v1(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t
     return timing_end(h, st);
 }
 
+}  // namespace cprng_impl
+
+using namespace cprng_impl;
+
+// Host-only self-test of the jump-ahead machinery (no device work).
+extern "C" int cprng_jump_selftest(uint32_t variant, uint32_t C, const uint32_t *comb1, const uint32_t *comb2,
+                                   uint64_t J)
+{
+    const uint32_t var = variant & 0xffu, flags = variant & ~0xffu;
+    std::mt19937_64 rng(0xabcdef12ull + J);
+    if (var == CPRNG_V2_SHMEM || var == CPRNG_V4_XOR64) {
+        if (flags) return set_error(CPRNG_E_INVAL, "no flags for the group self-test");
+        if (C < 3 || C > 64 || (64 % C)) return set_error(CPRNG_E_INVAL, "C must divide 64");
+        uint32_t c1[64], c2[64];
+        if (comb1 && comb2) {
+            for (uint32_t j = 0; j < C; ++j) {
+                if (comb1[j] >= C || comb2[j] >= C) return set_error(CPRNG_E_INVAL, "combination entry out of range");
+                c1[j] = comb1[j];
+                c2[j] = comb2[j];
+            }
+        } else if (!default_combs(C, c1, c2)) {
+            return set_error(CPRNG_E_INVAL, "no default combination arrays");
+        }
+        cprng h;
+        h.variant = var;
+        h.group = C;
+        for (uint32_t j = 0; j < 64; ++j) {
+            h.comb1[j] = (uint8_t)c1[j % C];
+            h.comb2[j] = (uint8_t)c2[j % C];
+        }
+        int rc = group_minpoly(&h);
+        if (rc) return rc;
+        GroupSim g{var, C, h.comb1, h.comb2, {}};
+        g.w.assign((size_t)C * g.words(), 0);
+        for (auto &x : g.w) x = (uint32_t)rng();
+        const Poly r = pxpow(J, h.gj_q);
+        GroupSim walk = g, direct = g;
+        std::vector<uint32_t> acc(g.w.size(), 0);
+        for (int k = 0; k < h.gj_deg; ++k) {
+            if (pbit(r, k))
+                for (size_t i = 0; i < acc.size(); ++i) acc[i] ^= walk.w[i];
+            walk.step();
+        }
+        for (uint64_t k = 0; k < J; ++k) direct.step();
+        return acc == direct.w ? CPRNG_OK : set_error(CPRNG_E_HIP, "group jump differs from stepping");
+    }
+    if (var == CPRNG_V1_NAIVE3) {
+        if (flags & ~(uint32_t)(CPRNG_F_V1_W32 | CPRNG_F_V1_XOR64)) return set_error(CPRNG_E_INVAL, "unknown flag bits");
+        const bool w32 = (flags & CPRNG_F_V1_W32) != 0, x64 = (flags & CPRNG_F_V1_XOR64) != 0;
+        if (w32 && x64) return set_error(CPRNG_E_INVAL, "xor64 needs 64-bit words");
+        const uint32_t sb = x64 ? 7u : 17u, sc = x64 ? 17u : 5u;
+        const V1Polys &P = v1_polys(w32 ? 32 : 64, sb, sc);
+        if (!P.ok) return set_error(CPRNG_E_HIP, "V1 jump-ahead: no annihilating polynomial found");
+        const uint64_t m = w32 ? 0xFFFFFFFFull : ~0ull;
+        auto step = [&](int k, std::vector<uint64_t> &s) {
+            if (k == 0) {
+                uint64_t a = s[0];
+                a ^= (a << 13) & m;
+                a ^= a >> sb;
+                a ^= (a << sc) & m;
+                s[0] = a;
+            } else if (k == 1) {
+                const uint64_t t = s[0] ^ ((s[0] << 11) & m);
+                s[0] = s[1]; s[1] = s[2]; s[2] = s[3];
+                s[3] = (s[3] ^ (s[3] >> 19)) ^ (t ^ (t >> 8));
+            } else {
+                const uint64_t u = s[0] ^ (s[0] >> 2);
+                s[0] = s[1]; s[1] = s[2]; s[2] = s[3]; s[3] = s[4];
+                s[4] = (s[4] ^ ((s[4] << 4) & m)) ^ (u ^ ((u << 1) & m));
+            }
+        };
+        const size_t nw[3] = {1, 4, 5};
+        for (int k = 0; k < 3; ++k) {
+            std::vector<uint64_t> s0(nw[k]);
+            for (auto &x : s0) x = rng() & m;
+            // jump: X^J mod q_k
+            const Poly r = pxpow(J, P.q[k]);
+            std::vector<uint64_t> walk = s0, direct = s0, acc(nw[k], 0), sum(nw[k], 0), sumd(nw[k], 0);
+            for (int b = 0; b < P.deg[k]; ++b) {
+                if (pbit(r, b))
+                    for (size_t i = 0; i < nw[k]; ++i) acc[i] ^= walk[i];
+                step(k, walk);
+            }
+            for (uint64_t i = 0; i < J; ++i) {
+                step(k, direct);
+                for (size_t w = 0; w < nw[k]; ++w) sumd[w] ^= direct[w];
+            }
+            if (acc != direct) return set_error(CPRNG_E_HIP, "V1 generator jump differs from stepping");
+            // geometric sum: sum_{i=1..J} A^i s0
+            const Poly g = pgeomsum(J, P.q[k]);
+            walk = s0;
+            for (int b = 0; b < P.deg[k]; ++b) {
+                if (pbit(g, b))
+                    for (size_t i = 0; i < nw[k]; ++i) sum[i] ^= walk[i];
+                step(k, walk);
+            }
+            if (sum != sumd) return set_error(CPRNG_E_HIP, "V1 aggregate sum differs from stepping");
+        }
+        return CPRNG_OK;
+    }
+    return set_error(CPRNG_E_INVAL, "the jump self-test covers V1, V2 and V4");
+}
+
+namespace cprng_impl {
 void destroy_group_buffers(cprng_t *h)
 {
     if (h->d_v1_items) (void)hipFree(h->d_v1_items);

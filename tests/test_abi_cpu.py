@@ -113,3 +113,25 @@ def test_header_is_plain_c(tmp_path):
     r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
                         str(src), "-o", str(tmp_path / "t")], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+@pytest.mark.parametrize("J", [0, 1, 777, 123457])
+def test_group_jump_ahead_selftest(L, J):
+    # The ragged paths' jump polynomials, checked on the host: X^J mod q of
+    # the group map reproduces J steps (V2 and V4, default and custom arrays).
+    L.cprng_jump_selftest(L.V2_SHMEM, 32, J=J)
+    L.cprng_jump_selftest(L.V4_XOR64, 16, J=J)
+    L.cprng_jump_selftest(L.V2_SHMEM, 8, comb1=[3, 4, 0, 1, 7, 6, 2, 5], comb2=[1, 3, 4, 2, 0, 7, 5, 6], J=J)
+
+
+@pytest.mark.parametrize("J", [0, 1, 4096, 99991])
+def test_v1_jump_ahead_and_aggregate_selftest(L, J):
+    for flags in (0, L.F_V1_W32, L.F_V1_XOR64):
+        L.cprng_jump_selftest(L.V1_NAIVE3 | flags, J=J)
+
+
+def test_jump_selftest_rejects_bad_arguments(L):
+    for args in ((L.V3_BBS, 32), (L.V2_SHMEM, 7), (L.V1_NAIVE3 | L.F_V1_W32 | L.F_V1_XOR64, 0)):
+        with pytest.raises(L.CprngError) as e:
+            L.cprng_jump_selftest(*args, J=10)
+        assert e.value.status == L.E_INVAL
