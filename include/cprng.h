@@ -267,12 +267,17 @@ int cprng_default_bbs_combs(uint32_t C, uint32_t *out);
  * caps residency, 0 = none). */
 typedef struct cprng_tuning {
     uint32_t block;            /* threads per block: 64, 128, 192 or 256; the interleaved
-                                  layout's tiles take 256, 512 or 1024 (streams per tile) */
+                                  layout's tiles take 256, 512 or 1024 (streams per tile);
+                                  batched runs of V1, V2 and V4 (chunk kernels): 64 or
+                                  256 (the default) */
     uint32_t unroll;           /* outputs per stream per round: 8, 16, 32 (direct);
                                   16..256, powers of two (LDS-transposed; chunk
                                   kernels 32..256); 16..128 (pipelined); the
                                   V3 (BBS) kernels are built for 8..32 only and
-                                  larger values are lowered to 32 */
+                                  larger values are lowered to 32; batched runs of
+                                  V1, V2 and V4: words per store round, 32, 64 (the
+                                  default) or 128 (V1 rounds follow the output's
+                                  aligned lines of that many words) */
     uint32_t store;            /* store mode, see above */
     uint32_t chunk;            /* ragged/requests: outputs per chunk (multiple of 64) */
     uint32_t waves_per_cu;     /* ragged/requests (store 1/2/4) and pipelined generate:

@@ -429,6 +429,22 @@ int ensure_buf(T **p, size_t *cap, size_t n)
     return CPRNG_OK;
 }
 
+// Store round of the chunk kernels: the tuning's unroll when it is 32, 64 or
+// 128 words, else the default.
+uint32_t chunk_round(const cprng_t *h)
+{
+    const uint32_t u = h->tuning.unroll;
+    return (u == 32 || u == 64 || u == 128) ? u : 64u;
+}
+
+// Waves per workgroup of the chunk kernels: 4 for a tuning block of 256, 1
+// for 64, else the default.
+uint32_t chunk_wg_waves(const cprng_t *h)
+{
+    const uint32_t b = h->tuning.block;
+    return b == 256 ? 4u : b == 64 ? 1u : 4u;
+}
+
 }  // namespace
 
 int ragged_groups(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets,
@@ -448,12 +464,13 @@ int ragged_groups(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint
         max_len = std::max(max_len, lengths[(size_t)g * C]);
     }
     if (group_steps == 0) return CPRNG_OK;
-    // Chunk: a power of two giving about 8 items per CU (items per wave =
-    // 64 / C; fewer, longer runs in flight store better), at least 16 x the
-    // jump's length, at most 2^20.
+    // Chunk: a power of two giving about 16 items per CU (items per wave =
+    // 64 / C: enough waves to hide the exchange reads' latency, while fewer,
+    // longer runs in flight store better), at least 16 x the jump's length,
+    // at most 2^20.
     uint64_t chunk = h->tuning.chunk ? h->tuning.chunk : 0;
     if (!chunk) {
-        const uint64_t target = group_steps / ((uint64_t)h->n_cu * 8u) + 1;
+        const uint64_t target = group_steps / ((uint64_t)h->n_cu * 16u) + 1;
         chunk = 1;
         while (chunk < target) chunk <<= 1;
         chunk = std::max<uint64_t>(chunk, 16ull * (uint64_t)h->gj_deg);
@@ -502,6 +519,8 @@ int ragged_groups(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint
     a.rows = h->d_gj_rows;
     a.row_words = (uint32_t)((h->gj_deg + 31) / 32);
     a.deg = (uint32_t)h->gj_deg;
+    a.round = chunk_round(h);
+    a.wg_waves = chunk_wg_waves(h);
     a.out = out;
     a.offsets = h->d_gj_offsets;
     int trc = timing_begin(h, st);
@@ -625,7 +644,8 @@ int ragged_v1(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t
     a.offsets = h->d_gj_offsets;
     a.chunk = chunk;
     a.sum_row = n_rows;
-    a.pad = 0;
+    a.round = chunk_round(h);
+    a.wg_waves = chunk_wg_waves(h);
     a.order = h->d_v1_order;
     int trc = timing_begin(h, st);
     if (trc) return trc;

@@ -85,6 +85,8 @@ struct GroupJumpArgs {
     uint32_t n_items;
     uint32_t row_words;         // 32-bit words per jump row
     uint32_t deg;               // degree of the group's minimal polynomial
+    uint32_t round;             // words per lane per store round: 32, 64 or 128
+    uint32_t wg_waves;          // waves per workgroup: 1 or 4
     const uint32_t *rows;       // row r: coefficients of X^(r * chunk) mod q
     uint32_t *out;
     const uint64_t *offsets;    // per stream
@@ -116,7 +118,8 @@ struct V1ChunkArgs {
     const uint64_t *offsets;    // per stream
     uint64_t chunk;             // length of a full chunk
     uint32_t sum_row;           // row of sum_{i=1..chunk} X^i (xorshift and xor128 parts)
-    uint32_t pad;
+    uint32_t round;             // generating pass: words per lane per store round (32, 64, 128)
+    uint32_t wg_waves;          // generating pass: waves per workgroup (1 or 4)
     const uint32_t *order;      // aggregate pass: full chunks first, then the shorter last ones
 };
 

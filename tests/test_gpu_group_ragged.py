@@ -34,11 +34,11 @@ def _group_lengths(n_groups, seed, cap):
     return rng.permutation(np.concatenate([base, extra]))[:n_groups]
 
 
-def _run(orc, G, name, ov, ns, Cg, gl, sigma, chunk, comb=None, offsets_mode=None, calls=2):
+def _run(orc, G, name, ov, ns, Cg, gl, sigma, chunk, comb=None, offsets_mode=None, calls=2, rnd=0, blk=0):
     g = G.Generator(ns, name, seed=sigma, group=Cg, comb=comb)
     try:
-        if chunk:
-            g.set_tuning(chunk=chunk)
+        if chunk or rnd or blk:
+            g.set_tuning(chunk=chunk, unroll=rnd, block=blk)
         combs = comb if comb is not None else orc.comb_tables(Cg)
         st = orc.seed(ov, sigma, 0, ns)
         lengths = np.repeat(gl, Cg).astype(np.uint64)
@@ -86,6 +86,15 @@ def test_group_ragged_custom_arrays_and_offsets(orc, G):
     c2 = np.array([1, 3, 4, 2, 0, 7, 5, 6], dtype=np.uint32)
     gl = _group_lengths(12, 83, 1500)
     _run(orc, G, "v2", 2, 96, 8, gl, sigma=83, chunk=192, comb=(c1, c2), offsets_mode="reversed")
+
+
+@pytest.mark.parametrize("name,ov", [("v2", 2), ("v4", 4)])
+@pytest.mark.parametrize("rnd", [32, 64, 128])
+@pytest.mark.parametrize("blk", [64, 256])
+def test_group_ragged_store_rounds(orc, G, name, ov, rnd, blk):
+    # each store-round length and workgroup size, runs misaligned by the 5-word gaps
+    gl = _group_lengths(10, 86, 2500)
+    _run(orc, G, name, ov, 10 * 16, 16, gl, sigma=86, chunk=320, offsets_mode="reversed", rnd=rnd, blk=blk)
 
 
 def test_group_ragged_long_run(orc, G):

@@ -33,11 +33,11 @@ def _lengths(ns, seed, cap):
     return rng.permutation(np.concatenate([base, extra]))
 
 
-def _run(orc, G, kw, ov, W, ns, lengths, sigma, chunk, offsets=None, calls=2):
+def _run(orc, G, kw, ov, W, ns, lengths, sigma, chunk, offsets=None, calls=2, rnd=0, blk=0):
     g = G.Generator(ns, "v1", seed=sigma, **kw)
     try:
-        if chunk:
-            g.set_tuning(chunk=chunk)
+        if chunk or rnd or blk:
+            g.set_tuning(chunk=chunk, unroll=rnd, block=blk)
         st = orc.seed(ov, sigma, 0, ns, W=W)
         offs = offsets if offsets is not None else np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.uint64)
         for _ in range(calls):
@@ -64,6 +64,19 @@ def test_v1_ragged_matches_the_oracle(orc, G, case, chunk):
         ov = 1 | orc.F_XOR64
     lengths = _lengths(128, 91, 5000)
     _run(orc, G, kw, ov, W, 128, lengths, sigma=91, chunk=chunk)
+
+
+@pytest.mark.parametrize("rnd", [32, 64, 128])
+@pytest.mark.parametrize("blk", [64, 256])
+def test_v1_ragged_store_rounds(orc, G, rnd, blk):
+    # each store-round length and workgroup size, runs misaligned by 3-word gaps
+    lengths = _lengths(96, 93, 4000)
+    offs = np.zeros(96, dtype=np.uint64)
+    pos = 0
+    for s in reversed(range(96)):
+        offs[s] = pos
+        pos += int(lengths[s]) + 3
+    _run(orc, G, {}, 1, 64, 96, lengths, sigma=93, chunk=448, offsets=offs, rnd=rnd, blk=blk)
 
 
 def test_v1_ragged_offsets_and_a_long_run(orc, G):
