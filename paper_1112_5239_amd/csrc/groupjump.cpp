@@ -464,17 +464,38 @@ int ragged_groups(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint
         max_len = std::max(max_len, lengths[(size_t)g * C]);
     }
     if (group_steps == 0) return CPRNG_OK;
-    // Chunk: a power of two giving about 16 items per CU (items per wave =
-    // 64 / C: enough waves to hide the exchange reads' latency, while fewer,
-    // longer runs in flight store better), at least 16 x the jump's length,
-    // at most 2^20.
+    // Chunk: the shortest (a multiple of 64, at least 16 x the jump's length,
+    // at most 2^20) whose items all fit one pass of the chip's resident waves.
+    // The exchange reads' latency wants many waves, fewer and longer runs in
+    // flight store better, and a second pass that is only partly full costs
+    // nearly a whole chunk's time.  Resident waves per CU follow from the
+    // tile's LDS (the kernel's other limits are looser); the pass is filled
+    // to 31/32, so a workgroup the dispatcher places late does not start a
+    // second one.
     uint64_t chunk = h->tuning.chunk ? h->tuning.chunk : 0;
     if (!chunk) {
-        const uint64_t target = group_steps / ((uint64_t)h->n_cu * 16u) + 1;
-        chunk = 1;
-        while (chunk < target) chunk <<= 1;
-        chunk = std::max<uint64_t>(chunk, 16ull * (uint64_t)h->gj_deg);
-        chunk = std::min<uint64_t>(chunk, 1ull << 20);
+        const uint64_t K = chunk_round(h), W = chunk_wg_waves(h);
+        const uint64_t wg_lds = W * 64u * (K + 1u) * 4u;
+        const uint64_t waves_cu = std::min<uint64_t>(32u, (kMaxLdsBytes / wg_lds) * W);
+        const uint64_t cap = (uint64_t)h->n_cu * waves_cu * (64u / C) * 31u / 32u;   // 3% slack
+        auto n_items = [&](uint64_t c) {
+            uint64_t n = 0;
+            for (uint32_t g = 0; g < n_groups; ++g) n += (lengths[(size_t)g * C] + c - 1) / c;
+            return n;
+        };
+        uint64_t lo = ((16ull * (uint64_t)h->gj_deg + 63u) / 64u) * 64u, hi = 1ull << 20;
+        if (n_items(lo) <= cap) {
+            chunk = lo;
+        } else if (n_items(hi) > cap) {
+            chunk = hi;
+        } else {
+            // n_items(lo) > cap >= n_items(hi); n_items does not grow with c
+            while (hi - lo > 64u) {
+                const uint64_t mid = lo + ((hi - lo) / 128u) * 64u;
+                if (n_items(mid) <= cap) hi = mid; else lo = mid;
+            }
+            chunk = hi;
+        }
     }
     std::vector<GroupItem> items;
     for (uint32_t g = 0; g < n_groups; ++g) {
