@@ -445,6 +445,31 @@ uint32_t chunk_wg_waves(const cprng_t *h)
     return b == 256 ? 4u : b == 64 ? 1u : 4u;
 }
 
+// Waves of a chunk kernel that stay resident per CU, from its tile's LDS
+// (the kernels' other limits are looser).
+uint64_t chunk_resident_waves(const cprng_t *h)
+{
+    const uint64_t K = chunk_round(h), W = chunk_wg_waves(h);
+    const uint64_t wg_lds = W * 64u * (K + 1u) * 4u;
+    return std::min<uint64_t>(32u, (kMaxLdsBytes / wg_lds) * W);
+}
+
+// Shortest chunk, a multiple of 64 in [lo, 2^20], with n_items(chunk) <= cap
+// (n_items does not grow with the chunk); 2^20 if none.
+template <typename F>
+uint64_t fit_chunk(uint64_t lo, uint64_t cap, F &&n_items)
+{
+    lo = std::max<uint64_t>(64u, (lo + 63u) / 64u * 64u);
+    uint64_t hi = 1ull << 20;
+    if (lo >= hi || n_items(hi) > cap) return hi;
+    if (n_items(lo) <= cap) return lo;
+    while (hi - lo > 64u) {                 // n_items(lo) > cap >= n_items(hi)
+        const uint64_t mid = lo + ((hi - lo) / 128u) * 64u;
+        if (n_items(mid) <= cap) hi = mid; else lo = mid;
+    }
+    return hi;
+}
+
 }  // namespace
 
 int ragged_groups(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets,
@@ -474,28 +499,12 @@ int ragged_groups(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint
     // second one.
     uint64_t chunk = h->tuning.chunk ? h->tuning.chunk : 0;
     if (!chunk) {
-        const uint64_t K = chunk_round(h), W = chunk_wg_waves(h);
-        const uint64_t wg_lds = W * 64u * (K + 1u) * 4u;
-        const uint64_t waves_cu = std::min<uint64_t>(32u, (kMaxLdsBytes / wg_lds) * W);
-        const uint64_t cap = (uint64_t)h->n_cu * waves_cu * (64u / C) * 31u / 32u;   // 3% slack
-        auto n_items = [&](uint64_t c) {
+        const uint64_t cap = (uint64_t)h->n_cu * chunk_resident_waves(h) * (64u / C) * 31u / 32u;   // 3% slack
+        chunk = fit_chunk(16ull * (uint64_t)h->gj_deg, cap, [&](uint64_t c) {
             uint64_t n = 0;
             for (uint32_t g = 0; g < n_groups; ++g) n += (lengths[(size_t)g * C] + c - 1) / c;
             return n;
-        };
-        uint64_t lo = ((16ull * (uint64_t)h->gj_deg + 63u) / 64u) * 64u, hi = 1ull << 20;
-        if (n_items(lo) <= cap) {
-            chunk = lo;
-        } else if (n_items(hi) > cap) {
-            chunk = hi;
-        } else {
-            // n_items(lo) > cap >= n_items(hi); n_items does not grow with c
-            while (hi - lo > 64u) {
-                const uint64_t mid = lo + ((hi - lo) / 128u) * 64u;
-                if (n_items(mid) <= cap) hi = mid; else lo = mid;
-            }
-            chunk = hi;
-        }
+        });
     }
     std::vector<GroupItem> items;
     for (uint32_t g = 0; g < n_groups; ++g) {
@@ -565,16 +574,20 @@ int ragged_v1(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t
     }
     if (total == 0) return CPRNG_OK;
     const uint64_t jump_steps = (uint64_t)(P.deg[0] + P.deg[1] + P.deg[2]);
-    // Chunk: a power of two giving about 2,048 chunks (32 waves) per CU --
-    // one lane per chunk, and the generators' serial chains need many waves
-    // -- at least 16 x the jump's steps, at most 2^20.
+    // Chunk: one lane per chunk.  The shortest (a multiple of 64, at least
+    // 16 x the jump's steps, at most 2^20) whose chunks fill at most 31/32 of
+    // two passes of the generating kernel's resident waves: its time follows
+    // whole passes (a last pass that is mostly empty costs a whole chunk's
+    // time), and the aggregate pass's serial xorwow chains want the twice as
+    // many waves that two passes' worth of chunks give it.
     uint64_t chunk = h->tuning.chunk ? h->tuning.chunk : 0;
     if (!chunk) {
-        const uint64_t target = total / ((uint64_t)h->n_cu * 2048u) + 1;
-        chunk = 1;
-        while (chunk < target) chunk <<= 1;
-        chunk = std::max<uint64_t>(chunk, 16ull * jump_steps);
-        chunk = std::min<uint64_t>(chunk, 1ull << 20);
+        const uint64_t cap = 2u * (uint64_t)h->n_cu * chunk_resident_waves(h) * 64u * 31u / 32u;
+        chunk = fit_chunk(16ull * jump_steps, cap, [&](uint64_t c) {
+            uint64_t n = 0;
+            for (uint32_t s = 0; s < h->ns; ++s) n += (lengths[s] + c - 1) / c;
+            return n;
+        });
     }
     std::vector<V1Item> items;
     for (uint32_t s = 0; s < h->ns; ++s) {
