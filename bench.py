@@ -10,6 +10,7 @@ resident on the device.  Prints ONE JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extra] [--no-cpu-baseline]
     python bench.py --workload serving [--duration 60]
+    python bench.py --workload ragged|ragged_v1|ragged_groups|consume   (one leg alone, for profiling)
 
 Secondary measurements (same JSON line, "extra"): the same workload in the
 stream-major layout out[s * 1024 + i], the plain variants V0 and V1 in both
@@ -180,7 +181,7 @@ def alu_roofline(gn, key):
 
 def run_plain(torch, G, variant, args, interleaved=False):
     ns, n = 1 << 20, 1024
-    words = {"v0": 5, "v1": 23, "v3": 10, "v4": 4}[variant]
+    words = {"v0": 5, "v1": 23, "v2": 6, "v3": 10, "v4": 4}[variant]
     g = G.Generator(ns, variant, seed=1, interleaved=interleaved)
     shape = (n, ns) if interleaved else (ns, n)
     out = torch.empty(shape, dtype=torch.int32, device="cuda")
@@ -330,7 +331,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=50,
                     help="untimed steps; the first ~50 launches after the GPU has been idle run slower")
-    ap.add_argument("--workload", default="paper", choices=["paper", "ragged", "serving", "consume"])
+    ap.add_argument("--workload", default="paper",
+                    choices=["paper", "ragged", "serving", "consume", "ragged_v1", "ragged_groups"])
     ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -385,6 +387,21 @@ def main():
                           "ms_per_step": res["ms"], "higher_is_better": True, "dtype": "u32",
                           "data": "synthetic", "config": {"workload": res["workload"]},
                           "plain_v0": ref, "ragged": res}), flush=True)
+        return
+
+    if args.workload in ("ragged_v1", "ragged_groups"):
+        # Batched uneven runs of V1 (4,096 streams) or of V2 in groups, alone,
+        # for profiling, against the plain variant (stream-major) timed first.
+        variant = "v1" if args.workload == "ragged_v1" else "v2"
+        ref = run_plain(torch, G, variant, args, interleaved=False)
+        run = run_ragged_v1 if variant == "v1" else run_ragged_groups
+        res = run(torch, G, args, ref["gnumbers_per_s"])
+        log(f"[bench] {args.workload}: {res}")
+        print(json.dumps({"metric": f"batched uneven runs ({variant}): Gnumbers/s and ratio to plain {variant}",
+                          "value": res["gnumbers_per_s"], "unit": "Gnumbers/s", "n_gpus": 1,
+                          "ms_per_step": res["ms"], "higher_is_better": True, "dtype": "u32",
+                          "data": "synthetic", "config": {"workload": res["workload"]},
+                          "plain": ref, args.workload: res}), flush=True)
         return
 
     ms, wall, numbers, alg_bytes, achieved = run_paper(torch, G, L, args, interleaved=True)
