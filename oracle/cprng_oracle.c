@@ -389,10 +389,16 @@ static void gen_v0_stream(uint32_t *st, uint64_t n, uint32_t *out, uint32_t *str
     st[4] = x;
 }
 
-/* V1: Listing 1 per stream (Algorithm 3).  Each generator steps once per
- * output; S is the xor of the low and high 32-bit halves of the three
- * generator outputs, in the order the listing applies them.  alt: the first
- * generator is xor64 (13,7,17) instead of the (13,17,5) triple. */
+/* The 32-bit fold of a generator output: its low half xor its high half (the
+ * high half is 0 for 32-bit words). */
+static uint32_t fold32(uint64_t v) { return (uint32_t)v ^ (uint32_t)(v >> 32); }
+
+/* V1: Listing 1 per stream (Algorithm 3).  Each of the three generators
+ * steps once per output, and the strategy word takes every 32-bit half of
+ * the three new outputs once under xor: S is the fold of t1 xor t2 xor t3
+ * (xor is associative and commutative, so the order in which the listing
+ * takes the six halves does not matter).  alt: the first generator is xor64
+ * (13,7,17) instead of the (13,17,5) triple. */
 static void gen_v1_stream(uint32_t *st, int W, int alt, uint64_t n, uint32_t *out, uint32_t *strat)
 {
     uint64_t g1 = get64(st, 0), g2[4], g3[6];
@@ -400,16 +406,10 @@ static void gen_v1_stream(uint32_t *st, int W, int alt, uint64_t n, uint32_t *ou
     for (int j = 0; j < 6; ++j) g3[j] = get64(st, 5 + j);
     uint32_t x = st[22];
     for (uint64_t i = 0; i < n; ++i) {
-        uint64_t t1 = alt ? orc_xor64_step(&g1) : orc_xs_step(&g1, 13, 17, 5, W);
-        uint64_t t2 = orc_x128_step(g2, W);
-        uint64_t t3 = orc_xwow_step(g3, W);
-        uint32_t S = 0;
-        S ^= (uint32_t)t1;
-        S ^= (uint32_t)(t2 >> 32);
-        S ^= (uint32_t)(t3 >> 32);
-        S ^= (uint32_t)t2;
-        S ^= (uint32_t)(t1 >> 32);
-        S ^= (uint32_t)t3;
+        const uint64_t t1 = alt ? orc_xor64_step(&g1) : orc_xs_step(&g1, 13, 17, 5, W);
+        const uint64_t t2 = orc_x128_step(g2, W);
+        const uint64_t t3 = orc_xwow_step(g3, W);
+        const uint32_t S = fold32(t1 ^ t2 ^ t3);
         x = orc_ci_step(x, S);
         if (out) out[i] = x;
         if (strat) strat[i] = S;
@@ -499,25 +499,24 @@ static int gen_v4_group(uint32_t *st, uint32_t C, const uint32_t *comb1, const u
 }
 
 /* Strategy bits of one step of Algorithm 5 for one thread, before the
- * neighbour mixing: the low four bits of BBS1 .. BBS8 (each stepped once),
- * shifted in four at a time so BBS1's end up highest; then twice a left
- * shift by 0..3 bits (taken from BBS3, then BBS7) with that many low bits of
- * BBS1, then BBS2, put in the vacated positions (array_shift = {0,1,3,7}). */
+ * neighbour mixing, as bit fields of the 32-bit word.  Each of the eight BBS
+ * gives one output whose low nibble fills a 4-bit field, BBS1's the top one
+ * (bits 28..31) down to BBS8's (bits 0..3).  Then BBS3 and BBS7 each give a
+ * second output whose low two bits are shift counts s1 and s2 (0..3), and
+ * BBS1 and BBS2 a second output whose low s1 and s2 bits fill the vacated
+ * places: the word is the nibble word moved up by s1 + s2 bits (its top bits
+ * dropped), BBS1's s1 bits at bits s2 .. s2+s1-1 and BBS2's s2 bits at bits
+ * 0 .. s2-1.  Slots are stepped in the order the paper's kernel steps them
+ * (each slot's own outputs are what matter; slots are independent). */
 uint32_t orc_bbs_word(uint32_t b[8])
 {
-    static const uint32_t array_shift[4] = {0u, 1u, 3u, 7u};
-    uint32_t t = 0;
-    for (int k = 0; k < 8; ++k) {
-        t <<= 4;
-        t |= orc_bbs_step(&b[k], k) & 15u;
-    }
-    uint32_t shift = orc_bbs_step(&b[2], 2) & 3u;
-    t <<= shift;
-    t |= orc_bbs_step(&b[0], 0) & array_shift[shift];
-    shift = orc_bbs_step(&b[6], 6) & 3u;
-    t <<= shift;
-    t |= orc_bbs_step(&b[1], 1) & array_shift[shift];
-    return t;
+    uint32_t nibbles = 0;
+    for (int k = 0; k < 8; ++k) nibbles |= (orc_bbs_step(&b[k], k) & 15u) << (28 - 4 * k);
+    const uint32_t s1 = orc_bbs_step(&b[2], 2) & 3u;
+    const uint32_t f1 = orc_bbs_step(&b[0], 0) & ((1u << s1) - 1u);
+    const uint32_t s2 = orc_bbs_step(&b[6], 6) & 3u;
+    const uint32_t f2 = orc_bbs_step(&b[1], 1) & ((1u << s2) - 1u);
+    return (nibbles << (s1 + s2)) | (f1 << s2) | f2;
 }
 
 /* V3: Algorithm 5 on one group of C consecutive streams (10-word states).

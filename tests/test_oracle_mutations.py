@@ -28,8 +28,9 @@ MUTATIONS = [
     ("xorwow Weyl 362437 -> 362439", "(s[5] + 362437ull)", "(s[5] + 362439ull)"),
     ("xorwow v<<4 -> v<<3", "((s[4] << 4) & m)", "((s[4] << 3) & m)"),
     ("step xor -> or", "return x ^ S;", "return x | S;"),
-    ("listing drops hi(t3)", "        S ^= (uint32_t)(t3 >> 32);\n", ""),
-    ("listing lo(t1) twice", "        S ^= (uint32_t)(t1 >> 32);\n", "        S ^= (uint32_t)t1;\n"),
+    ("listing drops t3", "fold32(t1 ^ t2 ^ t3)", "fold32(t1 ^ t2)"),
+    ("listing drops hi(t3)", "fold32(t1 ^ t2 ^ t3)", "fold32(t1 ^ t2) ^ (uint32_t)t3"),
+    ("listing high halves dropped", "{ return (uint32_t)v ^ (uint32_t)(v >> 32); }", "{ return (uint32_t)v; }"),
     ("alg4 reads comb2 twice", "u[j] ^ tprev[comb1[j]] ^ tprev[comb2[j]]", "u[j] ^ tprev[comb2[j]] ^ tprev[comb2[j]]"),
     ("alg4 index direction (inverse)",
      "for (uint32_t j = 0; j < C; ++j) tnext[j] = u[j] ^ tprev[comb1[j]] ^ tprev[comb2[j]];",
@@ -45,14 +46,16 @@ MUTATIONS = [
     ("splitmix gamma", "#define ORC_SM64_GAMMA 0x9E3779B97F4A7C15ull", "#define ORC_SM64_GAMMA 0x9E3779B97F4A7C17ull"),
     ("splitmix shift 30 -> 31", "z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;", "z = (z ^ (z >> 31)) * 0xBF58476D1CE4E5B9ull;"),
     ("continuation loses state", "    st[4] = x;\n}", "    st[4] = x ^ 1u;\n}"),
-    ("alg5 nibbles BBS8 first", "for (int k = 0; k < 8; ++k) {\n        t <<= 4;", "for (int k = 7; k >= 0; --k) {\n        t <<= 4;"),
+    ("alg5 nibbles BBS8 first", "& 15u) << (28 - 4 * k);", "& 15u) << (4 * k);"),
     ("alg5 (8+bbs2)&7 precedence", "combs[(size_t)(8u + (s[1] & 7u)) * C + j]", "combs[(size_t)((8u + s[1]) & 7u) * C + j]"),
     ("alg5 o1 array from slot 2", "o1[j] = combs[(size_t)(s[0] & 7u) * C + j];", "o1[j] = combs[(size_t)(s[1] & 7u) * C + j];"),
     ("alg5 rotation backwards",
      "uint32_t last = s[7];\n            for (int k = 7; k > 0; --k) s[k] = s[k - 1];\n            s[0] = last;",
      "uint32_t first = s[0];\n            for (int k = 0; k < 7; ++k) s[k] = s[k + 1];\n            s[7] = first;"),
-    ("alg5 shift mask 7 -> 3", "array_shift[4] = {0u, 1u, 3u, 7u}", "array_shift[4] = {0u, 1u, 3u, 3u}"),
-    ("alg5 BBS2 not stepped again", "t |= orc_bbs_step(&b[1], 1) & array_shift[shift];", "t |= b[1] & array_shift[shift];"),
+    ("alg5 fill mask of shift 3 one bit short", "orc_bbs_step(&b[0], 0) & ((1u << s1) - 1u)",
+     "orc_bbs_step(&b[0], 0) & ((1u << (s1 < 3 ? s1 : 2)) - 1u)"),
+    ("alg5 BBS2 not stepped again", "f2 = orc_bbs_step(&b[1], 1) & ((1u << s2) - 1u)", "f2 = b[1] & ((1u << s2) - 1u)"),
+    ("alg5 fields swapped", "| (f1 << s2) | f2;", "| (f2 << s1) | f1;"),
     ("alg5 modulus 251*239 -> 251*241", "251u * 239u, 251u * 227u", "251u * 241u, 251u * 227u"),
     ("alg5 seed not squared", "st[k] = (uint32_t)((r * r) % M);", "st[k] = (uint32_t)r;"),
     ("xor64 triple 7 -> 8", "orc_xs_step(y, 13, 7, 17, 64)", "orc_xs_step(y, 13, 8, 17, 64)"),
