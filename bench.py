@@ -221,10 +221,8 @@ def run_ragged_groups(torch, G, args, ref_gn):
     """Batched uneven runs of the exchange variant: 128 groups of 32 streams,
     group lengths log-uniform in [1e3, 1e7] (equal within a group), seed 2;
     ratio against plain V2 in the stream-major layout."""
-    import numpy as np
-    rng = np.random.default_rng(2)
-    gl = np.exp(rng.uniform(np.log(1e3), np.log(1e7), size=128)).astype(np.uint64)
-    lengths = np.repeat(gl, 32).astype(np.uint64)
+    from paper_1112_5239_amd import workloads
+    lengths = workloads.ragged_group_lengths()
     total = int(lengths.sum())
     g = G.Generator(lengths.size, "v2", seed=2)
     out = torch.empty(total, dtype=torch.int32, device="cuda")

@@ -20,6 +20,17 @@ def ragged_lengths(n_streams: int = RAGGED_STREAMS, lo: float = RAGGED_LO, hi: f
     return np.floor(lo * np.power(hi / lo, u)).astype(np.uint64)
 
 
+def ragged_group_lengths(n_groups: int = 128, group: int = 32, lo: float = RAGGED_LO, hi: float = RAGGED_HI,
+                         seed: int = RAGGED_SEED) -> np.ndarray:
+    """Per-stream lengths of batched uneven runs of the exchange variants: n_groups
+    group lengths exp(U(ln lo, ln hi)) truncated to integers (numpy PCG64 seeded with
+    `seed`), each repeated for the `group` streams of its group (a group's streams
+    advance together)."""
+    rng = np.random.default_rng(seed)
+    gl = np.exp(rng.uniform(np.log(lo), np.log(hi), size=n_groups)).astype(np.uint64)
+    return np.repeat(gl, group).astype(np.uint64)
+
+
 def serving_trace(rate_hz: float = 2000.0, duration_s: float = 60.0, n_clients: int = 10000,
                   min_bytes: int = 1024, max_bytes: int = 256 << 20, seed: int = 5):
     """Poisson arrivals with log-uniform request sizes (bytes, multiple of 4).
