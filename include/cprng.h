@@ -234,6 +234,27 @@ size_t cprng_state_bytes(const cprng_t *h);
 int cprng_get_state(cprng_t *h, uint32_t *host_words, size_t n_words);
 int cprng_set_state(cprng_t *h, const uint32_t *host_words, size_t n_words);
 
+/* Versioned checkpoint images.  The kernels write every stream's state back
+ * at the end of a call (the internal variables stored after the loop of
+ * Algorithms 3 and 4), so the device state between calls is a complete
+ * checkpoint.  An image is a 256-byte header -- magic "CPRNGCKP", format
+ * version 1, header size, the handle's variant and flags, n_streams, state
+ * words per stream, group size, the combination arrays (V2/V4), payload size,
+ * a 64-bit FNV-1a hash of the payload and one of the header -- followed by the
+ * states in cprng_get_state's order; integers little-endian.
+ * cprng_checkpoint_bytes: the image size for h (0 on a bad handle).
+ * cprng_checkpoint_save: write h's image to host_buf (host, exactly that many
+ * bytes; synchronises the device like cprng_get_state).
+ * cprng_checkpoint_load: restore an image saved from a handle of the same
+ * variant, flags, stream count, group size and arrays (the seed may differ);
+ * every header field, both hashes and the state rules of cprng_set_state are
+ * checked first, and a failing check leaves h unchanged.  Errors: E_INVAL
+ * (NULL, wrong size, bad magic, version, hash or a field that does not match
+ * h), E_HIP. */
+size_t cprng_checkpoint_bytes(const cprng_t *h);
+int cprng_checkpoint_save(cprng_t *h, void *host_buf, size_t bytes);
+int cprng_checkpoint_load(cprng_t *h, const void *host_buf, size_t bytes);
+
 /* ------------------------------------------------------------------------ */
 /* Introspection and tuning.                                                 */
 /* ------------------------------------------------------------------------ */

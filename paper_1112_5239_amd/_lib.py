@@ -59,7 +59,8 @@ class Tuning(C.Structure):
 EXPORTED = [
     "cprng_create", "cprng_create_ex", "cprng_destroy", "cprng_generate", "cprng_consume_qc",
     "cprng_generate_ragged", "cprng_generate_requests", "cprng_state_words", "cprng_state_bytes", "cprng_get_state",
-    "cprng_set_state", "cprng_n_streams", "cprng_variant", "cprng_default_combs", "cprng_default_bbs_combs", "cprng_jump_selftest",
+    "cprng_set_state", "cprng_checkpoint_bytes", "cprng_checkpoint_save", "cprng_checkpoint_load",
+    "cprng_n_streams", "cprng_variant", "cprng_default_combs", "cprng_default_bbs_combs", "cprng_jump_selftest",
     "cprng_set_tuning", "cprng_get_tuning", "cprng_autotune", "cprng_autotune_ragged",
     "cprng_enable_timing", "cprng_last_kernel_ms", "cprng_probe_fill", "cprng_probe_copy", "cprng_probe_valu",
     "cprng_strerror", "cprng_last_error", "cprng_now_ns", "cprng_server_create", "cprng_server_submit",
@@ -92,6 +93,9 @@ def lib():
         "cprng_state_bytes": (C.c_size_t, [vp]),
         "cprng_get_state": (i32, [vp, vp, C.c_size_t]),
         "cprng_set_state": (i32, [vp, vp, C.c_size_t]),
+        "cprng_checkpoint_bytes": (C.c_size_t, [vp]),
+        "cprng_checkpoint_save": (i32, [vp, vp, C.c_size_t]),
+        "cprng_checkpoint_load": (i32, [vp, vp, C.c_size_t]),
         "cprng_n_streams": (u32, [vp]),
         "cprng_variant": (u32, [vp]),
         "cprng_default_combs": (i32, [u32, vp, vp]),
@@ -222,6 +226,23 @@ def cprng_get_state(h: int, host_words) -> None:
 
 def cprng_set_state(h: int, host_words) -> None:
     _check(lib().cprng_set_state(h, _addr(host_words), host_words.size), "cprng_set_state")
+
+
+def cprng_checkpoint_bytes(h: int) -> int:
+    return int(lib().cprng_checkpoint_bytes(h))
+
+
+def cprng_checkpoint_save(h: int) -> bytes:
+    """The handle's versioned checkpoint image."""
+    n = cprng_checkpoint_bytes(h)
+    buf = (C.c_ubyte * n)()
+    _check(lib().cprng_checkpoint_save(h, buf, n), "cprng_checkpoint_save")
+    return bytes(buf)
+
+
+def cprng_checkpoint_load(h: int, image: bytes) -> None:
+    buf = (C.c_ubyte * len(image)).from_buffer_copy(image)
+    _check(lib().cprng_checkpoint_load(h, buf, len(image)), "cprng_checkpoint_load")
 
 
 def cprng_n_streams(h: int) -> int:

@@ -112,6 +112,13 @@ class Generator:
         w = np.ascontiguousarray(words, dtype=np.uint32)
         L.cprng_set_state(self.h, w)
 
+    def checkpoint(self) -> bytes:
+        """Versioned, hashed image of every stream's state (cprng_checkpoint_save)."""
+        return L.cprng_checkpoint_save(self.h)
+
+    def restore(self, image: bytes) -> None:
+        L.cprng_checkpoint_load(self.h, image)
+
     # -- tuning / timing ------------------------------------------------------
     def set_tuning(self, **kw):
         L.cprng_set_tuning(self.h, **kw)
