@@ -281,7 +281,11 @@ int cprng_default_bbs_combs(uint32_t C, uint32_t *out);
  * CPRNG_F_INTERLEAVED take 0/2/7 (LDS tiles of unroll steps x block streams,
  * each step's block stored as one contiguous run; needs n_streams % 4 == 0 and
  * a 16-byte aligned output, else the per-lane path runs), 4/8 (the same,
- * non-temporal) or 1/3 (per-lane dword stores).  The chunk kernels of
+ * non-temporal), 1/3 (per-lane dword stores) or 5/6 (V0, V2, V4: four
+ * consecutive streams per lane, whose words of each step are stored as one
+ * 16-byte store with no LDS tile; 6 non-temporal; block = 64, 128 or 256
+ * threads per tile of 4 x block streams; V1 and V3 take the tiles instead;
+ * other handles reject 5/6).  The chunk kernels of
  * cprng_generate_ragged / cprng_generate_requests take 1 (per-lane), 2/4
  * (LDS tiles, persistent waves fed by one work queue per XCD) or 7/8 (LDS
  * tiles, one workgroup per 64 chunks banded over the XCDs; waves_per_cu then

@@ -203,6 +203,9 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
         if (h->tuning.store == ST_DIRECT || h->tuning.store == ST_DIRECT_NT) c.store = ST_INTERLEAVED;
         if (h->tuning.store == ST_LDS || h->tuning.store == ST_PIPE) c.store = ST_ILV_TILE;
         if (h->tuning.store == ST_LDS_NT || h->tuning.store == ST_PIPE_NT) c.store = ST_ILV_TILE_NT;
+        if (h->tuning.store == 5) c.store = ST_ILV_QUAD;
+        if (h->tuning.store == 6) c.store = ST_ILV_QUAD_NT;
+        if (c.store == ST_ILV_QUAD || c.store == ST_ILV_QUAD_NT) c.block = 256;
         if (h->tuning.block) c.block = h->tuning.block;
         if (h->tuning.unroll) c.unroll = h->tuning.unroll;
         if (h->tuning.exchange) c.exchange = h->tuning.exchange;
@@ -271,8 +274,23 @@ int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchC
     if (h->variant == CPRNG_V3_BBS && c.unroll > 32) c.unroll = 32;
     if (h->flags & CPRNG_F_INTERLEAVED) {
         const bool tile_ok = ((uintptr_t)out % 16u) == 0 && (h->ns % 4u) == 0;
-        if (!tile_ok || (c.store != ST_ILV_TILE && c.store != ST_ILV_TILE_NT)) c.store = ST_INTERLEAVED;
-        if (c.store == ST_INTERLEAVED) {
+        const bool quad = c.store == ST_ILV_QUAD || c.store == ST_ILV_QUAD_NT;
+        // The quad-lane kernel covers the 32-bit-word variants V0, V2, V4; the
+        // others take the LDS tiles.
+        const bool quad_var = h->variant == CPRNG_V0_PLAIN || h->variant == CPRNG_V2_SHMEM ||
+                              h->variant == CPRNG_V4_XOR64;
+        if (quad && !quad_var) {
+            c.store = c.store == ST_ILV_QUAD_NT ? ST_ILV_TILE_NT : ST_ILV_TILE;
+            c.block = 256;
+        }
+        if (!tile_ok || (c.store != ST_ILV_TILE && c.store != ST_ILV_TILE_NT && c.store != ST_ILV_QUAD &&
+                         c.store != ST_ILV_QUAD_NT))
+            c.store = ST_INTERLEAVED;
+        if (c.store == ST_ILV_QUAD || c.store == ST_ILV_QUAD_NT) {
+            // 64, 128 or 256 threads, each holding four streams
+            if (c.block > 256) c.block = 256;
+            if (c.block != 64 && c.block != 128) c.block = 256;
+        } else if (c.store == ST_INTERLEAVED) {
             if (c.block > 256) c.block = 256;
             if (c.unroll > 32) c.unroll = 32;
         } else {
@@ -485,8 +503,9 @@ int cprng_set_tuning(cprng_t *h, const cprng_tuning_t *t)
     if (t->unroll && t->unroll != 8 && t->unroll != 16 && t->unroll != 32 && t->unroll != 64 &&
         t->unroll != 128 && t->unroll != 256)
         return set_error(CPRNG_E_INVAL, "unroll must be 8, 16, 32, 64, 128 or 256 (above 32: LDS store modes)");
-    if (t->store > 8 || t->store == 5 || t->store == 6)
-        return set_error(CPRNG_E_INVAL, "store mode must be 0..4, 7 or 8");
+    if (t->store > 8) return set_error(CPRNG_E_INVAL, "store mode must be 0..8");
+    if ((t->store == 5 || t->store == 6) && !(h->flags & CPRNG_F_INTERLEAVED))
+        return set_error(CPRNG_E_INVAL, "store modes 5 and 6 apply to interleaved handles");
     if (t->chunk && (t->chunk % 64 || t->chunk > (1u << 24))) return set_error(CPRNG_E_INVAL, "chunk must be a multiple of 64, <= 2^24");
     if (t->waves_per_cu > 32) return set_error(CPRNG_E_INVAL, "waves_per_cu must be <= 32");
     if (t->streams_per_lane && t->streams_per_lane != 1 && t->streams_per_lane != 2 && t->streams_per_lane != 4)

@@ -36,7 +36,9 @@ enum StoreMode : int {
     ST_PIPE = 7,          // persistent waves, double-buffered LDS tiles, stores overlapped
     ST_PIPE_NT = 8,       // as ST_PIPE with non-temporal stores
     ST_ILV_TILE = 9,      // interleaved layout through a K x block LDS tile, 16-byte stores
-    ST_ILV_TILE_NT = 10   // as ST_ILV_TILE with non-temporal stores
+    ST_ILV_TILE_NT = 10,  // as ST_ILV_TILE with non-temporal stores
+    ST_ILV_QUAD = 11,     // interleaved layout, four consecutive streams per lane, direct 16-byte stores
+    ST_ILV_QUAD_NT = 12   // as ST_ILV_QUAD with non-temporal stores
 };
 
 // Neighbour-exchange implementations of the V2 variant (tiled kernel).

@@ -361,3 +361,63 @@ def test_interleaved_persistent_workgroups(orc, G, name, variant):
     ns, n = 1 << 17, 200
     _ilv_check(orc, G, name, variant, ns, n, sigma=28,
                tuning=dict(block=256, unroll=16, store=4, streams_per_lane=2, waves_per_cu=1), calls=2)
+
+
+# ---------------------------------------------------------------------------
+# Interleaved layout, four consecutive streams per lane (tuning store 5 / 6):
+# no LDS tile; the exchange through a per-wave LDS word buffer.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("store", [5, 6])
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_interleaved_quad_lanes(orc, G, store, block):
+    # 5,024 streams: a partial last tile and a partial last wave (whole
+    # groups); n = 1003: four-step iterations plus a tail; two calls.
+    for name, variant in (("v0", 0), ("v2", 2), ("v4", 4)):
+        _ilv_check(orc, G, name, variant, 5024, 1003, sigma=29, tuning=dict(store=store, block=block))
+
+
+@pytest.mark.parametrize("group", [4, 16, 64])
+def test_interleaved_quad_lanes_group_sizes(orc, G, group):
+    # groups of 4 (one lane), 16 (four lanes) and 64 (sixteen lanes)
+    ns, n = 3072, 133
+    g = G.Generator(ns, "v2", seed=30, group=group, interleaved=True)
+    try:
+        g.set_tuning(store=6)
+        st = _oracle_states(orc, 2, 30, ns)
+        combs = orc.comb_tables(group)
+        for _ in range(2):
+            got = G.as_u32(g.generate(n))
+            want, _ = orc.generate(2, st, n, comb=combs)
+            assert np.array_equal(got.T, want)
+        assert np.array_equal(g.get_state(), st)
+    finally:
+        g.close()
+
+
+def test_interleaved_quad_lanes_persistent_and_fallbacks(orc, G, torch):
+    # persistent workgroups (two per CU) over 2^17 streams
+    _ilv_check(orc, G, "v2", 2, 1 << 17, 64, sigma=31, tuning=dict(store=6, waves_per_cu=2))
+    # V1 and V3 take the LDS tiles when the quad lanes are asked
+    _ilv_check(orc, G, "v1", 1, 1024, 77, sigma=32, tuning=dict(store=6))
+    # n_streams % 4 != 0 and a misaligned output select the per-lane kernel
+    _ilv_check(orc, G, "v0", 0, 1001, 50, sigma=33, tuning=dict(store=5))
+    g = G.Generator(1024, "v0", seed=34, interleaved=True)
+    try:
+        g.set_tuning(store=5)
+        buf = torch.empty(1024 * 64 + 1, dtype=torch.int32, device="cuda")
+        g.generate(64, out=buf[1:])
+        want, _ = orc.generate(0, _oracle_states(orc, 0, 34, 1024), 64)
+        assert np.array_equal(G.as_u32(buf[1:]).reshape(64, 1024).T, want)
+    finally:
+        g.close()
+
+
+def test_quad_store_modes_rejected_for_stream_major(G):
+    from paper_1112_5239_amd import _lib as L
+    g = G.Generator(64, "v0", seed=0)
+    try:
+        with pytest.raises(L.CprngError) as e:
+            g.set_tuning(store=5)
+        assert e.value.status == L.E_INVAL
+    finally:
+        g.close()
