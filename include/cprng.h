@@ -181,6 +181,29 @@ int cprng_consume_qc(cprng_t *h, uint64_t *counts, uint64_t n_per_stream, cprng_
 int cprng_generate_ragged(cprng_t *h, uint32_t *out, const uint64_t *lengths,
                           const uint64_t *offsets, cprng_stream_t stream);
 
+/* Bytes of the per-GPU device array cprng_generate_ragged_noalloc works in. */
+#define CPRNG_NOALLOC_SCRATCH_BYTES (16u << 20)
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): cprng_generate_ragged
+ * on a V0 handle, with the same arguments and the same results, allocating no
+ * device memory.  The work buffers of its kernels -- 8 queue counters, the run
+ * descriptors (32 bytes per stream with a nonzero length), the commit list (4
+ * bytes per such stream), the jump table (20 bytes per row; rows = the
+ * smallest power of two, at least 64, above the longest run's chunk count)
+ * and the end states (20 bytes per stream of the handle), each rounded up to
+ * 256 bytes after 256 bytes of counters -- live in one file-scope device array
+ * of CPRNG_NOALLOC_SCRATCH_BYTES (16 MiB) per GPU, held until the process
+ * ends.  The call plans on the host, copies the descriptors into the array in
+ * order on `stream`, resets the counters with a kernel and launches the chunk
+ * and commit kernels directly (no graph).  The array keeps the last call's
+ * contents, so calls that overlap on one GPU (any handles, on different
+ * streams or threads) race on it: order them on one stream.  Errors: as
+ * cprng_generate_ragged; E_UNSUPPORTED for handles other than V0; E_INVAL
+ * when the buffers would exceed the array (the detail gives the sizes). */
+int cprng_generate_ragged_noalloc(cprng_t *h, uint32_t *out, const uint64_t *lengths,
+                                  const uint64_t *offsets, cprng_stream_t stream);
+
 /* Host-only self-test of the jump-ahead used by cprng_generate_ragged (no
  * device work, no handle).  variant: CPRNG_V2_SHMEM or CPRNG_V4_XOR64 (a
  * group of C streams, comb1/comb2 host arrays of C entries or NULL for the

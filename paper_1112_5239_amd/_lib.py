@@ -58,7 +58,7 @@ class Tuning(C.Structure):
 
 EXPORTED = [
     "cprng_create", "cprng_create_ex", "cprng_destroy", "cprng_generate", "cprng_consume_qc",
-    "cprng_generate_ragged", "cprng_generate_requests", "cprng_state_words", "cprng_state_bytes", "cprng_get_state",
+    "cprng_generate_ragged", "cprng_generate_ragged_noalloc", "cprng_generate_requests", "cprng_state_words", "cprng_state_bytes", "cprng_get_state",
     "cprng_set_state", "cprng_checkpoint_bytes", "cprng_checkpoint_save", "cprng_checkpoint_load",
     "cprng_n_streams", "cprng_variant", "cprng_default_combs", "cprng_default_bbs_combs", "cprng_jump_selftest",
     "cprng_set_tuning", "cprng_get_tuning", "cprng_autotune", "cprng_autotune_ragged",
@@ -88,6 +88,7 @@ def lib():
         "cprng_generate": (i32, [vp, vp, u64, vp]),
         "cprng_consume_qc": (i32, [vp, vp, u64, vp]),
         "cprng_generate_ragged": (i32, [vp, vp, vp, vp, vp]),
+        "cprng_generate_ragged_noalloc": (i32, [vp, vp, vp, vp, vp]),
         "cprng_generate_requests": (i32, [vp, C.POINTER(Request), u32, vp]),
         "cprng_state_words": (i32, [vp]),
         "cprng_state_bytes": (C.c_size_t, [vp]),
@@ -200,6 +201,12 @@ def cprng_generate_ragged(h: int, out, lengths, offsets=None, stream=None) -> No
     """lengths/offsets: host uint64 numpy arrays of n_streams entries."""
     _check(lib().cprng_generate_ragged(h, _addr(out), _addr(lengths), _addr(offsets), _addr(stream)),
            "cprng_generate_ragged")
+
+
+def cprng_generate_ragged_noalloc(h: int, out, lengths, offsets=None, stream=None) -> None:
+    """As cprng_generate_ragged (V0 handles), allocating no device memory."""
+    _check(lib().cprng_generate_ragged_noalloc(h, _addr(out), _addr(lengths), _addr(offsets), _addr(stream)),
+           "cprng_generate_ragged_noalloc")
 
 
 def cprng_generate_requests(h: int, reqs, stream=None) -> None:

@@ -55,6 +55,25 @@ int prepare_request_tables(cprng_t *h, uint64_t max_len);
 struct RaggedPlan;
 void destroy_plans(cprng_t *h);
 
+// One launch of the V0 chunk kernels over batched uneven streams, planned on
+// the host: the runs (longest first) with their segment numbering, the
+// streams to commit, the jump-table rows needed and the launch configuration.
+struct V0Launch {
+    std::vector<RunDesc> runs;
+    std::vector<uint32_t> ids;
+    uint64_t nseg = 0, max_seg = 0;
+    uint32_t kcap = 0;
+    uint32_t chunk = 0, unroll = 0, waves = 0, block = 0, store = 0;
+};
+// Validate arguments (as cprng_generate_ragged) and plan the launch.  Needs
+// a V0 handle; no device work, no device allocation.
+int plan_ragged_v0(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets, V0Launch &p);
+// Enqueue the plan's kernels (queue reset, chunk kernel, commit) on st with
+// the given device buffers: runs, commit ids, jump table (p.kcap rows of
+// 5 words), 8 queue counters and end-state staging (5 x n_streams words).
+hipError_t launch_ragged_v0(const cprng_t *h, const V0Launch &p, const RunDesc *d_runs, const uint32_t *d_ids,
+                            const uint32_t *d_polys, uint32_t *d_counter, uint32_t *d_state_next, hipStream_t st);
+
 // Work buffers of request batches on one HIP stream (batches on different
 // streams may overlap on the device, so each stream has its own).
 struct ReqSlot {

@@ -380,6 +380,58 @@ int ragged_with(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64
     return CPRNG_OK;
 }
 
+int plan_ragged_v0(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets, V0Launch &p)
+{
+    uint64_t total = 0, max_len = 0;
+    int rc = check_ragged_args(h, out, lengths, offsets, &total, &max_len);
+    if (rc) return rc;
+    if (h->variant != CPRNG_V0_PLAIN) return set_error(CPRNG_E_UNSUPPORTED, "this path covers the V0 variant");
+    std::string why;
+    if (!jump_init(&why)) return set_error(CPRNG_E_UNSUPPORTED, "jump polynomials: " + why);
+    const SegCfg c = resolve_seg_cfg(h, total, max_len);
+    p = V0Launch{};
+    p.chunk = c.chunk;
+    p.unroll = c.unroll;
+    p.waves = c.waves;
+    p.block = c.block;
+    p.store = c.store;
+    // Longest runs first, so that the queues end with short segments.
+    std::vector<uint32_t> order;
+    for (uint32_t s = 0; s < h->ns; ++s)
+        if (lengths[s]) order.push_back(s);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return lengths[a] > lengths[b]; });
+    std::vector<uint64_t> offs(h->ns);
+    uint64_t acc = 0;
+    for (uint32_t s = 0; s < h->ns; ++s) {
+        offs[s] = offsets ? offsets[s] : acc;
+        acc += lengths[s];
+    }
+    RunList rl;
+    for (uint32_t s : order) {
+        if (!rl.add(s, (uint64_t)(uintptr_t)out + 4u * offs[s], lengths[s], c.chunk, 1))
+            return set_error(CPRNG_E_INVAL, "too many segments (raise the chunk length)");
+        p.ids.push_back(s);
+    }
+    p.runs = std::move(rl.runs);
+    p.nseg = rl.nseg;
+    p.max_seg = rl.max_seg;
+    p.kcap = kcap_for(rl.max_seg);
+    return CPRNG_OK;
+}
+
+hipError_t launch_ragged_v0(const cprng_t *h, const V0Launch &p, const RunDesc *d_runs, const uint32_t *d_ids,
+                            const uint32_t *d_polys, uint32_t *d_counter, uint32_t *d_state_next, hipStream_t st)
+{
+    const SegCfg c{p.chunk, p.unroll, p.waves, p.block, p.store};
+    SegArgs a = seg_args(h, c, d_runs, (uint32_t)p.runs.size(), p.nseg, p.kcap, d_polys, d_counter);
+    a.state_next = d_state_next;
+    hipError_t e = launch_zero_u32(d_counter, 8, st);
+    if (e == hipSuccess && p.nseg)
+        e = launch_segments(a, persistent_grid(h, c, p.nseg), c.block, seg_kernel_store(c), seg_lds_min(c), st);
+    if (e == hipSuccess) e = launch_commit(h->d_state, d_state_next, d_ids, (uint32_t)p.ids.size(), h->ns, st);
+    return e;
+}
+
 }  // namespace cprng_impl
 
 using namespace cprng_impl;
