@@ -354,17 +354,52 @@ typedef struct cprng_tuning {
 int cprng_set_tuning(cprng_t *h, const cprng_tuning_t *t);
 int cprng_get_tuning(const cprng_t *h, cprng_tuning_t *t);
 
-/* Time each candidate configuration of cprng_generate for n_per_stream on
- * this handle (the streams advance while tuning), keep the fastest, and
- * record it in the JSON cache file named by $CPRNG_TUNE_CACHE if set.
- * scratch: device buffer big enough for one generate call.  Errors: E_INVAL,
- * E_HIP. */
+/* Autotuner (the batched-launch configurations of the hot path, Sections 6
+ * and 7 give none for this hardware).  Times each candidate configuration of
+ * cprng_generate for n_per_stream on this handle with HIP events on `stream`
+ * (median of three launches after a warm-up), keeps the fastest in a
+ * process-wide table keyed by device architecture, variant, word-width flags,
+ * layout and the power-of-two classes of n_streams and n_per_stream, and
+ * rewrites the JSON cache file named by $CPRNG_TUNE_CACHE if set (read once
+ * per process, at the first lookup).  Later calls of any handle of the same
+ * class use the entry unless cprng_set_tuning overrides it.  Candidates:
+ * stream-major -- per-lane stores and LDS tiles of several widths, streams
+ * per lane, residency caps, exchange implementations; interleaved -- LDS
+ * tiles of 256/512/1024 streams x 8/16/32 steps, one or two tile buffers,
+ * exchange through cross-lane reads or the LDS word buffer, one workgroup per
+ * tile or 1/2 persistent workgroups per CU, and (V0, V2, V4) the
+ * four-streams-per-lane kernel.  The stream states are copied aside before
+ * tuning and put back after it, so the call leaves the streams where they
+ * were; scratch (device, 16-byte aligned, n_streams * n_per_stream words) is
+ * overwritten.  Synchronises `stream`.  Errors: E_INVAL (NULL, misaligned,
+ * stream-major n % 4 != 0, interleaved n_streams % 4 != 0), E_NOMEM, E_HIP. */
 int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n_per_stream, cprng_stream_t stream);
 
-/* Same for cprng_generate_ragged with the given lengths (chunk length and
- * persistent wave count).  Errors as cprng_generate_ragged. */
+/* Same for cprng_generate_ragged with the given lengths and offsets (keyed by
+ * variant, flags and the classes of n_streams, total and longest length).
+ * V0: chunk length, store mode and round, persistent waves per CU.  V1, V2,
+ * V4: store round (32/64/128 words), workgroup shape (1 or 4 waves), chunk
+ * length (automatic, half or twice the automatic one) and (V1) lanes per
+ * chunk of the aggregate pass.  States are restored as above; `out` is
+ * overwritten.  Errors as cprng_generate_ragged. */
 int cprng_autotune_ragged(cprng_t *h, uint32_t *out, const uint64_t *lengths,
                           const uint64_t *offsets, cprng_stream_t stream);
+
+/* The launch configuration the next cprng_generate of n_per_stream would use
+ * on this handle, before the per-call adjustments to alignment and LDS size
+ * (fields as cprng_tuning_t; store holds the internal mode: 9/10 interleaved
+ * tiles (10 non-temporal), 11/12 four streams per lane; waves_per_cu of the
+ * interleaved layout = persistent workgroups per CU).  *source (may be NULL):
+ * 0 defaults, 1 the autotuner's entry for this shape class, 2 cprng_set_tuning.
+ * No device work.  Errors: E_INVAL. */
+int cprng_resolved_tuning(cprng_t *h, uint64_t n_per_stream, cprng_tuning_t *out, int *source);
+
+/* Same for cprng_generate_ragged with these lengths: V0 chunk, unroll,
+ * waves_per_cu, block, store; V1/V2/V4 chunk (the automatic length resolved),
+ * unroll = store round, block = 64 * waves per workgroup, streams_per_lane =
+ * V1's aggregate lanes per chunk.  May compute the group's jump polynomial on
+ * the host.  Errors: E_INVAL, E_UNSUPPORTED (BBS, interleaved handles). */
+int cprng_resolved_tuning_ragged(cprng_t *h, const uint64_t *lengths, cprng_tuning_t *out, int *source);
 
 /* Average device time in milliseconds of the last kernel launched by the
  * most recent hot-path call on this handle, when timing is enabled with
@@ -447,6 +482,14 @@ int cprng_server_stats(const cprng_server_t *s, uint64_t *waiting, uint64_t *in_
 int cprng_server_replay(cprng_server_t *s, const uint64_t *arrival_ns, const uint32_t *client,
                         const uint64_t *length, uint32_t count, int release_results,
                         cprng_completion_t *results);
+
+/* As cprng_server_replay with release_results = 1, except that result i is
+ * kept (not released; the caller releases it) when keep[i] != 0 (host, count
+ * entries): a replay that checks a sample of the results after the run.
+ * Errors as cprng_server_replay; E_INVAL for a NULL keep with count > 0. */
+int cprng_server_replay_keep(cprng_server_t *s, const uint64_t *arrival_ns, const uint32_t *client,
+                             const uint64_t *length, uint32_t count, const uint8_t *keep,
+                             cprng_completion_t *results);
 
 /* Wait for the server's batches and free it.  NULL is a no-op. */
 void cprng_server_destroy(cprng_server_t *s);

@@ -62,9 +62,11 @@ EXPORTED = [
     "cprng_set_state", "cprng_checkpoint_bytes", "cprng_checkpoint_save", "cprng_checkpoint_load",
     "cprng_n_streams", "cprng_variant", "cprng_default_combs", "cprng_default_bbs_combs", "cprng_jump_selftest",
     "cprng_set_tuning", "cprng_get_tuning", "cprng_autotune", "cprng_autotune_ragged",
+    "cprng_resolved_tuning", "cprng_resolved_tuning_ragged",
     "cprng_enable_timing", "cprng_last_kernel_ms", "cprng_probe_fill", "cprng_probe_copy", "cprng_probe_valu",
     "cprng_strerror", "cprng_last_error", "cprng_now_ns", "cprng_server_create", "cprng_server_submit",
     "cprng_server_poll", "cprng_server_release", "cprng_server_stats", "cprng_server_replay",
+    "cprng_server_replay_keep",
     "cprng_server_destroy",
 ]
 
@@ -106,6 +108,8 @@ def lib():
         "cprng_get_tuning": (i32, [vp, C.POINTER(Tuning)]),
         "cprng_autotune": (i32, [vp, vp, u64, vp]),
         "cprng_autotune_ragged": (i32, [vp, vp, vp, vp, vp]),
+        "cprng_resolved_tuning": (i32, [vp, u64, C.POINTER(Tuning), vp]),
+        "cprng_resolved_tuning_ragged": (i32, [vp, vp, C.POINTER(Tuning), vp]),
         "cprng_enable_timing": (i32, [vp, i32]),
         "cprng_last_kernel_ms": (C.c_double, [vp]),
         "cprng_probe_fill": (i32, [vp, u64, u32, vp]),
@@ -120,6 +124,7 @@ def lib():
         "cprng_server_release": (i32, [vp, vp]),
         "cprng_server_stats": (i32, [vp, C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)]),
         "cprng_server_replay": (i32, [vp, vp, vp, vp, u32, i32, C.POINTER(Completion)]),
+        "cprng_server_replay_keep": (i32, [vp, vp, vp, vp, u32, vp, C.POINTER(Completion)]),
         "cprng_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -300,6 +305,28 @@ def cprng_get_tuning(h: int) -> dict:
             "exchange": t.exchange}
 
 
+def _tuning_dict(t) -> dict:
+    return {"block": t.block, "unroll": t.unroll, "store": t.store, "chunk": t.chunk,
+            "waves_per_cu": t.waves_per_cu, "streams_per_lane": t.streams_per_lane,
+            "exchange": t.exchange}
+
+
+_SOURCES = {0: "default", 1: "autotuned", 2: "explicit"}
+
+
+def cprng_resolved_tuning(h: int, n_per_stream: int) -> dict:
+    t, src = Tuning(), C.c_int(-1)
+    _check(lib().cprng_resolved_tuning(h, n_per_stream, C.byref(t), C.byref(src)), "cprng_resolved_tuning")
+    return {**_tuning_dict(t), "source": _SOURCES.get(src.value, src.value)}
+
+
+def cprng_resolved_tuning_ragged(h: int, lengths) -> dict:
+    t, src = Tuning(), C.c_int(-1)
+    _check(lib().cprng_resolved_tuning_ragged(h, _addr(lengths), C.byref(t), C.byref(src)),
+           "cprng_resolved_tuning_ragged")
+    return {**_tuning_dict(t), "source": _SOURCES.get(src.value, src.value)}
+
+
 def cprng_autotune(h: int, scratch, n_per_stream: int, stream=None) -> None:
     _check(lib().cprng_autotune(h, _addr(scratch), n_per_stream, _addr(stream)), "cprng_autotune")
 
@@ -379,6 +406,16 @@ def cprng_server_replay(s: int, arrival_ns, client, length, release_results: boo
     res = (Completion * max(1, n))()
     _check(lib().cprng_server_replay(s, _addr(arrival_ns), _addr(client), _addr(length), n,
                                      1 if release_results else 0, res), "cprng_server_replay")
+    return res
+
+
+def cprng_server_replay_keep(s: int, arrival_ns, client, length, keep):
+    """As cprng_server_replay with results released as they complete, except
+    those with keep[i] != 0 (uint8 numpy array)."""
+    n = len(arrival_ns)
+    res = (Completion * max(1, n))()
+    _check(lib().cprng_server_replay_keep(s, _addr(arrival_ns), _addr(client), _addr(length), n,
+                                          _addr(keep), res), "cprng_server_replay_keep")
     return res
 
 

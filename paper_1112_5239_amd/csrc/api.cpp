@@ -199,6 +199,15 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
             c.slots = 1;
             c.exchange = XCH_LDS;
         }
+        TuneEntry e;
+        if (tune_cache_lookup(h, n, &e) && e.store) {       // the autotuner's pick for this shape class
+            c.block = e.block;
+            c.unroll = e.unroll;
+            c.store = e.store;
+            c.slots = e.slots ? e.slots : 1;
+            if (e.exchange) c.exchange = e.exchange;
+            c.grid = h->n_cu * e.waves;
+        }
         if (h->tuning.streams_per_lane) c.slots = h->tuning.streams_per_lane;
         if (h->tuning.store == ST_DIRECT || h->tuning.store == ST_DIRECT_NT) c.store = ST_INTERLEAVED;
         if (h->tuning.store == ST_LDS || h->tuning.store == ST_PIPE) c.store = ST_ILV_TILE;
@@ -519,6 +528,35 @@ int cprng_get_tuning(const cprng_t *h, cprng_tuning_t *t)
 {
     if (!h || !t) return set_error(CPRNG_E_INVAL, "NULL argument");
     *t = h->tuning;
+    return CPRNG_OK;
+}
+
+static int tuning_source(const cprng_t *h, bool cached)
+{
+    const cprng_tuning_t &t = h->tuning;
+    if (t.block || t.unroll || t.store || t.chunk || t.waves_per_cu || t.streams_per_lane || t.exchange) return 2;
+    return cached ? 1 : 0;
+}
+
+int cprng_resolved_tuning(cprng_t *h, uint64_t n_per_stream, cprng_tuning_t *out, int *source)
+{
+    if (!h || !out) return set_error(CPRNG_E_INVAL, "NULL argument");
+    const LaunchCfg c = resolve_cfg(h, n_per_stream, false);
+    TuneEntry e;
+    const bool cached = tune_cache_lookup(h, n_per_stream, &e);
+    std::memset(out, 0, sizeof *out);
+    out->block = c.block;
+    out->unroll = c.unroll;
+    out->store = c.store;
+    out->streams_per_lane = c.slots;
+    out->exchange = c.exchange;
+    if (h->flags & CPRNG_F_INTERLEAVED)
+        out->waves_per_cu = h->n_cu ? c.grid / h->n_cu : 0;
+    else if (c.store == ST_PIPE || c.store == ST_PIPE_NT)
+        out->waves_per_cu = h->n_cu ? c.grid / h->n_cu : 0;
+    else
+        out->waves_per_cu = h->tuning.waves_per_cu ? h->tuning.waves_per_cu : (cached ? e.waves : default_entry(h->variant, false).waves);
+    if (source) *source = tuning_source(h, cached);
     return CPRNG_OK;
 }
 

@@ -19,6 +19,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <random>
 
@@ -416,40 +417,14 @@ void group_jump_rows(const cprng_t *h, uint64_t chunk, uint32_t rows, std::vecto
 
 namespace {
 
-template <typename T>
-int ensure_buf(T **p, size_t *cap, size_t n)
-{
-    if (*cap >= n && *p) return CPRNG_OK;
-    if (*p) (void)hipFree(*p);
-    *p = nullptr;
-    *cap = 0;
-    if (hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess)
-        return set_error(CPRNG_E_NOMEM, "hipMalloc of group-jump buffers failed");
-    *cap = n;
-    return CPRNG_OK;
-}
-
-// Store round of the chunk kernels: the tuning's unroll when it is 32, 64 or
-// 128 words, else the default.
-uint32_t chunk_round(const cprng_t *h)
-{
-    const uint32_t u = h->tuning.unroll;
-    return (u == 32 || u == 64 || u == 128) ? u : 64u;
-}
-
-// Waves per workgroup of the chunk kernels: 4 for a tuning block of 256, 1
-// for 64, else the default.
-uint32_t chunk_wg_waves(const cprng_t *h)
-{
-    const uint32_t b = h->tuning.block;
-    return b == 256 ? 4u : b == 64 ? 1u : 4u;
-}
+// Store round of the chunk kernels: 32, 64 or 128 words.
+uint32_t norm_round(uint32_t u) { return (u == 32 || u == 64 || u == 128) ? u : 64u; }
 
 // Waves of a chunk kernel that stay resident per CU, from its tile's LDS
 // (the kernels' other limits are looser).
-uint64_t chunk_resident_waves(const cprng_t *h)
+uint64_t chunk_resident_waves(const ChunkCfg &c)
 {
-    const uint64_t K = chunk_round(h), W = chunk_wg_waves(h);
+    const uint64_t K = c.round, W = c.wg_waves;
     const uint64_t wg_lds = W * 64u * (K + 1u) * 4u;
     return std::min<uint64_t>(32u, (kMaxLdsBytes / wg_lds) * W);
 }
@@ -470,43 +445,158 @@ uint64_t fit_chunk(uint64_t lo, uint64_t cap, F &&n_items)
     return hi;
 }
 
+// Device buffer that grows on demand.
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+int ensure(DevBuf &b, size_t bytes)
+{
+    if (b.p && b.cap >= bytes) return CPRNG_OK;
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    if (hipMalloc(&b.p, std::max<size_t>(bytes, 16)) != hipSuccess)
+        return set_error(CPRNG_E_NOMEM, "hipMalloc of batched-run buffers failed");
+    b.cap = bytes;
+    return CPRNG_OK;
+}
+
+void release(DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+template <typename T>
+int put(DevBuf &b, const std::vector<T> &v)
+{
+    int rc = ensure(b, v.size() * sizeof(T));
+    if (rc || v.empty()) return rc;
+    if (hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return set_error(CPRNG_E_HIP, "hipMemcpy of batched-run tables");
+    return CPRNG_OK;
+}
+
 }  // namespace
 
-int ragged_groups(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets,
-                  hipStream_t st)
-{
-    const uint32_t C = h->group;
-    for (uint32_t g0 = 0; g0 < h->ns; g0 += C)
-        for (uint32_t j = 1; j < C; ++j)
-            if (lengths[g0 + j] != lengths[g0])
-                return set_error(CPRNG_E_INVAL, "V2/V4: lengths must be equal within each group of C streams");
-    int rc = group_minpoly(h);
-    if (rc) return rc;
-    const uint32_t n_groups = h->ns / C;
-    uint64_t group_steps = 0, max_len = 0;
-    for (uint32_t g = 0; g < n_groups; ++g) {
-        group_steps += lengths[(size_t)g * C];
-        max_len = std::max(max_len, lengths[(size_t)g * C]);
+// Device tables of one batched call of V1 or V2/V4.
+struct ChunkBufs {
+    DevBuf items, rows, sub_rows, offs, order, agg, sfirst;
+    void release_all()
+    {
+        for (DevBuf *b : {&items, &rows, &sub_rows, &offs, &order, &agg, &sfirst}) release(*b);
     }
-    if (group_steps == 0) return CPRNG_OK;
-    // Chunk: the shortest (a multiple of 64, at least 16 x the jump's length,
-    // at most 2^20) whose items all fit one pass of the chip's resident waves.
-    // The exchange reads' latency wants many waves, fewer and longer runs in
-    // flight store better, and a second pass that is only partly full costs
-    // nearly a whole chunk's time.  Resident waves per CU follow from the
-    // tile's LDS (the kernel's other limits are looser); the pass is filled
-    // to 31/32, so a workgroup the dispatcher places late does not start a
-    // second one.
-    uint64_t chunk = h->tuning.chunk ? h->tuning.chunk : 0;
-    if (!chunk) {
-        const uint64_t cap = (uint64_t)h->n_cu * chunk_resident_waves(h) * (64u / C) * 31u / 32u;   // 3% slack
-        chunk = fit_chunk(16ull * (uint64_t)h->gj_deg, cap, [&](uint64_t c) {
+};
+
+// A cached batched call: its inputs, tables and captured graph.
+struct ChunkPlan {
+    std::vector<uint64_t> lengths, offsets;
+    uint32_t *out = nullptr;
+    ChunkCfg cfg;
+    ChunkBufs bufs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+
+namespace {
+
+uint64_t g_chunk_clock = 0;
+
+void free_chunk_plan(ChunkPlan *p)
+{
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->bufs.release_all();
+    delete p;
+}
+
+// Host side of one batched call: the chunk list, jump rows and offsets.
+struct ChunkHost {
+    ChunkCfg cfg;                      // resolved: chunk > 0
+    std::vector<GroupItem> gitems;     // V2/V4
+    std::vector<V1Item> vitems;        // V1
+    std::vector<uint32_t> order;       // V1: chunks with a successor
+    std::vector<uint32_t> sfirst;      // V1: first chunk per stream (+ end)
+    std::vector<uint32_t> rows, sub_rows;
+    std::vector<uint64_t> offs;
+    uint32_t row_words = 0, off[3] = {0, 0, 0}, deg[3] = {0, 0, 0}, w3 = 0, n_rows = 0;
+};
+
+bool is_v1(const cprng_t *h) { return h->variant == CPRNG_V1_NAIVE3; }
+
+const V1Polys &v1_polys_of(const cprng_t *h)
+{
+    const bool w32 = (h->flags & CPRNG_F_V1_W32) != 0;
+    const bool xor64 = (h->flags & CPRNG_F_V1_XOR64) != 0;
+    return v1_polys(w32 ? 32 : 64, xor64 ? 7u : 17u, xor64 ? 17u : 5u);
+}
+
+// Automatic chunk: the shortest multiple of 64 (at least 16 x the jump's
+// length, at most 2^20) whose chunks fill at most 31/32 of `passes` passes
+// of the chunk kernel's resident waves.  Its time follows whole passes (a
+// last pass that is mostly empty costs a whole chunk's time); the exchange
+// variants want their chunks in one pass (the exchange reads' latency needs
+// many waves; fewer, longer runs in flight store better), V1 in two (its
+// aggregate pass wants the waves).  The 3% slack keeps a workgroup the
+// dispatcher places late from opening another pass.
+uint64_t auto_chunk(const cprng_t *h, const uint64_t *lengths, const ChunkCfg &c, uint64_t jump_len)
+{
+    if (is_v1(h)) {
+        const uint64_t cap = 2u * (uint64_t)h->n_cu * chunk_resident_waves(c) * 64u * 31u / 32u;
+        return fit_chunk(16ull * jump_len, cap, [&](uint64_t ch) {
             uint64_t n = 0;
-            for (uint32_t g = 0; g < n_groups; ++g) n += (lengths[(size_t)g * C] + c - 1) / c;
+            for (uint32_t s = 0; s < h->ns; ++s) n += (lengths[s] + ch - 1) / ch;
             return n;
         });
     }
-    std::vector<GroupItem> items;
+    const uint32_t C = h->group;
+    const uint64_t cap = (uint64_t)h->n_cu * chunk_resident_waves(c) * (64u / C) * 31u / 32u;
+    return fit_chunk(16ull * jump_len, cap, [&](uint64_t ch) {
+        uint64_t n = 0;
+        for (uint32_t g = 0; g < h->ns / C; ++g) n += (lengths[(size_t)g * C] + ch - 1) / ch;
+        return n;
+    });
+}
+
+uint64_t jump_length(const cprng_t *h)
+{
+    if (is_v1(h)) {
+        const V1Polys &P = v1_polys_of(h);
+        return (uint64_t)(P.deg[0] + P.deg[1] + P.deg[2]);
+    }
+    return (uint64_t)h->gj_deg;
+}
+
+// Minimal polynomials of the handle's variant (V1: per process; V2/V4: per
+// handle).
+int prepare_polys(cprng_t *h)
+{
+    if (is_v1(h)) return v1_polys_of(h).ok ? CPRNG_OK : set_error(CPRNG_E_HIP, "V1 jump-ahead: no annihilating polynomial found");
+    return group_minpoly(h);
+}
+
+void fill_offsets(const cprng_t *h, const uint64_t *lengths, const uint64_t *offsets, std::vector<uint64_t> &offs)
+{
+    offs.resize(h->ns);
+    uint64_t acc = 0;
+    for (uint32_t s = 0; s < h->ns; ++s) {
+        offs[s] = offsets ? offsets[s] : acc;
+        acc += lengths[s];
+    }
+}
+
+int plan_groups(const cprng_t *h, const uint64_t *lengths, const uint64_t *offsets, ChunkHost &p)
+{
+    const uint32_t C = h->group;
+    const uint32_t n_groups = h->ns / C;
+    uint64_t max_len = 0;
+    for (uint32_t g = 0; g < n_groups; ++g) max_len = std::max(max_len, lengths[(size_t)g * C]);
+    const uint64_t chunk = p.cfg.chunk;
     for (uint32_t g = 0; g < n_groups; ++g) {
         const uint64_t L = lengths[(size_t)g * C];
         for (uint64_t a = 0, c = 0; a < L; a += chunk, ++c) {
@@ -516,82 +606,34 @@ int ragged_groups(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint
             it.start = a;
             it.len = std::min(chunk, L - a);
             it.last = (a + chunk >= L) ? 1u : 0u;
-            items.push_back(it);
+            p.gitems.push_back(it);
         }
     }
-    const uint32_t n_rows = (uint32_t)((max_len + chunk - 1) / chunk);
-    std::vector<uint32_t> rows;
-    group_jump_rows(h, chunk, n_rows, rows);
-    std::vector<uint64_t> offs(h->ns);
-    uint64_t acc = 0;
-    for (uint32_t s = 0; s < h->ns; ++s) {
-        offs[s] = offsets ? offsets[s] : acc;
-        acc += lengths[s];
-    }
-    // The buffers are reused by the next call: wait for the previous one.
-    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
-    const size_t nwords = (size_t)h->ns * h->words;
-    if ((rc = ensure_buf(&h->d_gj_next, &h->gj_next_cap, nwords))) return rc;
-    if ((rc = ensure_buf(&h->d_gj_items, &h->gj_items_cap, items.size()))) return rc;
-    if ((rc = ensure_buf(&h->d_gj_rows, &h->gj_rows_cap, rows.size()))) return rc;
-    if ((rc = ensure_buf(&h->d_gj_offsets, &h->gj_offsets_cap, offs.size()))) return rc;
-    HIP_TRY(hipMemcpy(h->d_gj_items, items.data(), items.size() * sizeof(GroupItem), hipMemcpyHostToDevice),
-            "hipMemcpy items");
-    HIP_TRY(hipMemcpy(h->d_gj_rows, rows.data(), rows.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
-            "hipMemcpy jump rows");
-    HIP_TRY(hipMemcpy(h->d_gj_offsets, offs.data(), offs.size() * sizeof(uint64_t), hipMemcpyHostToDevice),
-            "hipMemcpy offsets");
-    GroupJumpArgs a;
-    fill_gen_args(h, a.g);
-    a.state_next = h->d_gj_next;
-    a.items = h->d_gj_items;
-    a.n_items = (uint32_t)items.size();
-    a.rows = h->d_gj_rows;
-    a.row_words = (uint32_t)((h->gj_deg + 31) / 32);
-    a.deg = (uint32_t)h->gj_deg;
-    a.round = chunk_round(h);
-    a.wg_waves = chunk_wg_waves(h);
-    a.out = out;
-    a.offsets = h->d_gj_offsets;
-    int trc = timing_begin(h, st);
-    if (trc) return trc;
-    HIP_TRY(launch_copy(h->d_gj_next, h->d_state, nwords, st), "state copy");
-    HIP_TRY(launch_group_chunks(a, (int)h->variant, st), "group chunk kernel launch");
-    HIP_TRY(launch_copy(h->d_state, h->d_gj_next, nwords, st), "state commit");
-    return timing_end(h, st);
+    if (p.gitems.size() > 0xFFFFFFFFull) return set_error(CPRNG_E_INVAL, "too many chunks");
+    p.n_rows = (uint32_t)((max_len + chunk - 1) / chunk);
+    group_jump_rows(h, chunk, p.n_rows, p.rows);
+    p.row_words = (uint32_t)((h->gj_deg + 31) / 32);
+    fill_offsets(h, lengths, offsets, p.offs);
+    return CPRNG_OK;
 }
 
-int ragged_v1(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets, hipStream_t st)
+void put_poly(std::vector<uint32_t> &dst, size_t word0, const Poly &r, int deg)
 {
-    const bool w32 = (h->flags & CPRNG_F_V1_W32) != 0;
-    const bool xor64 = (h->flags & CPRNG_F_V1_XOR64) != 0;
-    const V1Polys &P = v1_polys(w32 ? 32 : 64, xor64 ? 7u : 17u, xor64 ? 17u : 5u);
-    if (!P.ok) return set_error(CPRNG_E_HIP, "V1 jump-ahead: no annihilating polynomial found");
-    uint64_t total = 0, max_len = 0;
+    for (int b = 0; b < deg; ++b)
+        if (pbit(r, b)) dst[word0 + (b >> 5)] |= 1u << (b & 31);
+}
+
+int plan_v1(const cprng_t *h, const uint64_t *lengths, const uint64_t *offsets, ChunkHost &p)
+{
+    const V1Polys &P = v1_polys_of(h);
+    uint64_t max_len = 0;
+    for (uint32_t s = 0; s < h->ns; ++s) max_len = std::max(max_len, lengths[s]);
+    const uint64_t chunk = p.cfg.chunk;
+    const uint32_t parts = p.cfg.parts;
+    p.sfirst.resize((size_t)h->ns + 1);
     for (uint32_t s = 0; s < h->ns; ++s) {
-        total += lengths[s];
-        max_len = std::max(max_len, lengths[s]);
-    }
-    if (total == 0) return CPRNG_OK;
-    const uint64_t jump_steps = (uint64_t)(P.deg[0] + P.deg[1] + P.deg[2]);
-    // Chunk: one lane per chunk.  The shortest (a multiple of 64, at least
-    // 16 x the jump's steps, at most 2^20) whose chunks fill at most 31/32 of
-    // two passes of the generating kernel's resident waves: its time follows
-    // whole passes (a last pass that is mostly empty costs a whole chunk's
-    // time), and the aggregate pass's serial xorwow chains want the twice as
-    // many waves that two passes' worth of chunks give it.
-    uint64_t chunk = h->tuning.chunk ? h->tuning.chunk : 0;
-    if (!chunk) {
-        const uint64_t cap = 2u * (uint64_t)h->n_cu * chunk_resident_waves(h) * 64u * 31u / 32u;
-        chunk = fit_chunk(16ull * jump_steps, cap, [&](uint64_t c) {
-            uint64_t n = 0;
-            for (uint32_t s = 0; s < h->ns; ++s) n += (lengths[s] + c - 1) / c;
-            return n;
-        });
-    }
-    std::vector<V1Item> items;
-    for (uint32_t s = 0; s < h->ns; ++s) {
-        const uint32_t first = (uint32_t)items.size();
+        const uint32_t first = (uint32_t)p.vitems.size();
+        p.sfirst[s] = first;
         for (uint64_t a = 0, c = 0; a < lengths[s]; a += chunk, ++c) {
             V1Item it{};
             it.stream = s;
@@ -600,93 +642,410 @@ int ragged_v1(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t
             it.len = std::min(chunk, lengths[s] - a);
             it.last = (a + chunk >= lengths[s]) ? 1u : 0u;
             it.first = first;
-            items.push_back(it);
+            if (!it.last) p.order.push_back((uint32_t)p.vitems.size());
+            p.vitems.push_back(it);
         }
+        if (p.vitems.size() > 0xFFFFFFF0ull) return set_error(CPRNG_E_INVAL, "too many chunks");
     }
-    if (items.size() > 0xFFFFFFFFull) return set_error(CPRNG_E_INVAL, "too many chunks");
-    const uint32_t n_rows = (uint32_t)((max_len + chunk - 1) / chunk);
-    uint32_t wk[3], off[3];
-    uint32_t row_words = 0;
+    p.sfirst[h->ns] = (uint32_t)p.vitems.size();
+    if (p.order.size() * (uint64_t)parts > 0xFFFFFFF0ull) return set_error(CPRNG_E_INVAL, "too many chunks");
+    p.n_rows = (uint32_t)((max_len + chunk - 1) / chunk);
+    uint32_t wk[3];
+    p.row_words = 0;
     for (int k = 0; k < 3; ++k) {
+        p.deg[k] = (uint32_t)P.deg[k];
         wk[k] = (uint32_t)((P.deg[k] + 31) / 32);
-        off[k] = row_words;
-        row_words += wk[k];
+        p.off[k] = p.row_words;
+        p.row_words += wk[k];
     }
+    p.w3 = wk[2];
     // rows 0..n_rows-1: X^(c * chunk) per generator; row n_rows: the sums
     // sum_{i=1..chunk} X^i of the xorshift and xor128 maps (full chunks'
     // aggregates)
-    std::vector<uint32_t> rows((size_t)(n_rows + 1) * row_words, 0);
-    for (int k = 0; k < 2; ++k) {
-        const Poly g = pgeomsum(chunk, P.q[k]);
-        for (int b = 0; b < P.deg[k]; ++b)
-            if (pbit(g, b)) rows[(size_t)n_rows * row_words + off[k] + (b >> 5)] |= 1u << (b & 31);
-    }
+    p.rows.assign((size_t)(p.n_rows + 1) * p.row_words, 0);
+    for (int k = 0; k < 2; ++k)
+        put_poly(p.rows, (size_t)p.n_rows * p.row_words + p.off[k], pgeomsum(chunk, P.q[k]), P.deg[k]);
     for (int k = 0; k < 3; ++k) {
         const Poly base = pxpow(chunk, P.q[k]);
         Poly r{1};
         pmod(r, P.q[k]);
-        for (uint32_t c = 0; c < n_rows; ++c) {
-            for (int b = 0; b < P.deg[k]; ++b)
-                if (pbit(r, b)) rows[(size_t)c * row_words + off[k] + (b >> 5)] |= 1u << (b & 31);
+        for (uint32_t c = 0; c < p.n_rows; ++c) {
+            put_poly(p.rows, (size_t)c * p.row_words + p.off[k], r, P.deg[k]);
             r = pmulmod(r, base, P.q[k]);
         }
     }
-    std::vector<uint64_t> offs(h->ns);
-    uint64_t acc = 0;
-    for (uint32_t s = 0; s < h->ns; ++s) {
-        offs[s] = offsets ? offsets[s] : acc;
-        acc += lengths[s];
+    // xorwow sub-starts of the aggregate pass: X^(c * chunk + j * chunk / parts)
+    const Poly step = pxpow(chunk / parts, P.q[2]);
+    p.sub_rows.assign((size_t)p.n_rows * parts * p.w3, 0);
+    Poly r{1};
+    pmod(r, P.q[2]);
+    for (uint32_t c = 0; c < p.n_rows; ++c)
+        for (uint32_t j = 0; j < parts; ++j) {
+            put_poly(p.sub_rows, ((size_t)c * parts + j) * p.w3, r, P.deg[2]);
+            r = pmulmod(r, step, P.q[2]);       // after `parts` steps: X^((c + 1) * chunk)
+        }
+    fill_offsets(h, lengths, offsets, p.offs);
+    return CPRNG_OK;
+}
+
+int upload(const ChunkHost &p, ChunkBufs &b)
+{
+    int rc = put(b.rows, p.rows);
+    if (!rc) rc = put(b.offs, p.offs);
+    if (p.vitems.empty()) {
+        if (!rc) rc = put(b.items, p.gitems);
+        return rc;
     }
-    // aggregate pass order: full chunks, then the shorter last ones
-    std::vector<uint32_t> order;
-    order.reserve(items.size());
-    for (int pass = 0; pass < 2; ++pass)
-        for (uint32_t i = 0; i < (uint32_t)items.size(); ++i)
-            if ((items[i].len == chunk) == (pass == 0)) order.push_back(i);
-    // The buffers are reused by the next call: wait for the previous one.
-    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (!rc) rc = put(b.items, p.vitems);
+    if (!rc) rc = put(b.order, p.order);
+    if (!rc) rc = put(b.sfirst, p.sfirst);
+    if (!rc) rc = put(b.sub_rows, p.sub_rows);
+    if (!rc) rc = ensure(b.agg, p.vitems.size() * sizeof(uint32_t));
+    return rc;
+}
+
+// Kernels of one call, in stream order: copy of the start states, the chunk
+// kernels, commit of the end states.
+hipError_t enqueue(const cprng_t *h, const ChunkHost &p, const ChunkBufs &b, uint32_t *out, hipStream_t st)
+{
     const size_t nwords = (size_t)h->ns * h->words;
-    int rc;
-    if ((rc = ensure_buf(&h->d_gj_next, &h->gj_next_cap, nwords))) return rc;
-    if ((rc = ensure_buf(&h->d_v1_items, &h->v1_items_cap, items.size()))) return rc;
-    if ((rc = ensure_buf(&h->d_v1_order, &h->v1_order_cap, order.size()))) return rc;
-    HIP_TRY(hipMemcpy(h->d_v1_order, order.data(), order.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
-            "hipMemcpy order");
-    if ((rc = ensure_buf(&h->d_v1_agg, &h->v1_agg_cap, items.size()))) return rc;
-    if ((rc = ensure_buf(&h->d_gj_rows, &h->gj_rows_cap, rows.size()))) return rc;
-    if ((rc = ensure_buf(&h->d_gj_offsets, &h->gj_offsets_cap, offs.size()))) return rc;
-    HIP_TRY(hipMemcpy(h->d_v1_items, items.data(), items.size() * sizeof(V1Item), hipMemcpyHostToDevice),
-            "hipMemcpy items");
-    HIP_TRY(hipMemcpy(h->d_gj_rows, rows.data(), rows.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
-            "hipMemcpy jump rows");
-    HIP_TRY(hipMemcpy(h->d_gj_offsets, offs.data(), offs.size() * sizeof(uint64_t), hipMemcpyHostToDevice),
-            "hipMemcpy offsets");
-    V1ChunkArgs a;
-    fill_gen_args(h, a.g);
-    a.state_next = h->d_gj_next;
-    a.items = h->d_v1_items;
-    a.n_items = (uint32_t)items.size();
-    a.row_words = row_words;
-    a.deg1 = (uint32_t)P.deg[0];
-    a.deg2 = (uint32_t)P.deg[1];
-    a.deg3 = (uint32_t)P.deg[2];
-    a.off2 = off[1];
-    a.off3 = off[2];
-    a.rows = h->d_gj_rows;
-    a.agg = h->d_v1_agg;
-    a.out = out;
-    a.offsets = h->d_gj_offsets;
-    a.chunk = chunk;
-    a.sum_row = n_rows;
-    a.round = chunk_round(h);
-    a.wg_waves = chunk_wg_waves(h);
-    a.order = h->d_v1_order;
-    int trc = timing_begin(h, st);
-    if (trc) return trc;
-    HIP_TRY(launch_copy(h->d_gj_next, h->d_state, nwords, st), "state copy");
-    HIP_TRY(launch_v1_chunks(a, w32, st), "V1 chunk kernels launch");
-    HIP_TRY(launch_copy(h->d_state, h->d_gj_next, nwords, st), "state commit");
-    return timing_end(h, st);
+    hipError_t e = launch_copy(h->d_gj_next, h->d_state, nwords, st);
+    if (e != hipSuccess) return e;
+    if (!p.vitems.empty()) {
+        V1ChunkArgs a;
+        std::memset(&a, 0, sizeof a);
+        fill_gen_args(h, a.g);
+        a.state_next = h->d_gj_next;
+        a.items = (const V1Item *)b.items.p;
+        a.n_items = (uint32_t)p.vitems.size();
+        a.row_words = p.row_words;
+        a.deg1 = p.deg[0];
+        a.deg2 = p.deg[1];
+        a.deg3 = p.deg[2];
+        a.off2 = p.off[1];
+        a.off3 = p.off[2];
+        a.rows = (const uint32_t *)b.rows.p;
+        a.agg = (uint32_t *)b.agg.p;
+        a.out = out;
+        a.offsets = (const uint64_t *)b.offs.p;
+        a.chunk = p.cfg.chunk;
+        a.sum_row = p.n_rows;
+        a.round = p.cfg.round;
+        a.wg_waves = p.cfg.wg_waves;
+        a.order = (const uint32_t *)b.order.p;
+        a.n_agg = (uint32_t)p.order.size();
+        a.parts = p.cfg.parts;
+        a.sub_rows = (const uint32_t *)b.sub_rows.p;
+        a.w3 = p.w3;
+        a.sfirst = (const uint32_t *)b.sfirst.p;
+        e = launch_v1_chunks(a, (h->flags & CPRNG_F_V1_W32) != 0, st);
+    } else if (!p.gitems.empty()) {
+        GroupJumpArgs a;
+        std::memset(&a, 0, sizeof a);
+        fill_gen_args(h, a.g);
+        a.state_next = h->d_gj_next;
+        a.items = (const GroupItem *)b.items.p;
+        a.n_items = (uint32_t)p.gitems.size();
+        a.rows = (const uint32_t *)b.rows.p;
+        a.row_words = p.row_words;
+        a.deg = (uint32_t)h->gj_deg;
+        a.round = p.cfg.round;
+        a.wg_waves = p.cfg.wg_waves;
+        a.out = out;
+        a.offsets = (const uint64_t *)b.offs.p;
+        e = launch_group_chunks(a, (int)h->variant, st);
+    }
+    if (e != hipSuccess) return e;
+    return launch_copy(h->d_state, h->d_gj_next, nwords, st);
+}
+
+int plan_host(cprng_t *h, const uint64_t *lengths, const uint64_t *offsets, const ChunkCfg &cfg, ChunkHost &p)
+{
+    p.cfg = cfg;
+    p.cfg.round = norm_round(cfg.round);
+    p.cfg.wg_waves = cfg.wg_waves == 1 ? 1u : 4u;
+    p.cfg.parts = (cfg.parts == 1 || cfg.parts == 2 || cfg.parts == 4) ? cfg.parts : 2u;
+    if (!p.cfg.chunk) p.cfg.chunk = auto_chunk(h, lengths, p.cfg, jump_length(h));
+    if (p.cfg.chunk % 64u || p.cfg.chunk > (1ull << 40))
+        return set_error(CPRNG_E_INVAL, "chunk must be a multiple of 64");
+    return is_v1(h) ? plan_v1(h, lengths, offsets, p) : plan_groups(h, lengths, offsets, p);
+}
+
+int ensure_next(cprng_t *h)
+{
+    const size_t need = (size_t)h->ns * h->words;
+    if (h->d_gj_next && h->gj_next_cap >= need) return CPRNG_OK;
+    if (h->d_gj_next) (void)hipFree(h->d_gj_next);       // waits for the device
+    h->d_gj_next = nullptr;
+    h->gj_next_cap = 0;
+    if (hipMalloc((void **)&h->d_gj_next, need * sizeof(uint32_t)) != hipSuccess)
+        return set_error(CPRNG_E_NOMEM, "hipMalloc of the end-state buffer failed");
+    h->gj_next_cap = need;
+    return CPRNG_OK;
+}
+
+bool same_cfg(const ChunkCfg &a, const ChunkCfg &b)
+{
+    return a.chunk == b.chunk && a.round == b.round && a.wg_waves == b.wg_waves && a.parts == b.parts;
+}
+
+ChunkPlan *find_chunk_plan(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets,
+                           const ChunkCfg &cfg)
+{
+    for (ChunkPlan *p : h->chunk_plans) {
+        if (p->out != out || !same_cfg(p->cfg, cfg)) continue;
+        if (std::memcmp(p->lengths.data(), lengths, sizeof(uint64_t) * h->ns) != 0) continue;
+        bool same = true;
+        uint64_t acc = 0;
+        for (uint32_t s = 0; s < h->ns && same; ++s) {
+            same = p->offsets[s] == (offsets ? offsets[s] : acc);
+            acc += lengths[s];
+        }
+        if (same) return p;
+    }
+    return nullptr;
+}
+
+int build_chunk_plan(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets,
+                     const ChunkCfg &cfg, ChunkPlan **res)
+{
+    ChunkHost hp;
+    int rc = plan_host(h, lengths, offsets, cfg, hp);
+    if (rc) return rc;
+    std::unique_ptr<ChunkPlan, void (*)(ChunkPlan *)> p(new ChunkPlan(), free_chunk_plan);
+    p->lengths.assign(lengths, lengths + h->ns);
+    fill_offsets(h, lengths, offsets, p->offsets);
+    p->out = out;
+    p->cfg = cfg;
+    if ((rc = upload(hp, p->bufs))) return rc;
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+        return set_error(CPRNG_E_HIP, "hipStreamCreate (capture)");
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = enqueue(h, hp, p->bufs, out, cs);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_error(e, "capture of the batched kernels");
+    }
+    if (e2 != hipSuccess) return hip_error(e2, "hipStreamEndCapture");
+    p->graph = graph;
+    e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_error(e, "hipGraphInstantiate");
+    *res = p.release();
+    return CPRNG_OK;
+}
+
+void drop_chunk_plan(cprng_t *h, ChunkPlan *p)
+{
+    auto it = std::find(h->chunk_plans.begin(), h->chunk_plans.end(), p);
+    if (it != h->chunk_plans.end()) h->chunk_plans.erase(it);
+    free_chunk_plan(p);
+}
+
+int check_group_lengths(const cprng_t *h, const uint64_t *lengths)
+{
+    if (is_v1(h)) return CPRNG_OK;
+    const uint32_t C = h->group;
+    for (uint32_t g0 = 0; g0 < h->ns; g0 += C)
+        for (uint32_t j = 1; j < C; ++j)
+            if (lengths[g0 + j] != lengths[g0])
+                return set_error(CPRNG_E_INVAL, "V2/V4: lengths must be equal within each group of C streams");
+    return CPRNG_OK;
+}
+
+}  // namespace
+
+ChunkCfg resolve_chunk_cfg(const cprng_t *h, uint64_t total, uint64_t max_len)
+{
+    // Defaults measured on MI355X (4,096 V1 streams / 128 V2 groups of 32,
+    // lengths log-uniform in [1e3, 1e7]): rounds of 64 words, four-wave
+    // workgroups, automatic chunk; V1 aggregates split over two lanes.
+    ChunkCfg c;
+    c.chunk = 0;
+    c.round = 64;
+    c.wg_waves = 4;
+    c.parts = 2;
+    TuneEntry e;
+    if (tune_cache_lookup_key(tune_key_ragged(h, total, max_len), &e)) {
+        c.chunk = e.chunk;
+        if (e.unroll) c.round = e.unroll;
+        if (e.block) c.wg_waves = e.block == 64 ? 1u : 4u;
+        if (e.slots) c.parts = e.slots;
+    }
+    if (h->tuning.chunk) c.chunk = h->tuning.chunk;
+    if (h->tuning.unroll) c.round = h->tuning.unroll;
+    if (h->tuning.block == 64 || h->tuning.block == 256) c.wg_waves = h->tuning.block == 64 ? 1u : 4u;
+    if (h->tuning.streams_per_lane) c.parts = h->tuning.streams_per_lane;
+    c.round = norm_round(c.round);
+    if (c.parts != 1 && c.parts != 2 && c.parts != 4) c.parts = 2;
+    return c;
+}
+
+int ragged_chunked(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets, hipStream_t st,
+                   const ChunkCfg &cfg, bool cached)
+{
+    int rc = check_group_lengths(h, lengths);
+    if (rc) return rc;
+    uint64_t total = 0;
+    for (uint32_t s = 0; s < h->ns; ++s) total += lengths[s];
+    if (total == 0) return CPRNG_OK;
+    if ((rc = prepare_polys(h))) return rc;
+    if ((rc = ensure_next(h))) return rc;
+    if (!cached) {
+        // One-off call (request rounds): plan, wait until the previous call
+        // has released the shared tables, upload, launch.
+        ChunkHost hp;
+        if ((rc = plan_host(h, lengths, offsets, cfg, hp))) return rc;
+        if (!h->chunk_direct) h->chunk_direct = new ChunkBufs();
+        HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+        if ((rc = upload(hp, *h->chunk_direct))) return rc;
+        if ((rc = timing_begin(h, st))) return rc;
+        HIP_TRY(enqueue(h, hp, *h->chunk_direct, out, st), "batched kernels");
+        return timing_end(h, st);
+    }
+    ChunkPlan *p = find_chunk_plan(h, out, lengths, offsets, cfg);
+    if (!p) {
+        if ((rc = build_chunk_plan(h, out, lengths, offsets, cfg, &p))) return rc;
+        if (h->chunk_plans.size() >= 8) {
+            auto it = std::min_element(h->chunk_plans.begin(), h->chunk_plans.end(),
+                                       [](ChunkPlan *a, ChunkPlan *b) { return a->last_use < b->last_use; });
+            free_chunk_plan(*it);
+            h->chunk_plans.erase(it);
+        }
+        h->chunk_plans.push_back(p);
+    }
+    p->last_use = ++g_chunk_clock;
+    if (h->timing && hipEventRecord(h->ev0, st) != hipSuccess) return set_error(CPRNG_E_HIP, "hipEventRecord");
+    HIP_TRY(hipGraphLaunch(p->exec, st), "hipGraphLaunch");
+    if (h->timing) {
+        if (hipEventRecord(h->ev1, st) != hipSuccess) return set_error(CPRNG_E_HIP, "hipEventRecord");
+        h->ev_pending = true;
+    }
+    return CPRNG_OK;
+}
+
+int chunk_for(cprng_t *h, const uint64_t *lengths, const ChunkCfg &cfg, uint64_t *chunk)
+{
+    if (cfg.chunk) {
+        *chunk = cfg.chunk;
+        return CPRNG_OK;
+    }
+    const int rc = prepare_polys(h);
+    if (rc) return rc;
+    ChunkCfg c = cfg;
+    c.round = norm_round(c.round);
+    c.wg_waves = c.wg_waves == 1 ? 1u : 4u;
+    *chunk = auto_chunk(h, lengths, c, jump_length(h));
+    return CPRNG_OK;
+}
+
+int ragged_groups(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets, hipStream_t st)
+{
+    uint64_t total = 0, max_len = 0;
+    for (uint32_t s = 0; s < h->ns; ++s) {
+        total += lengths[s];
+        max_len = std::max(max_len, lengths[s]);
+    }
+    return ragged_chunked(h, out, lengths, offsets, st, resolve_chunk_cfg(h, total, max_len), true);
+}
+
+int ragged_v1(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets, hipStream_t st,
+              bool cached)
+{
+    uint64_t total = 0, max_len = 0;
+    for (uint32_t s = 0; s < h->ns; ++s) {
+        total += lengths[s];
+        max_len = std::max(max_len, lengths[s]);
+    }
+    return ragged_chunked(h, out, lengths, offsets, st, resolve_chunk_cfg(h, total, max_len), cached);
+}
+
+// Autotuner of the chunk kernels (V1, V2, V4): store round, workgroup
+// shape, chunk length around the automatic one and (V1) the aggregate
+// pass's lanes per chunk.  Each candidate runs as its own cached graph;
+// only the winner's graph is kept.
+int autotune_chunked(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets, hipStream_t st,
+                     uint64_t total, uint64_t max_len)
+{
+    int rc = check_group_lengths(h, lengths);
+    if (rc) return rc;
+    if (total == 0) return CPRNG_OK;
+    if ((rc = prepare_polys(h))) return rc;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return set_error(CPRNG_E_HIP, "hipEventCreate");
+    const bool saved_timing = h->timing;
+    h->timing = false;
+    float best = 1e30f;
+    ChunkCfg best_c = resolve_chunk_cfg(h, total, max_len);
+    bool best_auto = best_c.chunk == 0;
+    const uint32_t rounds[] = {32, 64, 128};
+    const uint32_t wgs[] = {1, 4};
+    const uint32_t parts_v1[] = {1, 2, 4};
+    const uint32_t parts_grp[] = {1};
+    const uint32_t *parts = is_v1(h) ? parts_v1 : parts_grp;
+    const int n_parts = is_v1(h) ? 3 : 1;
+    for (uint32_t K : rounds)
+        for (uint32_t W : wgs)
+            for (int pi = 0; pi < n_parts && !rc; ++pi)
+                for (int scale = 0; scale < 3 && !rc; ++scale) {
+                    if (scale == 1 && is_v1(h)) continue;     // V1: automatic and twice that
+                    ChunkCfg c;
+                    c.round = K;
+                    c.wg_waves = W;
+                    c.parts = parts[pi];
+                    c.chunk = 0;
+                    if (scale) {
+                        const uint64_t a = auto_chunk(h, lengths, c, jump_length(h));
+                        c.chunk = scale == 1 ? std::max<uint64_t>(64u, a / 2u / 64u * 64u) : std::min<uint64_t>(a * 2u, 1ull << 20);
+                    }
+                    std::vector<float> t;
+                    for (int r = 0; r < 4 && !rc; ++r) {
+                        if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
+                        if (!rc) rc = ragged_chunked(h, out, lengths, offsets, st, c, true);
+                        if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
+                        if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventSynchronize");
+                        float ms = 0.f;
+                        if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = set_error(CPRNG_E_HIP, "elapsed");
+                        if (r > 0) t.push_back(ms);
+                    }
+                    if (ChunkPlan *p = find_chunk_plan(h, out, lengths, offsets, c)) drop_chunk_plan(h, p);
+                    if (rc) break;
+                    std::sort(t.begin(), t.end());
+                    if (t[t.size() / 2] < best) {
+                        best = t[t.size() / 2];
+                        best_c = c;
+                        best_auto = c.chunk == 0;
+                    }
+                }
+    h->timing = saved_timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    TuneEntry e;
+    e.chunk = best_auto ? 0u : (uint32_t)best_c.chunk;
+    e.unroll = best_c.round;
+    e.block = best_c.wg_waves == 1 ? 64u : 256u;
+    e.slots = best_c.parts;
+    tune_cache_store(tune_key_ragged(h, total, max_len), e);
+    return CPRNG_OK;
+}
+
+void destroy_group_buffers(cprng_t *h)
+{
+    for (ChunkPlan *p : h->chunk_plans) free_chunk_plan(p);
+    h->chunk_plans.clear();
+    if (h->chunk_direct) {
+        h->chunk_direct->release_all();
+        delete h->chunk_direct;
+        h->chunk_direct = nullptr;
+    }
+    if (h->d_gj_next) (void)hipFree(h->d_gj_next);
+    h->d_gj_next = nullptr;
+    h->gj_next_cap = 0;
 }
 
 }  // namespace cprng_impl
@@ -791,24 +1150,3 @@ extern "C" int cprng_jump_selftest(uint32_t variant, uint32_t C, const uint32_t 
     }
     return set_error(CPRNG_E_INVAL, "the jump self-test covers V1, V2 and V4");
 }
-
-namespace cprng_impl {
-void destroy_group_buffers(cprng_t *h)
-{
-    if (h->d_v1_items) (void)hipFree(h->d_v1_items);
-    if (h->d_v1_agg) (void)hipFree(h->d_v1_agg);
-    if (h->d_v1_order) (void)hipFree(h->d_v1_order);
-    h->d_v1_items = nullptr;
-    h->d_v1_agg = nullptr;
-    h->d_v1_order = nullptr;
-    if (h->d_gj_next) (void)hipFree(h->d_gj_next);
-    if (h->d_gj_items) (void)hipFree(h->d_gj_items);
-    if (h->d_gj_rows) (void)hipFree(h->d_gj_rows);
-    if (h->d_gj_offsets) (void)hipFree(h->d_gj_offsets);
-    h->d_gj_next = nullptr;
-    h->d_gj_items = nullptr;
-    h->d_gj_rows = nullptr;
-    h->d_gj_offsets = nullptr;
-}
-
-}  // namespace cprng_impl

@@ -51,8 +51,17 @@ void jump_table(uint32_t chunk, uint32_t kcap, std::vector<uint32_t> &out);
 // table on the device without rebuilding it (segments.cpp).
 int prepare_request_tables(cprng_t *h, uint64_t max_len);
 
-// ---- ragged / request plans (segments.cpp) --------------------------------
+// ---- ragged / request plans (segments.cpp, groupjump.cpp) -----------------
 struct RaggedPlan;
+struct ChunkPlan;
+struct ChunkBufs;
+// Launch configuration of the chunk kernels of batched V1/V2/V4 calls.
+struct ChunkCfg {
+    uint64_t chunk = 0;       // outputs per chunk, a multiple of 64; 0 = automatic
+    uint32_t round = 64;      // words per lane per store round: 32, 64 or 128
+    uint32_t wg_waves = 4;    // waves per workgroup: 1 or 4
+    uint32_t parts = 2;       // V1 aggregate pass: lanes per chunk (1, 2 or 4)
+};
 void destroy_plans(cprng_t *h);
 
 // One launch of the V0 chunk kernels over batched uneven streams, planned on
@@ -123,18 +132,10 @@ struct cprng {
     // group's one-step map and grow-only work buffers
     std::vector<uint64_t> gj_q;
     int gj_deg = 0;
-    uint32_t *d_gj_next = nullptr;
+    uint32_t *d_gj_next = nullptr;      // end states of batched V1/V2/V4 calls
     size_t gj_next_cap = 0;
-    cprng_impl::GroupItem *d_gj_items = nullptr;
-    size_t gj_items_cap = 0;
-    uint32_t *d_gj_rows = nullptr;
-    size_t gj_rows_cap = 0;
-    uint64_t *d_gj_offsets = nullptr;
-    size_t gj_offsets_cap = 0;
-    cprng_impl::V1Item *d_v1_items = nullptr;
-    size_t v1_items_cap = 0;
-    uint32_t *d_v1_agg = nullptr;
-    size_t v1_agg_cap = 0;
-    uint32_t *d_v1_order = nullptr;
-    size_t v1_order_cap = 0;
+    // batched V1/V2/V4 calls: cached plans with captured graphs, and the
+    // grow-only tables of one-off calls (request rounds)
+    std::vector<cprng_impl::ChunkPlan *> chunk_plans;
+    cprng_impl::ChunkBufs *chunk_direct = nullptr;
 };

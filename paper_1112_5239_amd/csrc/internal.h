@@ -95,8 +95,8 @@ struct GroupJumpArgs {
 };
 
 // One chunk of a V1 run: stream `stream` generates steps [start, start +
-// len); `row` selects the jump polynomials of J = start; items of a stream
-// are consecutive, its chunk 0 at index `first`.
+// len); `row` selects the jump polynomials of J = start (= row * chunk);
+// items of a stream are consecutive, its chunk 0 at index `first`.
 struct V1Item {
     uint32_t stream;
     uint32_t row;
@@ -115,14 +115,21 @@ struct V1ChunkArgs {
     uint32_t deg1, deg2, deg3;  // degrees of the three minimal polynomials
     uint32_t off2, off3;        // word offsets of the xor128 and xorwow polynomials in a row
     const uint32_t *rows;
-    uint32_t *agg;              // per chunk: xor of its strategy words
+    uint32_t *agg;              // per chunk: xor of its strategy words, then (after the
+                                // scan) the xor of those of the stream's earlier chunks
     uint32_t *out;
     const uint64_t *offsets;    // per stream
     uint64_t chunk;             // length of a full chunk
     uint32_t sum_row;           // row of sum_{i=1..chunk} X^i (xorshift and xor128 parts)
     uint32_t round;             // generating pass: words per lane per store round (32, 64, 128)
     uint32_t wg_waves;          // generating pass: waves per workgroup (1 or 4)
-    const uint32_t *order;      // aggregate pass: full chunks first, then the shorter last ones
+    const uint32_t *order;      // aggregate pass: the chunks that are not a stream's last
+    uint32_t n_agg;             // entries of order
+    uint32_t parts;             // aggregate pass: lanes per chunk (1, 2 or 4)
+    const uint32_t *sub_rows;   // xorwow polynomials X^(row * chunk + p * chunk / parts), row-major
+                                // by (row, p), w3 words each
+    uint32_t w3;                // 32-bit words per xorwow polynomial
+    const uint32_t *sfirst;     // per stream: index of its first chunk (n_streams + 1 entries)
 };
 
 struct LaunchCfg {

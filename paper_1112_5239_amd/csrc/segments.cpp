@@ -458,12 +458,51 @@ extern "C" int cprng_generate_ragged(cprng_t *h, uint32_t *out, const uint64_t *
     int rc = check_ragged_args(h, out, lengths, offsets, &total, &max_len);
     if (rc) return rc;
     DevGuard g(h->device);
-    if (h->variant == CPRNG_V1_NAIVE3) return ragged_v1(h, out, lengths, offsets, (hipStream_t)stream);
+    if (h->variant == CPRNG_V1_NAIVE3) return ragged_v1(h, out, lengths, offsets, (hipStream_t)stream, true);
     if (h->variant != CPRNG_V0_PLAIN) return ragged_groups(h, out, lengths, offsets, (hipStream_t)stream);
     rc = ensure_common(h);
     if (rc) return rc;
     const SegCfg c = resolve_seg_cfg(h, total, max_len);
     return ragged_with(h, out, lengths, offsets, (hipStream_t)stream, c);
+}
+
+extern "C" int cprng_resolved_tuning_ragged(cprng_t *h, const uint64_t *lengths, cprng_tuning_t *out, int *source)
+{
+    if (!h || !lengths || !out) return set_error(CPRNG_E_INVAL, "NULL argument");
+    if (h->variant == CPRNG_V3_BBS || (h->flags & CPRNG_F_INTERLEAVED))
+        return set_error(CPRNG_E_UNSUPPORTED, "no batched uneven form for this handle");
+    uint64_t total = 0, max_len = 0;
+    for (uint32_t s = 0; s < h->ns; ++s) {
+        total += lengths[s];
+        max_len = std::max(max_len, lengths[s]);
+    }
+    DevGuard g(h->device);
+    TuneEntry e;
+    const bool cached = tune_cache_lookup_key(tune_key_ragged(h, total, max_len), &e);
+    std::memset(out, 0, sizeof *out);
+    if (h->variant == CPRNG_V0_PLAIN) {
+        const SegCfg c = resolve_seg_cfg(h, total, max_len);
+        out->chunk = c.chunk;
+        out->unroll = c.unroll;
+        out->waves_per_cu = c.waves;
+        out->block = c.block;
+        out->store = c.store;
+    } else {
+        const ChunkCfg c = resolve_chunk_cfg(h, total, max_len);
+        uint64_t chunk = 0;
+        const int rc = chunk_for(h, lengths, c, &chunk);
+        if (rc) return rc;
+        out->chunk = (uint32_t)std::min<uint64_t>(chunk, 0xFFFFFFFFull);
+        out->unroll = c.round;
+        out->block = 64u * c.wg_waves;
+        out->streams_per_lane = h->variant == CPRNG_V1_NAIVE3 ? c.parts : 0u;
+    }
+    if (source) {
+        const cprng_tuning_t &t = h->tuning;
+        *source = (t.block || t.unroll || t.store || t.chunk || t.waves_per_cu || t.streams_per_lane || t.exchange)
+                      ? 2 : cached ? 1 : 0;
+    }
+    return CPRNG_OK;
 }
 
 extern "C" int cprng_autotune_ragged(cprng_t *h, uint32_t *out, const uint64_t *lengths,
@@ -472,12 +511,17 @@ extern "C" int cprng_autotune_ragged(cprng_t *h, uint32_t *out, const uint64_t *
     uint64_t total = 0, max_len = 0;
     int rc = check_ragged_args(h, out, lengths, offsets, &total, &max_len);
     if (rc) return rc;
-    if (h->variant != CPRNG_V0_PLAIN)
-        return set_error(CPRNG_E_UNSUPPORTED, "the ragged autotuner covers the V0 kernels only");
     DevGuard g(h->device);
+    hipStream_t st = (hipStream_t)stream;
+    StateBackup backup;
+    if ((rc = backup.save(h, st))) return rc;
+    if (h->variant != CPRNG_V0_PLAIN) {
+        rc = autotune_chunked(h, out, lengths, offsets, st, total, max_len);
+        const int rrc = backup.restore(h, st);
+        return rc ? rc : rrc;
+    }
     rc = ensure_common(h);
     if (rc) return rc;
-    hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return set_error(CPRNG_E_HIP, "hipEventCreate");
@@ -521,7 +565,9 @@ extern "C" int cprng_autotune_ragged(cprng_t *h, uint32_t *out, const uint64_t *
     h->timing = saved_timing;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    const int rrc = backup.restore(h, st);
     if (rc) return rc;
+    if (rrc) return rrc;
     TuneEntry e;
     e.block = best_c.block;
     e.unroll = best_c.unroll;
@@ -639,7 +685,7 @@ extern "C" int cprng_generate_requests(cprng_t *h, const cprng_request_t *reqs, 
                 lengths[q->stream] = q->length;
                 offs[q->stream] = ((uintptr_t)q->out - lo) / 4u;
             }
-            const int rc = ragged_v1(h, (uint32_t *)lo, lengths.data(), offs.data(), (hipStream_t)stream);
+            const int rc = ragged_v1(h, (uint32_t *)lo, lengths.data(), offs.data(), (hipStream_t)stream, false);
             if (rc) return rc;
         }
         return CPRNG_OK;

@@ -291,8 +291,27 @@ int cprng_server_stats(const cprng_server_t *s, uint64_t *waiting, uint64_t *in_
     return CPRNG_OK;
 }
 
+static int replay_impl(cprng_server_t *s, const uint64_t *arrival_ns, const uint32_t *client,
+                       const uint64_t *length, uint32_t count, int release_results, const uint8_t *keep,
+                       cprng_completion_t *results);
+
 int cprng_server_replay(cprng_server_t *s, const uint64_t *arrival_ns, const uint32_t *client,
                         const uint64_t *length, uint32_t count, int release_results, cprng_completion_t *results)
+{
+    return replay_impl(s, arrival_ns, client, length, count, release_results, nullptr, results);
+}
+
+int cprng_server_replay_keep(cprng_server_t *s, const uint64_t *arrival_ns, const uint32_t *client,
+                             const uint64_t *length, uint32_t count, const uint8_t *keep,
+                             cprng_completion_t *results)
+{
+    if (count && !keep) return set_error(CPRNG_E_INVAL, "NULL keep mask");
+    return replay_impl(s, arrival_ns, client, length, count, 1, keep, results);
+}
+
+static int replay_impl(cprng_server_t *s, const uint64_t *arrival_ns, const uint32_t *client,
+                       const uint64_t *length, uint32_t count, int release_results, const uint8_t *keep,
+                       cprng_completion_t *results)
 {
     if (!s || (count && (!arrival_ns || !client || !length || !results)))
         return set_error(CPRNG_E_INVAL, "NULL argument");
@@ -320,7 +339,7 @@ int cprng_server_replay(cprng_server_t *s, const uint64_t *arrival_ns, const uin
             const cprng_completion_t &c = buf[k];
             results[c.tag] = c;
             ++finished;
-            if (release_results) (void)cprng_server_release(s, c.out);
+            if (release_results && !(keep && keep[c.tag])) (void)cprng_server_release(s, c.out);
         }
         if (rc) return rc;
         if (n) progress = true;

@@ -147,16 +147,18 @@ uint32_t lds_for_waves(uint32_t block, uint32_t waves_per_cu)
 std::string tune_key_generate(const cprng_t *h, uint64_t n)
 {
     char buf[160];
-    std::snprintf(buf, sizeof buf, "%s/gen/v%u%s/ns2^%d/n2^%d", arch_name(h->device).c_str(), h->variant,
-                  (h->flags & CPRNG_F_V1_W32) ? "w32" : "", log2_bucket(h->ns), log2_bucket(n));
+    std::snprintf(buf, sizeof buf, "%s/gen/v%u%s%s%s/ns2^%d/n2^%d", arch_name(h->device).c_str(), h->variant,
+                  (h->flags & CPRNG_F_V1_W32) ? "w32" : "", (h->flags & CPRNG_F_V1_XOR64) ? "x64" : "",
+                  (h->flags & CPRNG_F_INTERLEAVED) ? "/ilv" : "", log2_bucket(h->ns), log2_bucket(n));
     return buf;
 }
 
 std::string tune_key_ragged(const cprng_t *h, uint64_t total, uint64_t max_len)
 {
     char buf[160];
-    std::snprintf(buf, sizeof buf, "%s/ragged/v%u/ns2^%d/total2^%d/max2^%d", arch_name(h->device).c_str(),
-                  h->variant, log2_bucket(h->ns), log2_bucket(total), log2_bucket(max_len));
+    std::snprintf(buf, sizeof buf, "%s/ragged/v%u%s%s/ns2^%d/total2^%d/max2^%d", arch_name(h->device).c_str(),
+                  h->variant, (h->flags & CPRNG_F_V1_W32) ? "w32" : "", (h->flags & CPRNG_F_V1_XOR64) ? "x64" : "",
+                  log2_bucket(h->ns), log2_bucket(total), log2_bucket(max_len));
     return buf;
 }
 
@@ -189,71 +191,161 @@ void tune_cache_store(const std::string &key, const TuneEntry &e)
     save_file_locked();
 }
 
+int StateBackup::save(const cprng_t *h, hipStream_t st)
+{
+    words = (size_t)h->ns * h->words;
+    if (hipMalloc(&d, words * sizeof(uint32_t)) != hipSuccess) {
+        d = nullptr;
+        return set_error(CPRNG_E_NOMEM, "hipMalloc of the state backup failed");
+    }
+    if (hipMemcpyAsync(d, h->d_state, words * sizeof(uint32_t), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return set_error(CPRNG_E_HIP, "state backup copy");
+    return CPRNG_OK;
+}
+
+int StateBackup::restore(cprng_t *h, hipStream_t st)
+{
+    if (!d) return CPRNG_OK;
+    if (hipMemcpyAsync(h->d_state, d, words * sizeof(uint32_t), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return set_error(CPRNG_E_HIP, "state restore copy");
+    return CPRNG_OK;
+}
+
+StateBackup::~StateBackup()
+{
+    if (d) (void)hipFree(d);
+}
+
 }  // namespace cprng_impl
 
 using namespace cprng_impl;
 
-extern "C" int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n, cprng_stream_t stream)
+namespace {
+
+// Median device time of a few runs of one candidate (the first is a warm-up).
+int time_candidate(cprng_t *h, uint32_t *scratch, uint64_t n, hipStream_t st, const LaunchCfg &c,
+                   hipEvent_t e0, hipEvent_t e1, float *med)
 {
-    if (!h || !scratch || n == 0) return set_error(CPRNG_E_INVAL, "NULL handle/scratch or n == 0");
-    if (h->flags & CPRNG_F_INTERLEAVED) return set_error(CPRNG_E_UNSUPPORTED, "autotune covers the stream-major layout");
-    if ((uintptr_t)scratch % 16u || n % 4u)
-        return set_error(CPRNG_E_INVAL, "autotune needs a 16-byte aligned buffer and n % 4 == 0");
-    hipStream_t st = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return set_error(CPRNG_E_HIP, "hipEventCreate");
+    std::vector<float> t;
+    int rc = CPRNG_OK;
+    for (int r = 0; r < 4 && rc == CPRNG_OK; ++r) {
+        if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
+        if (rc == CPRNG_OK) rc = generate_with(h, scratch, n, st, c);
+        if (rc == CPRNG_OK && hipEventRecord(e1, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
+        if (rc == CPRNG_OK && hipEventSynchronize(e1) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventSynchronize");
+        float ms = 0.f;
+        if (rc == CPRNG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = set_error(CPRNG_E_HIP, "elapsed");
+        if (r > 0) t.push_back(ms);
+    }
+    if (rc) return rc;
+    std::sort(t.begin(), t.end());
+    *med = t[t.size() / 2];
+    return CPRNG_OK;
+}
+
+// Candidates of the interleaved layout: LDS tiles of block streams x unroll
+// steps (one or two tile buffers, cross-lane or LDS-buffer exchange, one
+// workgroup per tile or persistent workgroups per CU) and, for V0/V2/V4, the
+// four-streams-per-lane kernel.
+void interleaved_candidates(const cprng_t *h, std::vector<std::pair<LaunchCfg, TuneEntry>> &out)
+{
+    const bool xch = has_exchange(h->variant);
+    for (uint32_t st : {(uint32_t)ST_ILV_TILE, (uint32_t)ST_ILV_TILE_NT})
+        for (uint32_t b : {256u, 512u, 1024u})
+            for (uint32_t u : {8u, 16u, 32u})
+                for (uint32_t db : {1u, 2u})
+                    for (uint32_t xm : {(uint32_t)XCH_BPERM, (uint32_t)XCH_LDS}) {
+                        if (!xch && xm != XCH_BPERM) continue;
+                        const uint32_t extra = (xch && xm == XCH_LDS) ? 1u : 0u;
+                        if ((uint64_t)(db * u + extra) * b * 4u > kMaxLdsBytes) continue;
+                        for (uint32_t w : {0u, 1u, 2u}) {
+                            LaunchCfg c{b, u, st, 0, db, xm, h->n_cu * w};
+                            TuneEntry e;
+                            e.block = b; e.unroll = u; e.store = st; e.slots = db; e.exchange = xm; e.waves = w;
+                            out.emplace_back(c, e);
+                        }
+                    }
+    if (h->variant == CPRNG_V0_PLAIN || h->variant == CPRNG_V2_SHMEM || h->variant == CPRNG_V4_XOR64)
+        for (uint32_t st : {(uint32_t)ST_ILV_QUAD, (uint32_t)ST_ILV_QUAD_NT})
+            for (uint32_t b : {64u, 128u, 256u}) {
+                LaunchCfg c{b, 16, st, 0, 1, XCH_LDS, 0};
+                TuneEntry e;
+                e.block = b; e.unroll = 16; e.store = st; e.slots = 1; e.exchange = XCH_LDS; e.waves = 0;
+                out.emplace_back(c, e);
+            }
+}
+
+// Candidates of the stream-major layout: per-lane stores (K <= 32) and LDS
+// tiles of several widths, streams per lane, residency caps and exchanges.
+void stream_major_candidates(const cprng_t *h, std::vector<std::pair<LaunchCfg, TuneEntry>> &out)
+{
     const uint32_t blocks[] = {64, 128, 256};
     const uint32_t unrolls[] = {8, 16, 32, 64, 128, 256};
     const uint32_t stores[] = {ST_DIRECT, ST_LDS, ST_LDS_NT};
     const uint32_t caps[] = {0, 4, 8};
     const uint32_t slot_opts[] = {1, 2, 4};
     const uint32_t xch_opts[] = {XCH_BPERM, XCH_LDS, XCH_DPP};
-    float best = 1e30f;
-    TuneEntry best_e;
-    const bool saved_timing = h->timing;
-    h->timing = false;
-    int rc = CPRNG_OK;
     for (uint32_t b : blocks)
         for (uint32_t u : unrolls)
             for (uint32_t s : stores)
                 for (uint32_t w : caps)
-                for (uint32_t sl : slot_opts)
-                for (uint32_t xm : xch_opts) {
-                const bool lds_mode = s == ST_LDS || s == ST_LDS_NT;
-                if (!lds_mode && (u > 32 || w || sl > 1 || xm != XCH_BPERM)) continue;   // direct: K <= 32
-                if (!has_exchange(h->variant) && xm != XCH_BPERM) continue;
-                if (xm == XCH_DPP && !dpp_pattern(h)) continue;
-                if (lds_mode && u < 16) continue;
-                if (lds_mode && (size_t)b * sl * (u + (xm == XCH_LDS ? 1 : 0)) * 4 > kMaxLdsBytes) continue;
-                LaunchCfg c{b, u, s, lds_for_waves(b, w), sl, xm};
-                std::vector<float> t;
-                for (int r = 0; r < 4 && rc == CPRNG_OK; ++r) {
-                    if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
-                    if (rc == CPRNG_OK) rc = generate_with(h, scratch, n, st, c);
-                    if (rc == CPRNG_OK && hipEventRecord(e1, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
-                    if (rc == CPRNG_OK && hipEventSynchronize(e1) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventSynchronize");
-                    float ms = 0.f;
-                    if (rc == CPRNG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = set_error(CPRNG_E_HIP, "elapsed");
-                    if (r > 0) t.push_back(ms);
-                }
-                if (rc != CPRNG_OK) break;
-                std::sort(t.begin(), t.end());
-                const float med = t[t.size() / 2];
-                if (med < best) {
-                    best = med;
-                    best_e.block = b;
-                    best_e.unroll = u;
-                    best_e.store = s;
-                    best_e.waves = w;
-                    best_e.slots = sl;
-                    best_e.exchange = xm;
-                }
-            }
+                    for (uint32_t sl : slot_opts)
+                        for (uint32_t xm : xch_opts) {
+                            const bool lds_mode = s == ST_LDS || s == ST_LDS_NT;
+                            if (!lds_mode && (u > 32 || w || sl > 1 || xm != XCH_BPERM)) continue;
+                            if (!has_exchange(h->variant) && xm != XCH_BPERM) continue;
+                            if (xm == XCH_DPP && !dpp_pattern(h)) continue;
+                            if (lds_mode && u < 16) continue;
+                            if (lds_mode && (size_t)b * sl * (u + (xm == XCH_LDS ? 1 : 0)) * 4 > kMaxLdsBytes) continue;
+                            LaunchCfg c{b, u, s, lds_for_waves(b, w), sl, xm, 0};
+                            TuneEntry e;
+                            e.block = b; e.unroll = u; e.store = s; e.waves = w; e.slots = sl; e.exchange = xm;
+                            out.emplace_back(c, e);
+                        }
+}
+
+}  // namespace
+
+extern "C" int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n, cprng_stream_t stream)
+{
+    if (!h || !scratch || n == 0) return set_error(CPRNG_E_INVAL, "NULL handle/scratch or n == 0");
+    const bool ilv = (h->flags & CPRNG_F_INTERLEAVED) != 0;
+    if ((uintptr_t)scratch % 16u || (!ilv && n % 4u) || (ilv && h->ns % 4u))
+        return set_error(CPRNG_E_INVAL, "autotune needs a 16-byte aligned buffer and n % 4 == 0 "
+                                        "(interleaved: n_streams % 4 == 0)");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<std::pair<LaunchCfg, TuneEntry>> cands;
+    if (ilv)
+        interleaved_candidates(h, cands);
+    else
+        stream_major_candidates(h, cands);
+    StateBackup backup;
+    int rc = backup.save(h, st);
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return set_error(CPRNG_E_HIP, "hipEventCreate");
+    float best = 1e30f;
+    TuneEntry best_e;
+    const bool saved_timing = h->timing;
+    h->timing = false;
+    for (const auto &ce : cands) {
+        float med = 0.f;
+        rc = time_candidate(h, scratch, n, st, ce.first, e0, e1, &med);
+        if (rc) break;
+        if (med < best) {
+            best = med;
+            best_e = ce.second;
+        }
+    }
     h->timing = saved_timing;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (rc != CPRNG_OK) return rc;
+    const int rrc = backup.restore(h, st);
+    if (rc) return rc;
+    if (rrc) return rrc;
     tune_cache_store(tune_key_generate(h, n), best_e);
     return CPRNG_OK;
 }

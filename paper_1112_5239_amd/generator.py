@@ -138,6 +138,14 @@ class Generator:
             offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
         L.cprng_autotune_ragged(self.h, out, lengths, offsets, _stream(stream))
 
+    def resolved_tuning(self, n: int) -> dict:
+        """Launch configuration the next generate(n) uses, and its source."""
+        return L.cprng_resolved_tuning(self.h, n)
+
+    def resolved_tuning_ragged(self, lengths) -> dict:
+        lengths = np.ascontiguousarray(lengths, dtype=np.uint64)
+        return L.cprng_resolved_tuning_ragged(self.h, lengths)
+
     def enable_timing(self, on: bool = True):
         L.cprng_enable_timing(self.h, on)
 

@@ -111,7 +111,10 @@ def _stream_sample(lengths, frac, seed):
                                      [int(np.argmax(lengths)), int(np.argmin(lengths)), 0, ns - 1]]))
 
 
-def test_batched_v1_full_workload_auto_chunk(orc, G, torch):
+@pytest.mark.parametrize("tuned", [False, True])
+def test_batched_v1_full_workload_auto_chunk(orc, G, torch, tuned):
+    # default configuration, then the configuration the autotuner picks on
+    # this workload (what bench.py's batched leg times)
     from paper_1112_5239_amd import workloads
     lengths = workloads.ragged_lengths()
     ns = lengths.size
@@ -121,6 +124,9 @@ def test_batched_v1_full_workload_auto_chunk(orc, G, torch):
     g = G.Generator(ns, "v1", seed=2)
     try:
         out = torch.empty(total, dtype=torch.int32, device="cuda")
+        if tuned:
+            g.autotune_ragged(lengths, out=out)
+            assert g.resolved_tuning_ragged(lengths)["source"] == "autotuned"
         pick = _stream_sample(lengths, 0.01, 101)
         st = orc.seed(1, 2, 0, ns)
         for call in range(2):
@@ -140,7 +146,8 @@ def test_batched_v1_full_workload_auto_chunk(orc, G, torch):
         g.close()
 
 
-def test_batched_v2_groups_full_workload_auto_chunk(orc, G, torch):
+@pytest.mark.parametrize("tuned", [False, True])
+def test_batched_v2_groups_full_workload_auto_chunk(orc, G, torch, tuned):
     from paper_1112_5239_amd import workloads
     lengths = workloads.ragged_group_lengths()
     ns, Cg = lengths.size, 32
@@ -151,6 +158,9 @@ def test_batched_v2_groups_full_workload_auto_chunk(orc, G, torch):
     g = G.Generator(ns, "v2", seed=2)
     try:
         out = torch.empty(total, dtype=torch.int32, device="cuda")
+        if tuned:
+            g.autotune_ragged(lengths, out=out)
+            assert g.resolved_tuning_ragged(lengths)["source"] == "autotuned"
         groups = np.unique(np.concatenate([workloads.parity_sample(gl.size, 0.01, 102),
                                            [int(np.argmax(gl)), int(np.argmin(gl))]]))
         st = orc.seed(2, 2, 0, ns)

@@ -207,3 +207,27 @@ def test_serving_workload_short_sampled(orc, torch, mods):
     finally:
         srv.close()
         gen.close()
+
+
+def test_serving_trace_seconds_checked(orc, torch, mods):
+    # The benchmark's serving leg (serving.run_trace) on 3 s of its trace,
+    # with every result of 20 sampled clients kept and compared with the
+    # oracle generating each of those clients' streams alone; every other
+    # result is released as it completes.
+    G, S, W = mods
+    st = orc.seed(0, 4, 0, 10000)
+    seen = []
+
+    def check(c, results):
+        total = sum(r.size for r in results)
+        want, _ = orc.generate(0, st[c:c + 1].copy(), total)
+        pos = 0
+        for k, r in enumerate(results):
+            assert np.array_equal(r, want[0, pos:pos + r.size]), f"client {c} request {k}"
+            pos += r.size
+        seen.append(c)
+
+    summary = S.run_trace(3.0, check_clients=20, oracle_check=check)
+    assert summary["statuses"] == [0]
+    assert summary["clients_checked"] == len(seen) == 20
+    assert summary["latency_ms"]["p50"] > 0

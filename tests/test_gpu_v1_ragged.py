@@ -33,11 +33,11 @@ def _lengths(ns, seed, cap):
     return rng.permutation(np.concatenate([base, extra]))
 
 
-def _run(orc, G, kw, ov, W, ns, lengths, sigma, chunk, offsets=None, calls=2, rnd=0, blk=0):
+def _run(orc, G, kw, ov, W, ns, lengths, sigma, chunk, offsets=None, calls=2, rnd=0, blk=0, parts=0):
     g = G.Generator(ns, "v1", seed=sigma, **kw)
     try:
-        if chunk or rnd or blk:
-            g.set_tuning(chunk=chunk, unroll=rnd, block=blk)
+        if chunk or rnd or blk or parts:
+            g.set_tuning(chunk=chunk, unroll=rnd, block=blk, streams_per_lane=parts)
         st = orc.seed(ov, sigma, 0, ns, W=W)
         offs = offsets if offsets is not None else np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.uint64)
         for _ in range(calls):
@@ -77,6 +77,19 @@ def test_v1_ragged_store_rounds(orc, G, rnd, blk):
         offs[s] = pos
         pos += int(lengths[s]) + 3
     _run(orc, G, {}, 1, 64, 96, lengths, sigma=93, chunk=448, offsets=offs, rnd=rnd, blk=blk)
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("parts", [1, 2, 4])
+@pytest.mark.parametrize("chunk", [64, 320, 0])
+def test_v1_ragged_aggregate_lanes(orc, G, case, parts, chunk):
+    # lanes per chunk of the aggregate pass (each steps xorwow through its own
+    # share of the chunk from its own jump), including shares of 16 and 80 steps
+    kw, ov, W = CASES[case]
+    if ov is None:
+        ov = 1 | orc.F_XOR64
+    lengths = _lengths(72, 94, 30000 if chunk == 0 else 3000)
+    _run(orc, G, kw, ov, W, 72, lengths, sigma=94, chunk=chunk, parts=parts)
 
 
 def test_v1_ragged_offsets_and_a_long_run(orc, G):
