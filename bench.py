@@ -9,15 +9,22 @@ number of threads), states seeded from SplitMix64 with seed 1 and already
 resident on the device.  Prints ONE JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extra] [--no-cpu-baseline]
+                    [--no-autotune] [--serving-duration S]
     python bench.py --workload serving [--duration 60]
     python bench.py --workload ragged|ragged_v1|ragged_groups|consume   (one leg alone, for profiling)
 
-Secondary measurements (same JSON line, "extra"): the same workload in the
-stream-major layout out[s * 1024 + i], the plain variants V0 and V1 in both
-layouts, batched uneven streams (4,096 streams, log-uniform lengths in
-[1e3, 1e7], one hipGraph launch), in-kernel consumption (2^36 numbers) against
-its instruction-mix ALU roofline, the VALU issue-rate probes and the store-only
-fill probe.
+Order of the default run: the headline's W + K launches right after idle
+(per-launch times in extra.cold_start: the shader clock settles over the
+first tens of milliseconds of activity); the serving trace (Poisson 2,000
+req/s, 60 s by default); the small plain configuration (1,024 x 1,024, V0 and
+V1); the same workload in the stream-major layout out[s * 1024 + i]; the
+plain variants V0, V1, V3, V4 in both layouts; batched uneven runs of V0, V1
+and V2 groups (each autotuned first, then one hipGraph launch per call);
+in-kernel consumption (2^36 numbers) against its instruction-mix ALU
+roofline; the VALU issue-rate probes and the store-only fill probe; then the
+headline: W untimed and K timed steps (and each launch's duration); then the
+autotuner on the headline workload (reported beside it, not used for it) and
+the CPU oracle baselines.
 """
 import argparse
 import hashlib
@@ -54,6 +61,10 @@ ALU_MIX = {
     "v3_consume": (2281 / 16, 449 / 16),    # k_consume<3, u32, 16>
 }
 
+# kernels whose loop bodies are integer-only (no f32 instruction to pair with)
+INTEGER_ONLY = {"v1_generate"}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -87,6 +98,17 @@ def traffic_from_profile(kernel_tag):
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def per_launch(torch, fn, count):
+    """Device time of each of `count` back-to-back launches (events around each)."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(count)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in ev]
 
 
 def timed(torch, fn, steps, warmup):
@@ -131,7 +153,9 @@ def cpu_baseline_all_cores(budget_s=8.0):
     exchange groups (ctypes releases the GIL inside the oracle's C code)."""
     import concurrent.futures as cf
     from oracle import oracle as O
-    threads = max(1, min(os.cpu_count() or 1, 16))
+    # the host cores this process may use, at most the 16 a GPU's jobs get on
+    # a shared host
+    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
     comb = O.comb_tables(32)
     batch = 2048
     O.generate(2, O.seed(2, 1, 0, 32), 16, comb=comb)
@@ -149,6 +173,7 @@ def cpu_baseline_all_cores(budget_s=8.0):
         done = sum(ex.map(work, range(threads)))
     wall = time.perf_counter() - t0
     return {"value": done * 1024 / wall / 1e9, "unit": "Gnumbers/s", "cores": threads, "kind": "oracle",
+            "host_cores": os.cpu_count(), "affinity_cores": len(os.sched_getaffinity(0)),
             "sample": f"{done} of the 2^20 streams x 1024 outputs (exchange variant, seed 1), "
                       f"{threads} threads, {wall:.1f} s wall"}
 
@@ -174,9 +199,16 @@ def alu_roofline(gn, key):
     """ALU roofline (Gnumbers/s) of a kernel from its per-number VALU mix."""
     n, single = ALU_MIX[key]
     peak = CU * CLOCK_HZ * 64 / max(n / 2, single) / 1e9
-    return {"bound": "alu", "achieved": round(gn, 1), "peak": round(peak, 1), "unit": "Gnumbers/s",
-            "frac": round(gn / peak, 4), "valu_per_number": round(n, 3),
-            "single_rate_per_number": round(single, 3)}
+    res = {"bound": "alu", "achieved": round(gn, 1), "peak": round(peak, 1), "unit": "Gnumbers/s",
+           "frac": round(gn / peak, 4), "valu_per_number": round(n, 3),
+           "single_rate_per_number": round(single, 3)}
+    if key in INTEGER_ONLY:
+        # integer-only mixes holding single-rate shifts issue about one
+        # wave64 instruction per CU-clock in total (measured on gfx950)
+        peak1 = CU * CLOCK_HZ * 64 / n / 1e9
+        res["peak_integer_mix"] = round(peak1, 1)
+        res["frac_integer_mix"] = round(gn / peak1, 4)
+    return res
 
 
 def run_plain(torch, G, variant, args, interleaved=False):
@@ -196,6 +228,15 @@ def run_plain(torch, G, variant, args, interleaved=False):
             "frac_hbm_peak": round(byts / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def _tune_ragged(g, lengths, out, args):
+    """Run the batched-launch autotuner unless disabled; returns its record."""
+    t0 = time.perf_counter()
+    if not args.no_autotune:
+        g.autotune_ragged(lengths, out=out)
+    cfg = g.resolved_tuning_ragged(lengths)
+    return {"tuned": not args.no_autotune, "tune_s": round(time.perf_counter() - t0, 2), "config": cfg}
+
+
 def run_ragged(torch, G, args, ref_v0_gn):
     """Ratio is against plain V0 in the same (stream-major) layout."""
     from paper_1112_5239_amd import workloads
@@ -204,8 +245,7 @@ def run_ragged(torch, G, args, ref_v0_gn):
     total = int(lengths.sum())
     g = G.Generator(ns, "v0", seed=2)
     out = torch.empty(total, dtype=torch.int32, device="cuda")
-    if args.autotune:
-        g.autotune_ragged(lengths, out=out)
+    tune = _tune_ragged(g, lengths, out, args)
     ms, _ = timed(torch, lambda: g.generate_ragged(lengths, out=out), max(5, args.steps // 4), 10)
     g.close()
     del out
@@ -214,44 +254,98 @@ def run_ragged(torch, G, args, ref_v0_gn):
                         "one hipGraph launch", "ms": round(ms, 4), "gnumbers_per_s": round(gn, 2),
             "hbm_gbs": round(total * 4 / (ms / 1e3) / 1e9, 1),
             "frac_hbm_peak": round(total * 4 / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-            "ratio_to_plain_v0": round(gn / ref_v0_gn, 4) if ref_v0_gn else None}
+            "ratio_to_plain_v0": round(gn / ref_v0_gn, 4) if ref_v0_gn else None, **tune}
 
 
 def run_ragged_groups(torch, G, args, ref_gn):
     """Batched uneven runs of the exchange variant: 128 groups of 32 streams,
-    group lengths log-uniform in [1e3, 1e7] (equal within a group), seed 2;
-    ratio against plain V2 in the stream-major layout."""
+    group lengths log-uniform in [1e3, 1e7] (equal within a group), seed 2,
+    one hipGraph launch; ratio against plain V2 in the stream-major layout."""
     from paper_1112_5239_amd import workloads
     lengths = workloads.ragged_group_lengths()
     total = int(lengths.sum())
     g = G.Generator(lengths.size, "v2", seed=2)
     out = torch.empty(total, dtype=torch.int32, device="cuda")
-    ms, _ = timed(torch, lambda: g.generate_ragged(lengths, out=out), max(5, args.steps // 10), 3)
+    tune = _tune_ragged(g, lengths, out, args)
+    ms, _ = timed(torch, lambda: g.generate_ragged(lengths, out=out), max(5, args.steps // 4), 3)
     g.close()
     del out
     gn = total / (ms / 1e3) / 1e9
     return {"workload": f"V2, 128 groups x 32 streams, group lengths log-uniform [1e3,1e7] (total {total}), "
-                        "seed 2", "ms": round(ms, 4), "gnumbers_per_s": round(gn, 2),
+                        "seed 2, one hipGraph launch", "ms": round(ms, 4), "gnumbers_per_s": round(gn, 2),
             "hbm_gbs": round(total * 4 / (ms / 1e3) / 1e9, 1),
-            "ratio_to_plain_v2_stream_major": round(gn / ref_gn, 4) if ref_gn else None}
+            "frac_hbm_peak": round(total * 4 / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "ratio_to_plain_v2_stream_major": round(gn / ref_gn, 4) if ref_gn else None, **tune}
 
 
 def run_ragged_v1(torch, G, args, ref_gn):
     """Batched uneven runs of V1 on the batched workload's lengths (4,096
-    streams, log-uniform [1e3, 1e7], seed 2); ratio against plain V1 in the
-    stream-major layout."""
+    streams, log-uniform [1e3, 1e7], seed 2), one hipGraph launch; ratio
+    against plain V1 in the stream-major layout."""
     from paper_1112_5239_amd import workloads
     lengths = workloads.ragged_lengths()
     total = int(lengths.sum())
     g = G.Generator(lengths.size, "v1", seed=2)
     out = torch.empty(total, dtype=torch.int32, device="cuda")
-    ms, _ = timed(torch, lambda: g.generate_ragged(lengths, out=out), max(3, args.steps // 20), 2)
+    tune = _tune_ragged(g, lengths, out, args)
+    ms, _ = timed(torch, lambda: g.generate_ragged(lengths, out=out), max(5, args.steps // 4), 3)
     g.close()
     del out
     gn = total / (ms / 1e3) / 1e9
-    return {"workload": f"V1, 4096 streams, log-uniform lengths [1e3,1e7] (total {total}), seed 2",
-            "ms": round(ms, 4), "gnumbers_per_s": round(gn, 2),
-            "ratio_to_plain_v1_stream_major": round(gn / ref_gn, 4) if ref_gn else None}
+    return {"workload": f"V1, 4096 streams, log-uniform lengths [1e3,1e7] (total {total}), seed 2, "
+                        "one hipGraph launch", "ms": round(ms, 4), "gnumbers_per_s": round(gn, 2),
+            "ratio_to_plain_v1_stream_major": round(gn / ref_gn, 4) if ref_gn else None, **tune}
+
+
+def run_small(torch, G, args):
+    """The small plain configuration: 1,024 streams x 1,024 outputs (4 MiB),
+    seed 0, V0 and V1, stream-major: a launch-bound size (16 waves)."""
+    res = {"workload": "1024 streams x 1024 uint32 (4 MiB), seed 0, stream-major"}
+    for variant in ("v0", "v1"):
+        g = G.Generator(1024, variant, seed=0)
+        out = torch.empty((1024, 1024), dtype=torch.int32, device="cuda")
+        ms, _ = timed(torch, lambda: g.generate(1024, out=out), 200, 20)
+        g.close()
+        res[variant] = {"ms": round(ms, 5), "gnumbers_per_s": round((1 << 20) / (ms / 1e3) / 1e9, 2),
+                        "frac_hbm_peak": round((1 << 22) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return res
+
+
+def run_serving(args):
+    from paper_1112_5239_amd import serving
+    summary = serving.run_trace(args.serving_duration)
+    return {"workload": f"Poisson 2000 req/s for {args.serving_duration:g} s, sizes log-uniform 1 KiB..256 MiB "
+                        "of uint32, 10000 resident client streams (V0, seed 4), 64 GiB result budget, "
+                        "2 HIP streams; results released as they complete", **summary}
+
+
+def run_headline_autotuned(torch, G, args, default_ms):
+    """The autotuner on the headline workload (interleaved candidates); the
+    headline itself is timed on the default configuration before this runs."""
+    ns, n = 1 << 20, 1024
+    g = G.Generator(ns, "v2", seed=1, interleaved=True)
+    out = torch.empty((n, ns), dtype=torch.int32, device="cuda")
+    t0 = time.perf_counter()
+    g.autotune(n, scratch=out)
+    tune_s = time.perf_counter() - t0
+    cfg = g.resolved_tuning(n)
+    ms, _ = timed(torch, lambda: g.generate(n, out=out), max(5, args.steps // 2), 10)
+    g.close()
+    del out
+    return {"ms": round(ms, 4), "tune_s": round(tune_s, 2), "config": cfg,
+            "ratio_to_default": round(default_ms / ms, 4)}
+
+
+def run_copy_probe(torch, L):
+    """Two 1 GiB copies by k_copy: the byte counters' calibration in profiled runs."""
+    n_words = 1 << 28
+    src = torch.zeros(n_words, dtype=torch.int32, device="cuda")
+    dst = torch.empty(n_words, dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        L.cprng_probe_copy(dst, src, n_words, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    del src, dst
+    log("[bench] copy probe: 2 x 1 GiB copies (k_copy)")
 
 
 def run_valu_probes(torch, L):
@@ -327,14 +421,16 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=50,
-                    help="untimed steps; the first ~50 launches after the GPU has been idle run slower")
+    ap.add_argument("--warmup", type=int, default=10, help="untimed steps before the timed ones")
     ap.add_argument("--workload", default="paper",
                     choices=["paper", "ragged", "serving", "consume", "ragged_v1", "ragged_groups"])
     ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched legs on the default launch configuration instead of the autotuner's")
+    ap.add_argument("--serving-duration", type=float, default=60.0,
+                    help="seconds of arrivals of the serving leg in the default run (0: skip it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB copy kernel (hardware byte-counter calibration)")
     args = ap.parse_args()
@@ -371,13 +467,7 @@ def main():
         # in one hipGraph launch, against plain V0 (stream-major) timed first.
         ref = run_plain(torch, G, "v0", args, interleaved=False)
         if args.copy_probe:
-            n_words = 1 << 28
-            src = torch.zeros(n_words, dtype=torch.int32, device="cuda")
-            dst = torch.empty(n_words, dtype=torch.int32, device="cuda")
-            for _ in range(2):
-                L.cprng_probe_copy(dst, src, n_words, torch.cuda.current_stream().cuda_stream)
-            torch.cuda.synchronize()
-            del src, dst
+            run_copy_probe(torch, L)
         res = run_ragged(torch, G, args, ref["gnumbers_per_s"])
         log(f"[bench] ragged: {res}")
         print(json.dumps({"metric": "batched uneven streams: Gnumbers/s and ratio to plain V0",
@@ -392,6 +482,8 @@ def main():
         # for profiling, against the plain variant (stream-major) timed first.
         variant = "v1" if args.workload == "ragged_v1" else "v2"
         ref = run_plain(torch, G, variant, args, interleaved=False)
+        if args.copy_probe:
+            run_copy_probe(torch, L)
         run = run_ragged_v1 if variant == "v1" else run_ragged_groups
         res = run(torch, G, args, ref["gnumbers_per_s"])
         log(f"[bench] {args.workload}: {res}")
@@ -402,20 +494,33 @@ def main():
                           "plain": ref, args.workload: res}), flush=True)
         return
 
-    ms, wall, numbers, alg_bytes, achieved = run_paper(torch, G, L, args, interleaved=True)
-    if args.copy_probe:
-        n_words = 1 << 28
-        src = torch.zeros(n_words, dtype=torch.int32, device="cuda")
-        dst = torch.empty(n_words, dtype=torch.int32, device="cuda")
-        for _ in range(2):
-            L.cprng_probe_copy(dst, src, n_words, torch.cuda.current_stream().cuda_stream)
-        torch.cuda.synchronize()
-        del src, dst
-        log("[bench] copy probe: 2 x 1 GiB copies (k_copy)")
-    value = numbers / (ms / 1e3) / 1e9
-    log(f"[bench] paper: {ms:.4f} ms/step, {value:.1f} Gnumbers/s, {achieved:.0f} GB/s")
+    ns, n = 1 << 20, 1024
+    numbers = ns * n
+    alg_bytes = numbers * 4 + ns * 6 * 4 * 2        # outputs + the 24-byte state read and written
+    log(f"[bench] paper workload: V2, {ns} streams x {n}, seed 1, interleaved layout")
+    g = G.Generator(ns, "v2", seed=1, interleaved=True)
+    out = torch.empty((n, ns), dtype=torch.int32, device="cuda")
+    step = lambda: g.generate(n, out=out)
     extra = {}
     if not args.no_extra:
+        # The first launches after the GPU has been idle (host-side seeding just
+        # ran): the shader clock settles over ~30-40 ms of activity, and the
+        # kernel, store-bound at the settled clock, runs slower meanwhile.  The
+        # headline below is timed after the secondary legs, with the clock
+        # settled; the same warmup + steps launches from idle are reported here.
+        cold = per_launch(torch, step, args.warmup + args.steps)
+        win = cold[args.warmup:]
+        extra["cold_start"] = {
+            "what": "the headline's warmup + steps launches right after idle (before any other leg)",
+            "ms_per_launch": [round(x, 4) for x in cold],
+            "timed_window_mean_ms": round(sum(win) / len(win), 4),
+            "frac_hbm_peak": round(alg_bytes / (sum(win) / len(win) / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"[bench] cold start: window mean {extra['cold_start']['timed_window_mean_ms']} ms")
+        if args.serving_duration > 0:
+            extra["serving"] = run_serving(args)
+            log(f"[bench] serving: {extra['serving']}")
+        extra["small"] = run_small(torch, G, args)
+        log(f"[bench] small: {extra['small']}")
         sm_ms, _, _, sm_bytes, sm_ach = run_paper(torch, G, L, args, interleaved=False,
                                                   steps=max(5, args.steps // 2), warmup=30)
         extra["v2_stream_major"] = {"workload": "the same run in the stream-major layout out[s * 1024 + i]",
@@ -443,6 +548,39 @@ def main():
         log(f"[bench] dpp study: {extra['dpp_study']}")
         extra["fill_probe"] = run_fill_probe(torch, L)
         log(f"[bench] fill probe: {extra['fill_probe']}")
+
+    # Headline: warmup untimed steps, then exactly `steps` timed steps, each
+    # launch bracketed by its own events as well (the kernel's duration).
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for a, b in ev:
+        a.record()
+        step()
+        b.record()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    launches = [a.elapsed_time(b) for a, b in ev]
+    kernel_ms = sum(launches) / len(launches)
+    achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
+    value = numbers / (ms / 1e3) / 1e9
+    log(f"[bench] paper: {ms:.4f} ms/step ({kernel_ms:.4f} ms per launch), {value:.1f} Gnumbers/s, "
+        f"{achieved:.0f} GB/s")
+    extra["headline_launch_ms"] = [round(x, 4) for x in launches]
+    if args.copy_probe:
+        run_copy_probe(torch, L)
+    g.close()
+    del out
+    if not args.no_extra and not args.no_autotune:
+        extra["headline_autotuned"] = run_headline_autotuned(torch, G, args, ms)
+        log(f"[bench] headline autotuned: {extra['headline_autotuned']}")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_paper()
@@ -468,11 +606,13 @@ def main():
         "config": {"workload": "paper-shaped neighbour-exchange variant (Algorithm 4): 2^20 streams "
                                "x 1024 uint32 outputs (4 GiB), SplitMix64 seed 1, group 32, interleaved "
                                "layout out[i * 2^20 + s]",
-                   "n_streams": 1 << 20, "n_per_stream": 1024, "variant": "v2", "layout": "interleaved"},
+                   "n_streams": ns, "n_per_stream": n, "variant": "v2", "layout": "interleaved",
+                   "timed_after": "the secondary legs (shader clock settled)" if not args.no_extra
+                                  else "the first launches after idle"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_from_profile("k_generate_ilv_v2_paper"),
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes, "kernel_ms": round(kernel_ms, 5)},
         "cpu_baseline": cpu,
         "extra": extra,
     }
