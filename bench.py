@@ -70,13 +70,18 @@ def log(msg):
 
 
 def kernel_source_sha():
-    """Hash of every device source (kernel files, their includes, internal.h)."""
+    """Hash of the sources the headline kernel (k_generate_ilv of the exchange
+    variant) is built from: its template and launch code, the device helpers,
+    the variant's instantiation unit and the kernel-argument struct."""
     csrc = os.path.join(ROOT, "paper_1112_5239_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".inc")) or name == "internal.h":
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in ("device_common.inc", "gen_kernels.inc", "gen_v2.hip"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(csrc, "internal.h"), "rb") as f:
+        text = f.read()
+    a = text.index(b"struct GenArgs {")
+    h.update(b"GenArgs\0" + text[a:text.index(b"};", a)])
     return h.hexdigest()[:16]
 
 

@@ -317,15 +317,16 @@ typedef struct cprng_tuning {
     uint32_t block;            /* threads per block: 64, 128, 192 or 256; the interleaved
                                   layout's tiles take 256, 512 or 1024 (streams per tile);
                                   batched runs of V1, V2 and V4 (chunk kernels): 64 or
-                                  256 (the default) */
+                                  256 (defaults: V1 256, V2/V4 64; the V2/V4 kernel
+                                  takes 64 with unroll 128) */
     uint32_t unroll;           /* outputs per stream per round: 8, 16, 32 (direct);
                                   16..256, powers of two (LDS-transposed; chunk
                                   kernels 32..256); 16..128 (pipelined); the
                                   V3 (BBS) kernels are built for 8..32 only and
                                   larger values are lowered to 32; batched runs of
-                                  V1, V2 and V4: words per store round, 32, 64 (the
-                                  default) or 128 (V1 rounds follow the output's
-                                  aligned lines of that many words) */
+                                  V1, V2 and V4: words per store round = the output's
+                                  aligned lines those rounds store, 32, 64 or 128
+                                  (defaults: V1 64, V2/V4 32) */
     uint32_t store;            /* store mode, see above */
     uint32_t chunk;            /* ragged/requests: outputs per chunk (multiple of 64) */
     uint32_t waves_per_cu;     /* ragged/requests (store 1/2/4) and pipelined generate:
@@ -335,6 +336,8 @@ typedef struct cprng_tuning {
                                   taking tiles of its XCD's band in turn (0 = one
                                   workgroup per tile, the default) */
     uint32_t streams_per_lane; /* LDS-transposed generate: 1, 2 or 4 streams per lane;
+                                  batched V1 runs: lanes per chunk of the aggregate
+                                  pass, 1, 2 (the default) or 4;
                                   interleaved tiles: 2 = two tile buffers, so each
                                   round's stores overlap the next round's steps */
     uint32_t exchange;         /* V2/V3/V4 tile kernels (stream-major, pipelined,

@@ -173,7 +173,10 @@ int create_impl(const cprng_params_t *p, cprng_t **out)
     return CPRNG_OK;
 }
 
-LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
+// Launch configuration of a generate / consume call: the library's defaults,
+// then the autotuner's entry for the shape class, then cprng_set_tuning's
+// fields.  defaults_only: the defaults alone.
+LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume, bool defaults_only = false)
 {
     if (!h->tuned_loaded) {
         tune_cache_load(h);
@@ -199,6 +202,7 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
             c.slots = 1;
             c.exchange = XCH_LDS;
         }
+        if (defaults_only) return c;
         TuneEntry e;
         if (tune_cache_lookup(h, n, &e) && e.store) {       // the autotuner's pick for this shape class
             c.block = e.block;
@@ -225,6 +229,10 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
     }
     LaunchCfg c = default_cfg(h->variant, (h->flags & CPRNG_F_V1_W32) != 0, consume);
     TuneEntry e = default_entry(h->variant, consume);
+    if (defaults_only) {
+        c.lds_bytes = (c.store == ST_PIPE || c.store == ST_PIPE_NT) ? 0u : lds_for_waves(c.block, consume ? 0u : e.waves);
+        return c;
+    }
     if (!consume && tune_cache_lookup(h, n, &e)) {
         c.block = e.block;
         c.unroll = e.unroll;
@@ -254,6 +262,19 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume)
 namespace cprng_impl {
 
 void fill_gen_args(const cprng_t *h, GenArgs &a) { fill_args(h, a); }
+
+std::pair<LaunchCfg, TuneEntry> default_generate(cprng_t *h, uint64_t n)
+{
+    const LaunchCfg c = resolve_cfg(h, n, false, true);
+    TuneEntry e;
+    e.block = c.block;
+    e.unroll = c.unroll;
+    e.store = c.store;
+    e.slots = c.slots;
+    e.exchange = c.exchange;
+    e.waves = (h->flags & CPRNG_F_INTERLEAVED) ? (h->n_cu ? c.grid / h->n_cu : 0u) : default_entry(h->variant, false).waves;
+    return {c, e};
+}
 int timing_begin(cprng_t *h, hipStream_t st) { return begin_timing(h, st); }
 int timing_end(cprng_t *h, hipStream_t st) { return end_timing(h, st); }
 

@@ -420,13 +420,14 @@ namespace {
 // Store round of the chunk kernels: 32, 64 or 128 words.
 uint32_t norm_round(uint32_t u) { return (u == 32 || u == 64 || u == 128) ? u : 64u; }
 
-// Waves of a chunk kernel that stay resident per CU, from its tile's LDS
-// (the kernels' other limits are looser).
-uint64_t chunk_resident_waves(const ChunkCfg &c)
+// Waves of a chunk kernel that stay resident per CU, from its tiles' LDS
+// (the kernels' other limits are looser): V1 64 rows of K + 1 words per
+// wave; the group kernel 64 rings of 2K + 4 words and a 512-byte line table.
+uint64_t chunk_resident_waves(const ChunkCfg &c, bool v1)
 {
     const uint64_t K = c.round, W = c.wg_waves;
-    const uint64_t wg_lds = W * 64u * (K + 1u) * 4u;
-    return std::min<uint64_t>(32u, (kMaxLdsBytes / wg_lds) * W);
+    const uint64_t wave_lds = v1 ? 64u * (K + 1u) * 4u : 64u * (2u * K + 4u) * 4u + 512u;
+    return std::min<uint64_t>(32u, (kMaxLdsBytes / (W * wave_lds)) * W);
 }
 
 // Shortest chunk, a multiple of 64 in [lo, 2^20], with n_items(chunk) <= cap
@@ -547,7 +548,7 @@ const V1Polys &v1_polys_of(const cprng_t *h)
 uint64_t auto_chunk(const cprng_t *h, const uint64_t *lengths, const ChunkCfg &c, uint64_t jump_len)
 {
     if (is_v1(h)) {
-        const uint64_t cap = 2u * (uint64_t)h->n_cu * chunk_resident_waves(c) * 64u * 31u / 32u;
+        const uint64_t cap = 2u * (uint64_t)h->n_cu * chunk_resident_waves(c, true) * 64u * 31u / 32u;
         return fit_chunk(16ull * jump_len, cap, [&](uint64_t ch) {
             uint64_t n = 0;
             for (uint32_t s = 0; s < h->ns; ++s) n += (lengths[s] + ch - 1) / ch;
@@ -555,7 +556,7 @@ uint64_t auto_chunk(const cprng_t *h, const uint64_t *lengths, const ChunkCfg &c
         });
     }
     const uint32_t C = h->group;
-    const uint64_t cap = (uint64_t)h->n_cu * chunk_resident_waves(c) * (64u / C) * 31u / 32u;
+    const uint64_t cap = (uint64_t)h->n_cu * chunk_resident_waves(c, false) * (64u / C) * 31u / 32u;
     return fit_chunk(16ull * jump_len, cap, [&](uint64_t ch) {
         uint64_t n = 0;
         for (uint32_t g = 0; g < h->ns / C; ++g) n += (lengths[(size_t)g * C] + ch - 1) / ch;
@@ -764,6 +765,7 @@ int plan_host(cprng_t *h, const uint64_t *lengths, const uint64_t *offsets, cons
     p.cfg = cfg;
     p.cfg.round = norm_round(cfg.round);
     p.cfg.wg_waves = cfg.wg_waves == 1 ? 1u : 4u;
+    if (!is_v1(h) && p.cfg.round == 128) p.cfg.wg_waves = 1;   // the group kernel's K = 128 rings: one wave per workgroup
     p.cfg.parts = (cfg.parts == 1 || cfg.parts == 2 || cfg.parts == 4) ? cfg.parts : 2u;
     if (!p.cfg.chunk) p.cfg.chunk = auto_chunk(h, lengths, p.cfg, jump_length(h));
     if (p.cfg.chunk % 64u || p.cfg.chunk > (1ull << 40))
@@ -858,16 +860,24 @@ int check_group_lengths(const cprng_t *h, const uint64_t *lengths)
 
 }  // namespace
 
-ChunkCfg resolve_chunk_cfg(const cprng_t *h, uint64_t total, uint64_t max_len)
+// Defaults measured on MI355X (4,096 V1 streams / 128 V2 groups of 32,
+// lengths log-uniform in [1e3, 1e7]), automatic chunk: V1 rounds of 64
+// words in four-wave workgroups, aggregates split over two lanes; the group
+// kernel rounds of 32 words (128-byte lines; its two-line rings then leave
+// 8-9 waves per CU) in one-wave workgroups.
+ChunkCfg default_chunk_cfg(const cprng_t *h)
 {
-    // Defaults measured on MI355X (4,096 V1 streams / 128 V2 groups of 32,
-    // lengths log-uniform in [1e3, 1e7]): rounds of 64 words, four-wave
-    // workgroups, automatic chunk; V1 aggregates split over two lanes.
     ChunkCfg c;
     c.chunk = 0;
-    c.round = 64;
-    c.wg_waves = 4;
+    c.round = is_v1(h) ? 64u : 32u;
+    c.wg_waves = is_v1(h) ? 4u : 1u;
     c.parts = 2;
+    return c;
+}
+
+ChunkCfg resolve_chunk_cfg(const cprng_t *h, uint64_t total, uint64_t max_len)
+{
+    ChunkCfg c = default_chunk_cfg(h);
     TuneEntry e;
     if (tune_cache_lookup_key(tune_key_ragged(h, total, max_len), &e)) {
         c.chunk = e.chunk;
@@ -938,6 +948,7 @@ int chunk_for(cprng_t *h, const uint64_t *lengths, const ChunkCfg &cfg, uint64_t
     ChunkCfg c = cfg;
     c.round = norm_round(c.round);
     c.wg_waves = c.wg_waves == 1 ? 1u : 4u;
+    if (!is_v1(h) && c.round == 128) c.wg_waves = 1;
     *chunk = auto_chunk(h, lengths, c, jump_length(h));
     return CPRNG_OK;
 }
@@ -970,29 +981,24 @@ int ragged_v1(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t
 int autotune_chunked(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets, hipStream_t st,
                      uint64_t total, uint64_t max_len)
 {
+    (void)max_len;
     int rc = check_group_lengths(h, lengths);
     if (rc) return rc;
     if (total == 0) return CPRNG_OK;
     if ((rc = prepare_polys(h))) return rc;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return set_error(CPRNG_E_HIP, "hipEventCreate");
-    const bool saved_timing = h->timing;
-    h->timing = false;
-    float best = 1e30f;
-    ChunkCfg best_c = resolve_chunk_cfg(h, total, max_len);
-    bool best_auto = best_c.chunk == 0;
-    const uint32_t rounds[] = {32, 64, 128};
-    const uint32_t wgs[] = {1, 4};
+    if ((rc = ensure_next(h))) return rc;
+    std::vector<ChunkCfg> cands;
+    cands.push_back(default_chunk_cfg(h));                    // candidate 0: the defaults
     const uint32_t parts_v1[] = {1, 2, 4};
-    const uint32_t parts_grp[] = {1};
+    const uint32_t parts_grp[] = {2};
     const uint32_t *parts = is_v1(h) ? parts_v1 : parts_grp;
     const int n_parts = is_v1(h) ? 3 : 1;
-    for (uint32_t K : rounds)
-        for (uint32_t W : wgs)
-            for (int pi = 0; pi < n_parts && !rc; ++pi)
-                for (int scale = 0; scale < 3 && !rc; ++scale) {
+    for (uint32_t K : {32u, 64u, 128u})
+        for (uint32_t W : {1u, 4u})
+            for (int pi = 0; pi < n_parts; ++pi)
+                for (int scale = 0; scale < 3; ++scale) {
                     if (scale == 1 && is_v1(h)) continue;     // V1: automatic and twice that
+                    if (!is_v1(h) && K == 128 && W == 4) continue; // group rings of K = 128: one wave per workgroup
                     ChunkCfg c;
                     c.round = K;
                     c.wg_waves = W;
@@ -1002,34 +1008,30 @@ int autotune_chunked(cprng_t *h, uint32_t *out, const uint64_t *lengths, const u
                         const uint64_t a = auto_chunk(h, lengths, c, jump_length(h));
                         c.chunk = scale == 1 ? std::max<uint64_t>(64u, a / 2u / 64u * 64u) : std::min<uint64_t>(a * 2u, 1ull << 20);
                     }
-                    std::vector<float> t;
-                    for (int r = 0; r < 4 && !rc; ++r) {
-                        if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
-                        if (!rc) rc = ragged_chunked(h, out, lengths, offsets, st, c, true);
-                        if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
-                        if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventSynchronize");
-                        float ms = 0.f;
-                        if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = set_error(CPRNG_E_HIP, "elapsed");
-                        if (r > 0) t.push_back(ms);
-                    }
-                    if (ChunkPlan *p = find_chunk_plan(h, out, lengths, offsets, c)) drop_chunk_plan(h, p);
-                    if (rc) break;
-                    std::sort(t.begin(), t.end());
-                    if (t[t.size() / 2] < best) {
-                        best = t[t.size() / 2];
-                        best_c = c;
-                        best_auto = c.chunk == 0;
-                    }
+                    cands.push_back(c);
                 }
+    const bool saved_timing = h->timing;
+    h->timing = false;
+    auto drop = [&](const ChunkCfg &c) {
+        if (ChunkPlan *p = find_chunk_plan(h, out, lengths, offsets, c)) drop_chunk_plan(h, p);
+    };
+    size_t best = 0;
+    rc = tune_select(
+        cands.size(), 0, st, [&](size_t i) { return ragged_chunked(h, out, lengths, offsets, st, cands[i], true); },
+        [&](size_t i, bool kept) {
+            if (!kept) drop(cands[i]);
+        },
+        &best);
+    for (size_t i = 0; i < cands.size(); ++i)
+        if (i != best) drop(cands[i]);
     h->timing = saved_timing;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc) return rc;
+    const ChunkCfg &b = cands[best];
     TuneEntry e;
-    e.chunk = best_auto ? 0u : (uint32_t)best_c.chunk;
-    e.unroll = best_c.round;
-    e.block = best_c.wg_waves == 1 ? 64u : 256u;
-    e.slots = best_c.parts;
+    e.chunk = (uint32_t)b.chunk;
+    e.unroll = b.round;
+    e.block = b.wg_waves == 1 ? 64u : 256u;
+    e.slots = b.parts;
     tune_cache_store(tune_key_ragged(h, total, max_len), e);
     return CPRNG_OK;
 }

@@ -145,15 +145,17 @@ void normalize(SegCfg &c)
     if (c.waves == 0 && seg_persistent(c)) c.waves = 4;
 }
 
+// Default measured on MI355X for 4,096 streams of 1e3..1e7 outputs:
+// LDS-tiled non-temporal stores of K = 128 outputs per row and round,
+// 2048-output chunks (a wave's 64 chunks span 512 KiB of the output),
+// three persistent waves per CU.  With runs aligned to 256 bytes every
+// round writes whole lines; then 3 waves per CU keep enough SIMDs busy
+// without widening the set of rows written at once too far.
+constexpr SegCfg kDefaultSeg{2048, 128, 3, 64, ST_LDS_NT};
+
 SegCfg resolve_seg_cfg(const cprng_t *h, uint64_t total, uint64_t max_len)
 {
-    // Default measured on MI355X for 4,096 streams of 1e3..1e7 outputs:
-    // LDS-tiled non-temporal stores of K = 128 outputs per row and round,
-    // 2048-output chunks (a wave's 64 chunks span 512 KiB of the output),
-    // three persistent waves per CU.  With runs aligned to 256 bytes every
-    // round writes whole lines; then 3 waves per CU keep enough SIMDs busy
-    // without widening the set of rows written at once too far.
-    SegCfg c{2048, 128, 3, 64, ST_LDS_NT};
+    SegCfg c = kDefaultSeg;
     TuneEntry e;
     if (tune_cache_lookup_key(tune_key_ragged(h, total, max_len), &e)) {
         if (e.chunk) c.chunk = e.chunk;
@@ -522,52 +524,51 @@ extern "C" int cprng_autotune_ragged(cprng_t *h, uint32_t *out, const uint64_t *
     }
     rc = ensure_common(h);
     if (rc) return rc;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return set_error(CPRNG_E_HIP, "hipEventCreate");
     const uint32_t chunks[] = {1024, 2048, 4096, 8192, 16384};
     const uint32_t waves[] = {1, 2, 3, 4, 8};
     // (store, unroll, block): per-lane stores and LDS tiles of several widths
     const uint32_t modes[][3] = {{ST_DIRECT, 16, 256}, {ST_DIRECT, 32, 256}, {ST_LDS, 32, 64},
                                  {ST_LDS, 64, 64}, {ST_LDS, 128, 64}, {ST_LDS_NT, 32, 64},
-                                 {ST_PIPE, 64, 64}, {ST_PIPE, 128, 64}, {ST_PIPE_NT, 128, 64}};
-    float best = 1e30f;
-    SegCfg best_c = resolve_seg_cfg(h, total, max_len);
-    const bool saved_timing = h->timing;
-    h->timing = false;
+                                 {ST_LDS_NT, 128, 64}, {ST_PIPE, 64, 64}, {ST_PIPE, 128, 64},
+                                 {ST_PIPE_NT, 128, 64}};
+    std::vector<SegCfg> cands;
+    SegCfg d = kDefaultSeg;
+    normalize(d);
+    cands.push_back(d);                                      // candidate 0: the default
     for (uint32_t ch : chunks)
         for (uint32_t w : waves)
             for (const auto &m : modes) {
                 SegCfg c{ch, m[1], w, m[2], m[0]};
                 normalize(c);
-                std::vector<float> t;
-                for (int r = 0; r < 4 && rc == CPRNG_OK; ++r) {
-                    if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
-                    if (!rc) rc = ragged_with(h, out, lengths, offsets, st, c);
-                    if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
-                    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventSynchronize");
-                    float ms = 0.f;
-                    if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = set_error(CPRNG_E_HIP, "elapsed");
-                    if (r > 0) t.push_back(ms);
-                }
-                // Drop this candidate's graph again; only the winner is kept.
-                if (RaggedPlan *p = find_plan(h, out, lengths, offsets, c)) {
-                    h->plans.erase(std::find(h->plans.begin(), h->plans.end(), p));
-                    free_plan(p);
-                }
-                if (rc) break;
-                std::sort(t.begin(), t.end());
-                if (t[t.size() / 2] < best) {
-                    best = t[t.size() / 2];
-                    best_c = c;
-                }
+                cands.push_back(c);
             }
+    const bool saved_timing = h->timing;
+    h->timing = false;
+    auto drop = [&](const SegCfg &c) {
+        if (RaggedPlan *p = find_plan(h, out, lengths, offsets, c)) {
+            h->plans.erase(std::find(h->plans.begin(), h->plans.end(), p));
+            free_plan(p);
+        }
+    };
+    size_t best = 0;
+    rc = tune_select(
+        cands.size(), 0, st,
+        [&](size_t i) {
+            const int r = ragged_with(h, out, lengths, offsets, st, cands[i]);
+            return r;
+        },
+        [&](size_t i, bool kept) {
+            if (!kept) drop(cands[i]);
+        },
+        &best);
+    // Only the winner's graph is kept.
+    for (size_t i = 0; i < cands.size(); ++i)
+        if (i != best) drop(cands[i]);
     h->timing = saved_timing;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     const int rrc = backup.restore(h, st);
     if (rc) return rc;
     if (rrc) return rrc;
+    const SegCfg best_c = cands[best];
     TuneEntry e;
     e.block = best_c.block;
     e.unroll = best_c.unroll;

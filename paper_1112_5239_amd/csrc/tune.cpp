@@ -7,6 +7,7 @@
 // Keys name the device architecture, variant and a power-of-two bucket of
 // the shape, so one tuning serves every shape of the same class.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -191,6 +192,81 @@ void tune_cache_store(const std::string &key, const TuneEntry &e)
     save_file_locked();
 }
 
+int tune_select(size_t n_cand, size_t default_idx, hipStream_t st, const std::function<int(size_t)> &run,
+                const std::function<void(size_t, bool)> &after_screen, size_t *best)
+{
+    if (n_cand == 0) return set_error(CPRNG_E_INVAL, "no candidate configuration");
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return set_error(CPRNG_E_HIP, "hipEventCreate");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return set_error(CPRNG_E_HIP, "hipEventCreate");
+    }
+    int rc = CPRNG_OK;
+    // Average device time of `reps` back-to-back runs of candidate i.
+    auto time_runs = [&](size_t i, int reps, float *ms) -> int {
+        if (hipEventRecord(e0, st) != hipSuccess) return set_error(CPRNG_E_HIP, "hipEventRecord");
+        for (int r = 0; r < reps; ++r) {
+            const int c = run(i);
+            if (c) return c;
+        }
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return set_error(CPRNG_E_HIP, "hipEventRecord/Synchronize");
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) return set_error(CPRNG_E_HIP, "hipEventElapsedTime");
+        *ms = t / (float)reps;
+        return CPRNG_OK;
+    };
+    auto reps_for = [](float one_ms, float target_ms) {
+        const float r = one_ms > 0.f ? target_ms / one_ms : 64.f;
+        return std::max(1, std::min(64, (int)std::ceil(r)));
+    };
+    std::vector<float> screen(n_cand, 1e30f);
+    std::vector<int> reps(n_cand, 1);
+    for (size_t i = 0; i < n_cand && !rc; ++i) {
+        float one = 0.f;
+        rc = time_runs(i, 1, &one);                          // warm-up (builds plans, loads code)
+        if (!rc) {
+            reps[i] = reps_for(one, 2.0f);
+            rc = time_runs(i, reps[i], &screen[i]);
+        }
+    }
+    std::vector<size_t> order(n_cand);
+    for (size_t i = 0; i < n_cand; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return screen[a] < screen[b]; });
+    std::vector<size_t> fin(order.begin(), order.begin() + std::min<size_t>(4, n_cand));
+    if (std::find(fin.begin(), fin.end(), default_idx) == fin.end() && default_idx < n_cand) fin.push_back(default_idx);
+    for (size_t i = 0; i < n_cand; ++i) after_screen(i, std::find(fin.begin(), fin.end(), i) != fin.end());
+    std::vector<std::vector<float>> conf(fin.size());
+    for (size_t k = 0; k < fin.size() && !rc; ++k) {
+        float one = 0.f;
+        rc = time_runs(fin[k], 1, &one);                     // warm-up again (plans may have been dropped)
+    }
+    for (int round = 0; round < 5 && !rc; ++round)
+        for (size_t k = 0; k < fin.size() && !rc; ++k) {
+            float t = 0.f;
+            rc = time_runs(fin[k], reps_for(screen[fin[k]], 3.0f), &t);
+            conf[k].push_back(t);
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    size_t win = 0;
+    float win_t = 1e30f, def_t = 1e30f;
+    for (size_t k = 0; k < fin.size(); ++k) {
+        std::vector<float> v = conf[k];
+        std::sort(v.begin(), v.end());
+        const float med = v[v.size() / 2];
+        if (fin[k] == default_idx) def_t = med;
+        if (med < win_t) {
+            win_t = med;
+            win = fin[k];
+        }
+    }
+    *best = (default_idx < n_cand && def_t <= win_t * 1.01f) ? default_idx : win;
+    return CPRNG_OK;
+}
+
 int StateBackup::save(const cprng_t *h, hipStream_t st)
 {
     words = (size_t)h->ns * h->words;
@@ -223,27 +299,6 @@ StateBackup::~StateBackup()
 using namespace cprng_impl;
 
 namespace {
-
-// Median device time of a few runs of one candidate (the first is a warm-up).
-int time_candidate(cprng_t *h, uint32_t *scratch, uint64_t n, hipStream_t st, const LaunchCfg &c,
-                   hipEvent_t e0, hipEvent_t e1, float *med)
-{
-    std::vector<float> t;
-    int rc = CPRNG_OK;
-    for (int r = 0; r < 4 && rc == CPRNG_OK; ++r) {
-        if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
-        if (rc == CPRNG_OK) rc = generate_with(h, scratch, n, st, c);
-        if (rc == CPRNG_OK && hipEventRecord(e1, st) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventRecord");
-        if (rc == CPRNG_OK && hipEventSynchronize(e1) != hipSuccess) rc = set_error(CPRNG_E_HIP, "hipEventSynchronize");
-        float ms = 0.f;
-        if (rc == CPRNG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = set_error(CPRNG_E_HIP, "elapsed");
-        if (r > 0) t.push_back(ms);
-    }
-    if (rc) return rc;
-    std::sort(t.begin(), t.end());
-    *med = t[t.size() / 2];
-    return CPRNG_OK;
-}
 
 // Candidates of the interleaved layout: LDS tiles of block streams x unroll
 // steps (one or two tile buffers, cross-lane or LDS-buffer exchange, one
@@ -317,6 +372,7 @@ extern "C" int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n, cprng_s
                                         "(interleaved: n_streams % 4 == 0)");
     hipStream_t st = (hipStream_t)stream;
     std::vector<std::pair<LaunchCfg, TuneEntry>> cands;
+    cands.push_back(default_generate(h, n));                  // candidate 0: the library's default
     if (ilv)
         interleaved_candidates(h, cands);
     else
@@ -324,28 +380,16 @@ extern "C" int cprng_autotune(cprng_t *h, uint32_t *scratch, uint64_t n, cprng_s
     StateBackup backup;
     int rc = backup.save(h, st);
     if (rc) return rc;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return set_error(CPRNG_E_HIP, "hipEventCreate");
-    float best = 1e30f;
-    TuneEntry best_e;
     const bool saved_timing = h->timing;
     h->timing = false;
-    for (const auto &ce : cands) {
-        float med = 0.f;
-        rc = time_candidate(h, scratch, n, st, ce.first, e0, e1, &med);
-        if (rc) break;
-        if (med < best) {
-            best = med;
-            best_e = ce.second;
-        }
-    }
+    size_t best = 0;
+    rc = tune_select(
+        cands.size(), 0, st, [&](size_t i) { return generate_with(h, scratch, n, st, cands[i].first); },
+        [](size_t, bool) {}, &best);
     h->timing = saved_timing;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     const int rrc = backup.restore(h, st);
     if (rc) return rc;
     if (rrc) return rrc;
-    tune_cache_store(tune_key_generate(h, n), best_e);
+    tune_cache_store(tune_key_generate(h, n), cands[best].second);
     return CPRNG_OK;
 }

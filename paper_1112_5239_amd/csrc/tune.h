@@ -1,7 +1,9 @@
 // tune.h -- launch configuration defaults, the autotuner and its JSON cache.
 #pragma once
 
+#include <functional>
 #include <string>
+#include <utility>
 
 #include "host.h"
 
@@ -24,6 +26,19 @@ bool tune_cache_lookup_key(const std::string &key, TuneEntry *e);
 void tune_cache_store(const std::string &key, const TuneEntry &e);
 
 int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchCfg c);
+// The library's default launch configuration of cprng_generate for this
+// handle and n (no cache entry, no explicit tuning), as a cache entry too.
+std::pair<LaunchCfg, TuneEntry> default_generate(cprng_t *h, uint64_t n);
+// Candidate selection of the autotuners.  run(i) enqueues candidate i once on
+// st.  Screening: each candidate is run once untimed, then timed over enough
+// back-to-back runs to cover about 2 ms.  Confirmation: the four fastest and
+// candidate default_idx are run once more untimed, then timed in 5 rounds that
+// alternate between them (so slow drifts of the clock hit all of them alike);
+// the lowest median wins, and default_idx is kept unless another candidate
+// is more than 1% faster.  after_screen(i, kept) is told which candidates
+// take part in the confirmation (to release the others' resources).
+int tune_select(size_t n_cand, size_t default_idx, hipStream_t st, const std::function<int(size_t)> &run,
+                const std::function<void(size_t, bool)> &after_screen, size_t *best);
 // The handle's stream states, copied aside on the device before tuning and
 // put back afterwards, so that tuning leaves the streams where they were.
 struct StateBackup {

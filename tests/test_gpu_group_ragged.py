@@ -114,3 +114,36 @@ def test_group_ragged_rejects_unequal_lengths_within_a_group(G):
         assert e.value.status == L.E_INVAL
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("shift", [1, 2, 3, 17])
+@pytest.mark.parametrize("rnd", [32, 64, 128])
+def test_group_ragged_misaligned_output_base(orc, G, rnd, shift):
+    # the output pointer itself off its lines by `shift` words: each stream's
+    # first line starts at its own column of the store ring
+    import torch
+    Cg = 16
+    gl = _group_lengths(6, 87 + shift, 1800)
+    ns = gl.size * Cg
+    lengths = np.repeat(gl, Cg).astype(np.uint64)
+    total = int(lengths.sum())
+    g = G.Generator(ns, "v2", seed=87, group=Cg)
+    try:
+        g.set_tuning(chunk=256, unroll=rnd, block=256)
+        buf = torch.zeros(total + 64, dtype=torch.int32, device="cuda")
+        view = buf[shift:shift + total]
+        g.generate_ragged(lengths, out=view)
+        got = G.as_u32(buf)
+        st = orc.seed(2, 87, 0, ns)
+        combs = orc.comb_tables(Cg)
+        pos = shift
+        for gi in range(gl.size):
+            sub = st[gi * Cg:(gi + 1) * Cg].copy()
+            want, _ = orc.generate(2, sub, int(gl[gi]), comb=combs)
+            for j in range(Cg):
+                L = int(gl[gi])
+                assert np.array_equal(got[pos:pos + L], want[j]), f"group {gi} stream {j}"
+                pos += L
+        assert not got[:shift].any() and not got[shift + total:].any(), "words outside the runs were written"
+    finally:
+        g.close()
