@@ -317,8 +317,8 @@ typedef struct cprng_tuning {
     uint32_t block;            /* threads per block: 64, 128, 192 or 256; the interleaved
                                   layout's tiles take 256, 512 or 1024 (streams per tile);
                                   batched runs of V1, V2 and V4 (chunk kernels): 64 or
-                                  256 (defaults: V1 256, V2/V4 64; the V2/V4 kernel
-                                  takes 64 with unroll 128) */
+                                  256 (the default; the V2/V4 kernel takes 64 with
+                                  unroll 128) */
     uint32_t unroll;           /* outputs per stream per round: 8, 16, 32 (direct);
                                   16..256, powers of two (LDS-transposed; chunk
                                   kernels 32..256); 16..128 (pipelined); the

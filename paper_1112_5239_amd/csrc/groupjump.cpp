@@ -422,11 +422,11 @@ uint32_t norm_round(uint32_t u) { return (u == 32 || u == 64 || u == 128) ? u : 
 
 // Waves of a chunk kernel that stay resident per CU, from its tiles' LDS
 // (the kernels' other limits are looser): V1 64 rows of K + 1 words per
-// wave; the group kernel 64 rings of 2K + 4 words and a 512-byte line table.
+// wave; the group kernel 64 rings of 2K + 1 words and a 512-byte line table.
 uint64_t chunk_resident_waves(const ChunkCfg &c, bool v1)
 {
     const uint64_t K = c.round, W = c.wg_waves;
-    const uint64_t wave_lds = v1 ? 64u * (K + 1u) * 4u : 64u * (2u * K + 4u) * 4u + 512u;
+    const uint64_t wave_lds = v1 ? 64u * (K + 1u) * 4u : 64u * (2u * K + 1u) * 4u + 512u;
     return std::min<uint64_t>(32u, (kMaxLdsBytes / (W * wave_lds)) * W);
 }
 
@@ -861,16 +861,16 @@ int check_group_lengths(const cprng_t *h, const uint64_t *lengths)
 }  // namespace
 
 // Defaults measured on MI355X (4,096 V1 streams / 128 V2 groups of 32,
-// lengths log-uniform in [1e3, 1e7]), automatic chunk: V1 rounds of 64
-// words in four-wave workgroups, aggregates split over two lanes; the group
-// kernel rounds of 32 words (128-byte lines; its two-line rings then leave
-// 8-9 waves per CU) in one-wave workgroups.
+// lengths log-uniform in [1e3, 1e7]), four-wave workgroups and the
+// automatic chunk: V1 rounds of 64 words, aggregates split over two lanes;
+// the group kernel rounds of 32 words (128-byte lines; its two-line rings
+// then leave 8 waves per CU).
 ChunkCfg default_chunk_cfg(const cprng_t *h)
 {
     ChunkCfg c;
     c.chunk = 0;
     c.round = is_v1(h) ? 64u : 32u;
-    c.wg_waves = is_v1(h) ? 4u : 1u;
+    c.wg_waves = 4;
     c.parts = 2;
     return c;
 }
