@@ -510,6 +510,9 @@ uint64_t g_chunk_clock = 0;
 void free_chunk_plan(ChunkPlan *p)
 {
     if (!p) return;
+    // A replay of this plan may still be queued or running: let the device
+    // finish before the graph and its tables go.
+    if (p->exec) (void)hipDeviceSynchronize();
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     p->bufs.release_all();

@@ -47,6 +47,9 @@ uint64_t g_use_clock = 0;
 void free_plan(RaggedPlan *p)
 {
     if (!p) return;
+    // A replay of this plan may still be queued or running: let the device
+    // finish before the graph and its tables go.
+    if (p->exec) (void)hipDeviceSynchronize();
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->d_runs) (void)hipFree(p->d_runs);
