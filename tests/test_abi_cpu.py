@@ -135,3 +135,20 @@ def test_jump_selftest_rejects_bad_arguments(L):
         with pytest.raises(L.CprngError) as e:
             L.cprng_jump_selftest(*args, J=10)
         assert e.value.status == L.E_INVAL
+
+
+def test_tuning_queries_and_replay_reject_null_before_device_work(L):
+    lib = L.lib()
+    t = L.Tuning()
+    src = C.c_int(-1)
+    assert lib.cprng_resolved_tuning(None, 64, C.byref(t), C.byref(src)) == L.E_INVAL
+    lengths = np.ones(4, dtype=np.uint64)
+    assert lib.cprng_resolved_tuning_ragged(None, lengths.ctypes.data, C.byref(t), C.byref(src)) == L.E_INVAL
+    res = (L.Completion * 1)()
+    z64 = np.zeros(1, dtype=np.uint64)
+    z32 = np.zeros(1, dtype=np.uint32)
+    keep = np.zeros(1, dtype=np.uint8)
+    assert lib.cprng_server_replay_keep(None, z64.ctypes.data, z32.ctypes.data, z64.ctypes.data, 1,
+                                        keep.ctypes.data, res) == L.E_INVAL
+    assert lib.cprng_autotune(None, None, 64, None) == L.E_INVAL
+    assert lib.cprng_autotune_ragged(None, None, lengths.ctypes.data, None, None) == L.E_INVAL
