@@ -421,12 +421,13 @@ namespace {
 uint32_t norm_round(uint32_t u) { return (u == 32 || u == 64 || u == 128) ? u : 64u; }
 
 // Waves of a chunk kernel that stay resident per CU, from its tiles' LDS
-// (the kernels' other limits are looser): V1 64 rows of K + 1 words per
-// wave; the group kernel 64 rings of 2K + 1 words and a 512-byte line table.
+// (the kernels' other limits are looser): per wave, V1 64 rows of K + 1
+// words, the group kernel 64 rings of 2K + 1 words, each with a 512-byte
+// table of line addresses.
 uint64_t chunk_resident_waves(const ChunkCfg &c, bool v1)
 {
     const uint64_t K = c.round, W = c.wg_waves;
-    const uint64_t wave_lds = v1 ? 64u * (K + 1u) * 4u : 64u * (2u * K + 1u) * 4u + 512u;
+    const uint64_t wave_lds = (v1 ? 64u * (K + 1u) * 4u : 64u * (2u * K + 1u) * 4u) + 512u;
     return std::min<uint64_t>(32u, (kMaxLdsBytes / (W * wave_lds)) * W);
 }
 
@@ -601,6 +602,10 @@ int plan_groups(const cprng_t *h, const uint64_t *lengths, const uint64_t *offse
     uint64_t max_len = 0;
     for (uint32_t g = 0; g < n_groups; ++g) max_len = std::max(max_len, lengths[(size_t)g * C]);
     const uint64_t chunk = p.cfg.chunk;
+    uint64_t n_items = 0;
+    for (uint32_t g = 0; g < n_groups; ++g) n_items += (lengths[(size_t)g * C] + chunk - 1) / chunk;
+    if (n_items > (1ull << 26)) return set_error(CPRNG_E_INVAL, "more than 2^26 chunks (raise the chunk length)");
+    p.gitems.reserve(n_items);
     for (uint32_t g = 0; g < n_groups; ++g) {
         const uint64_t L = lengths[(size_t)g * C];
         for (uint64_t a = 0, c = 0; a < L; a += chunk, ++c) {
@@ -613,7 +618,6 @@ int plan_groups(const cprng_t *h, const uint64_t *lengths, const uint64_t *offse
             p.gitems.push_back(it);
         }
     }
-    if (p.gitems.size() > 0xFFFFFFFFull) return set_error(CPRNG_E_INVAL, "too many chunks");
     p.n_rows = (uint32_t)((max_len + chunk - 1) / chunk);
     group_jump_rows(h, chunk, p.n_rows, p.rows);
     p.row_words = (uint32_t)((h->gj_deg + 31) / 32);
@@ -634,6 +638,10 @@ int plan_v1(const cprng_t *h, const uint64_t *lengths, const uint64_t *offsets, 
     for (uint32_t s = 0; s < h->ns; ++s) max_len = std::max(max_len, lengths[s]);
     const uint64_t chunk = p.cfg.chunk;
     const uint32_t parts = p.cfg.parts;
+    uint64_t n_items = 0;
+    for (uint32_t s = 0; s < h->ns; ++s) n_items += (lengths[s] + chunk - 1) / chunk;
+    if (n_items > (1ull << 26)) return set_error(CPRNG_E_INVAL, "more than 2^26 chunks (raise the chunk length)");
+    p.vitems.reserve(n_items);
     p.sfirst.resize((size_t)h->ns + 1);
     for (uint32_t s = 0; s < h->ns; ++s) {
         const uint32_t first = (uint32_t)p.vitems.size();
