@@ -253,13 +253,28 @@ def run_ragged(torch, G, args, ref_v0_gn):
     tune = _tune_ragged(g, lengths, out, args)
     ms, _ = timed(torch, lambda: g.generate_ragged(lengths, out=out), max(5, args.steps // 4), 10)
     g.close()
+    # The same runs as a device-described subset (cprng_generate_subset):
+    # descriptors in device memory, checked, counted and chunked on the device
+    # in every call (default tuning: 2048-output chunks).
+    gs = G.Generator(ns, "v0", seed=2)
+    ids = torch.arange(ns, dtype=torch.int32, device="cuda")
+    lens = torch.tensor(lengths.astype(np.int64), device="cuda")
+    offs = torch.cumsum(lens, 0) - lens
+    ms_sub, _ = timed(torch, lambda: gs.generate_subset(ids, lens, offs, out), max(5, args.steps // 4), 10)
+    gs.close()
     del out
     gn = total / (ms / 1e3) / 1e9
+    gn_sub = total / (ms_sub / 1e3) / 1e9
     return {"workload": f"4096 streams, log-uniform lengths [1e3,1e7] (total {total}), seed 2, "
                         "one hipGraph launch", "ms": round(ms, 4), "gnumbers_per_s": round(gn, 2),
             "hbm_gbs": round(total * 4 / (ms / 1e3) / 1e9, 1),
             "frac_hbm_peak": round(total * 4 / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-            "ratio_to_plain_v0": round(gn / ref_v0_gn, 4) if ref_v0_gn else None, **tune}
+            "ratio_to_plain_v0": round(gn / ref_v0_gn, 4) if ref_v0_gn else None, **tune,
+            "device_subset": {"workload": "the same runs through cprng_generate_subset (descriptors in device "
+                                          "memory, planned on the device every call, 2048-output chunks)",
+                              "ms": round(ms_sub, 4), "gnumbers_per_s": round(gn_sub, 2),
+                              "frac_hbm_peak": round(total * 4 / (ms_sub / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                              "ratio_to_host_planned": round(gn_sub / gn, 4)}}
 
 
 def run_ragged_groups(torch, G, args, ref_gn):

@@ -235,6 +235,31 @@ typedef struct cprng_request {
 int cprng_generate_requests(cprng_t *h, const cprng_request_t *reqs, uint32_t count,
                             cprng_stream_t stream);
 
+/* Serve a subset of the streams described in device memory (V0): descriptor
+ * k makes stream ids[k] write its next lens[k] outputs to out_base +
+ * out_offsets[k] (offsets in uint32 elements); streams not listed keep their
+ * state.  This is the per-thread generation of Algorithms 3 and 4 restricted
+ * to the listed streams, each with its own length, and it equals generating
+ * each listed stream alone.  ids (uint32), lens and out_offsets (uint64):
+ * device, count entries each, written by the caller's own kernels if it
+ * likes -- the host never reads them.  The descriptors are checked, counted
+ * and cut into chunks on the device (the same jumped-ahead chunks as
+ * cprng_generate_ragged, from a two-level jump table), so the call does no
+ * host round trip and, once a call of at least `count` descriptors has been
+ * made on `stream`, allocates nothing (it can then be captured in a hipGraph
+ * and replayed with new descriptor contents).  Lengths are at most 2^37; ids
+ * must be distinct within a call.  status: optional device int32 that
+ * receives, in stream order, 0 or CPRNG_E_INVAL when a descriptor is
+ * invalid (id >= n_streams, repeated id, length > 2^37); an invalid call
+ * writes no output and changes no state.  Calls on different HIP streams
+ * must list disjoint streams.  ids, lens and out_offsets must stay valid
+ * until the call has run.  Chunk length: tuning.chunk (at least 2048), else
+ * 2048.  Errors (host side): E_INVAL (NULL or misaligned pointers, count >
+ * n_streams, chunk below 2048), E_UNSUPPORTED (V1 .. V4), E_NOMEM, E_HIP. */
+int cprng_generate_subset(cprng_t *h, const uint32_t *ids, const uint64_t *lens,
+                          const uint64_t *out_offsets, uint32_t count, uint32_t *out_base,
+                          int32_t *status, cprng_stream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* State (checkpoint / resume).                                              */
 /* ------------------------------------------------------------------------ */

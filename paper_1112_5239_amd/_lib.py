@@ -58,7 +58,8 @@ class Tuning(C.Structure):
 
 EXPORTED = [
     "cprng_create", "cprng_create_ex", "cprng_destroy", "cprng_generate", "cprng_consume_qc",
-    "cprng_generate_ragged", "cprng_generate_ragged_noalloc", "cprng_generate_requests", "cprng_state_words", "cprng_state_bytes", "cprng_get_state",
+    "cprng_generate_ragged", "cprng_generate_ragged_noalloc", "cprng_generate_requests", "cprng_generate_subset",
+    "cprng_state_words", "cprng_state_bytes", "cprng_get_state",
     "cprng_set_state", "cprng_checkpoint_bytes", "cprng_checkpoint_save", "cprng_checkpoint_load",
     "cprng_n_streams", "cprng_variant", "cprng_default_combs", "cprng_default_bbs_combs", "cprng_jump_selftest",
     "cprng_set_tuning", "cprng_get_tuning", "cprng_autotune", "cprng_autotune_ragged",
@@ -92,6 +93,7 @@ def lib():
         "cprng_generate_ragged": (i32, [vp, vp, vp, vp, vp]),
         "cprng_generate_ragged_noalloc": (i32, [vp, vp, vp, vp, vp]),
         "cprng_generate_requests": (i32, [vp, C.POINTER(Request), u32, vp]),
+        "cprng_generate_subset": (i32, [vp, vp, vp, vp, u32, vp, vp, vp]),
         "cprng_state_words": (i32, [vp]),
         "cprng_state_bytes": (C.c_size_t, [vp]),
         "cprng_get_state": (i32, [vp, vp, C.c_size_t]),
@@ -222,6 +224,13 @@ def cprng_generate_requests(h: int, reqs, stream=None) -> None:
         arr[i].length = n
         arr[i].out = _addr(o)
     _check(lib().cprng_generate_requests(h, arr, len(reqs), _addr(stream)), "cprng_generate_requests")
+
+
+def cprng_generate_subset(h: int, ids, lens, out_offsets, count: int, out_base, status=None, stream=None) -> None:
+    """ids (uint32), lens and out_offsets (uint64): device addresses or tensors
+    of `count` entries; status: optional device int32 (address or tensor)."""
+    _check(lib().cprng_generate_subset(h, _addr(ids), _addr(lens), _addr(out_offsets), count, _addr(out_base),
+                                       _addr(status), _addr(stream)), "cprng_generate_subset")
 
 
 def cprng_state_bytes(h: int) -> int:

@@ -105,6 +105,7 @@ struct Seg {
     gu32 *out;             // first output of the segment
     uint32_t len, head, stream, last;
     const uint32_t *poly;  // nullptr: no jump (segment 0); else X^(k*chunk) mod q
+    const uint32_t *poly2; // two-level tables: the second factor of the jump, or nullptr
     uint32_t skip;         // steps after the jump: the run's head
     uint64_t pos;          // start position within the run
 };
@@ -129,6 +130,7 @@ __device__ __forceinline__ Seg decode_segment(const SegArgs &a, uint32_t idx)
         len = r.len < seg0 ? r.len : seg0;
         s.head = r.head;
         s.poly = nullptr;
+        s.poly2 = nullptr;
         s.skip = 0;
     } else {
         // position head + k*chunk: jump by k*chunk, then step head times
@@ -136,7 +138,14 @@ __device__ __forceinline__ Seg decode_segment(const SegArgs &a, uint32_t idx)
         const uint64_t left = r.len - s.pos;
         len = left < a.chunk ? left : a.chunk;
         s.head = 0;
-        s.poly = a.polys + 5ull * k;
+        if (a.polys_hi) {
+            const uint32_t klo = k & ((1u << a.lo_bits) - 1u), khi = k >> a.lo_bits;
+            s.poly = klo ? a.polys + 5ull * klo : nullptr;
+            s.poly2 = khi ? a.polys_hi + 5ull * khi : nullptr;
+        } else {
+            s.poly = a.polys + 5ull * k;
+            s.poly2 = nullptr;
+        }
         s.skip = r.head;
     }
     s.len = (uint32_t)len;
@@ -150,6 +159,7 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t ns = a.ns;
+    if (a.nseg_dev) a.nseg = (uint32_t)__builtin_amdgcn_readfirstlane((int)*a.nseg_dev);
     uint32_t qi = 0, base = 0, end = 0;
     while (grab_segments(a, lane, qi, base, end)) {
         const uint32_t idx = base + lane;
@@ -158,10 +168,9 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a)
             const uint32_t *p = a.state + d.stream;
             X128 g{p[0], p[ns], p[2 * ns], p[3 * ns]};
             uint32_t x = p[4 * ns];
-            if (d.poly) {
-                jump_v0(g, x, d.poly);
-                for (uint32_t i = 0; i < d.skip; ++i) x ^= x128_next(g);
-            }
+            if (d.poly) jump_v0(g, x, d.poly);
+            if (d.poly2) jump_v0(g, x, d.poly2);
+            for (uint32_t i = 0; i < d.skip; ++i) x ^= x128_next(g);
             gu32 *o = d.out;
             const uint32_t len = d.len;
             uint32_t i = 0;
@@ -227,6 +236,7 @@ __global__ __launch_bounds__(64) void k_segments_tile(SegArgs a)
     const uint32_t q = lane % QPR;           // quad a lane stores
     const uint32_t rsub = lane / QPR;        // row within an instruction's RPI rows
     const uint64_t ns = a.ns;
+    if (a.nseg_dev) a.nseg = (uint32_t)__builtin_amdgcn_readfirstlane((int)*a.nseg_dev);
     uint32_t qi = 0, base = 0, end = 0;
     while (grab_segments(a, lane, qi, base, end)) {
         const uint32_t idx = base + lane;
@@ -238,10 +248,9 @@ __global__ __launch_bounds__(64) void k_segments_tile(SegArgs a)
             const uint32_t *p = a.state + d.stream;
             g = X128{p[0], p[ns], p[2 * ns], p[3 * ns]};
             x = p[4 * ns];
-            if (d.poly) {
-                jump_v0(g, x, d.poly);
-                for (uint32_t i = 0; i < d.skip; ++i) x ^= x128_next(g);
-            }
+            if (d.poly) jump_v0(g, x, d.poly);
+            if (d.poly2) jump_v0(g, x, d.poly2);
+            for (uint32_t i = 0; i < d.skip; ++i) x ^= x128_next(g);
             const uint32_t head = d.head < d.len ? d.head : d.len;
             for (uint32_t i = 0; i < head; ++i) {
                 x ^= x128_next(g);
@@ -331,6 +340,134 @@ __global__ void k_commit(uint32_t *state, const uint32_t *state_next, const uint
     const uint64_t id = ids[i];
 #pragma unroll
     for (int k = 0; k < 5; ++k) state[k * (uint64_t)ns + id] = state_next[k * (uint64_t)ns + id];
+}
+
+// ------------------------------------------------------------------------
+// Stream subsets described in device memory (ids, lengths and output offsets
+// that the caller's kernels may have written).  Three small kernels turn the
+// descriptors into the run list of the segment kernels above with no host
+// round trip:
+//   k_subset_count  checks each descriptor and counts its segments, with one
+//                   sum per block of 256 descriptors;
+//   k_subset_scan   (one workgroup) turns the block sums into offsets,
+//                   decides the call's status, resets the work-queue
+//                   counters and moves to the next call epoch;
+//   k_subset_runs   writes the run descriptors.
+// A repeated stream id is caught with a per-stream mark: each descriptor
+// swaps the call's epoch into its stream's mark, and a swap that returns that
+// same epoch means another descriptor of the call named the stream first.
+// After an error the segment count is 0 and the commit is skipped, so no
+// output is written and no state changes.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t subset_head(uint64_t addr) { return (64u - (uint32_t)((addr >> 2) & 63u)) & 63u; }
+
+__global__ __launch_bounds__(256) void k_subset_count(SubsetArgs a)
+{
+    __shared__ unsigned long long part[4];
+    const uint32_t t = threadIdx.x, lane = t & 63u;
+    const uint32_t i = blockIdx.x * 256u + t;
+    uint32_t nseg = 0;
+    bool bad = false;
+    if (i < a.count) {
+        const uint32_t id = a.ids[i];
+        const uint64_t len = a.lens[i];
+        if (id >= a.ns || len > kSubsetMaxLen) {
+            bad = true;
+        } else {
+            const unsigned long long ep = a.ctl->epoch;
+            if (atomicExch(a.mark + id, ep) == ep) bad = true;
+            if (len) {
+                const uint64_t seg0 = (uint64_t)subset_head(a.out_base + 4ull * a.offs[i]) + a.chunk;
+                nseg = len <= seg0 ? 1u : (uint32_t)(1u + (len - seg0 + a.chunk - 1u) / a.chunk);
+            }
+        }
+        a.segs[i] = nseg;
+    }
+    if (bad) atomicOr(&a.ctl->err, 1u);
+    unsigned long long v = nseg;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    if (lane == 0) part[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) a.bsum[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
+__global__ __launch_bounds__(1024) void k_subset_scan(SubsetArgs a)
+{
+    __shared__ unsigned long long wsum[16];
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    unsigned long long carry = 0;
+    for (uint32_t base = 0; base < a.nblocks; base += 1024u) {
+        const uint32_t i = base + t;
+        const unsigned long long v = i < a.nblocks ? a.bsum[i] : 0ull;
+        unsigned long long inc = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const unsigned long long o = __shfl_up(inc, d);
+            if (lane >= (uint32_t)d) inc += o;
+        }
+        if (lane == 63u) wsum[w] = inc;
+        __syncthreads();
+        unsigned long long before = 0, total = 0;
+        for (uint32_t k = 0; k < 16u; ++k) {
+            if (k < w) before += wsum[k];
+            total += wsum[k];
+        }
+        if (i < a.nblocks) a.bsum[i] = carry + before + inc - v;
+        carry += total;
+        __syncthreads();
+    }
+    if (t == 0) {
+        const bool ok = a.ctl->err == 0u && carry < (1ull << 31);
+        const int32_t st = ok ? 0 : (int32_t)CPRNG_E_INVAL;
+        a.ctl->nseg = ok ? (uint32_t)carry : 0u;
+        a.ctl->status = st;
+        if (a.status) *a.status = st;
+        a.ctl->err = 0u;
+        a.ctl->epoch = a.ctl->epoch + 1ull;
+    }
+    if (t < 8u) a.ctl->counter[t] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_subset_runs(SubsetArgs a)
+{
+    if (a.ctl->status != 0) return;
+    __shared__ uint32_t part[4];
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    const uint32_t i = blockIdx.x * 256u + t;
+    // With the status clear the call has fewer than 2^31 segments, so every
+    // prefix below fits 32 bits.
+    const uint32_t v = i < a.count ? a.segs[i] : 0u;
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d);
+        if (lane >= (uint32_t)d) inc += o;
+    }
+    if (lane == 63u) part[w] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t k = 0; k < w; ++k) before += part[k];
+    if (i < a.count) {
+        RunDesc r;
+        r.out = a.out_base + 4ull * a.offs[i];
+        r.len = a.lens[i];
+        r.stream = a.ids[i];
+        r.head = subset_head(r.out);
+        r.first_seg = (uint32_t)a.bsum[blockIdx.x] + before + inc - v;
+        r.last = 1u;
+        a.runs[i] = r;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_subset_commit(SubsetArgs a, uint32_t *state, const uint32_t *state_next)
+{
+    if (a.ctl->status != 0) return;
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= a.count || a.lens[i] == 0) return;
+    const uint64_t id = a.ids[i], ns = a.ns;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) state[k * ns + id] = state_next[k * ns + id];
 }
 
 __global__ void k_zero_u32(uint32_t *p, uint32_t count)
@@ -485,6 +622,23 @@ hipError_t launch_segments(const SegArgs &a, uint32_t grid, uint32_t block, uint
     case 32: hipLaunchKernelGGL((k_segments<32>), dim3(grid), dim3(block), 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_subset(const SubsetArgs &sa, const SegArgs &a, uint32_t grid, uint32_t block, uint32_t store,
+                         uint32_t *state, hipStream_t st)
+{
+    if (sa.count == 0 || sa.nblocks != (sa.count + 255u) / 256u || !a.nseg_dev || !a.persistent)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_subset_count, dim3(sa.nblocks), dim3(256), 0, st, sa);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_subset_scan, dim3(1), dim3(1024), 0, st, sa);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_subset_runs, dim3(sa.nblocks), dim3(256), 0, st, sa);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_segments(a, grid, block, store, 0, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_subset_commit, dim3(sa.nblocks), dim3(256), 0, st, sa, state, a.state_next);
     return hipGetLastError();
 }
 

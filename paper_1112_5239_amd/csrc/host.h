@@ -92,6 +92,12 @@ struct ReqSlot {
     void *h_stage = nullptr;            // pinned staging of d_buf
     size_t buf_cap = 0;
     hipEvent_t ev_stage = nullptr;      // the previous upload has completed
+    uint32_t index = 0;                 // slot number (top byte of its subset call epochs)
+    // subset calls: control block and grow-only work buffers (segment counts,
+    // block sums, run descriptors for sub_cap descriptors)
+    SubsetCtl *d_sub_ctl = nullptr;
+    void *d_sub_buf = nullptr;
+    uint32_t sub_cap = 0;
 };
 void destroy_req_slots(cprng_t *h);
 
@@ -127,6 +133,10 @@ struct cprng {
     // jump tables X^(h + k*chunk) for requests, per chunk length
     std::unordered_map<uint32_t, uint32_t> req_poly_kcap;
     std::unordered_map<uint32_t, uint32_t *> d_req_poly_tables;
+    // subset calls: per-stream marks (epoch of the last call listing the
+    // stream) and the two-level jump tables, per chunk length
+    unsigned long long *d_sub_mark = nullptr;
+    std::unordered_map<uint32_t, uint32_t *> d_sub_tables;
 
     // group jump-ahead (V2/V4 batched uneven runs): minimal polynomial of the
     // group's one-step map and grow-only work buffers

@@ -197,7 +197,54 @@ struct SegArgs {
     uint32_t *counter;     // work-queue counters, one per XCD (8 words, reset before each launch)
     uint32_t unroll;       // outputs per lane per round
     uint32_t persistent;   // 1: waves take grabs from the queues; 0: one grab per wave, by workgroup id
+    // Device-planned launches (stream subsets): when set, the segment count
+    // is read from *nseg_dev at kernel start instead of nseg.
+    const uint32_t *nseg_dev;
+    // Two-level jump table: when set, segment k jumps by (k mod 2^lo_bits) *
+    // chunk with polys and by (k >> lo_bits) * 2^lo_bits * chunk with
+    // polys_hi (the two maps commute), so k is bounded by 2^(2 lo_bits)
+    // whatever the run lengths.
+    const uint32_t *polys_hi;
+    uint32_t lo_bits;
 };
+
+// Stream subsets described in device memory (cprng_generate_subset).
+constexpr uint64_t kSubsetMaxLen = 1ull << 37;   // outputs per descriptor
+constexpr uint32_t kSubsetLoBits = 13;           // jump table: 2 x 2^13 rows
+constexpr uint32_t kSubsetMinChunk = 2048;       // (2^37 / 2048 = 2^26 segments per run)
+
+// Per-call control block of a subset launch, in device memory.
+struct SubsetCtl {
+    unsigned long long epoch;  // this call's stream mark (unique per slot and call)
+    uint32_t err;              // set when a descriptor is invalid
+    uint32_t nseg;             // segments of the call (0 after an error)
+    int32_t status;            // 0 or CPRNG_E_INVAL
+    uint32_t pad[3];
+    uint32_t counter[8];       // work-queue counters of the segment kernel
+};
+
+struct SubsetArgs {
+    const uint32_t *ids;       // count stream ids (device)
+    const uint64_t *lens;      // count lengths (device)
+    const uint64_t *offs;      // count output offsets in uint32 elements (device)
+    uint32_t count;
+    uint32_t ns;
+    uint32_t chunk;
+    uint32_t nblocks;          // blocks of 256 descriptors
+    uint64_t out_base;         // device address of the output base
+    unsigned long long *mark;  // ns entries: the epoch of the last call that listed the stream
+    SubsetCtl *ctl;
+    uint32_t *segs;            // count: segments per descriptor
+    unsigned long long *bsum;  // nblocks: segments per block, then their exclusive prefix
+    RunDesc *runs;             // count run descriptors
+    int32_t *status;           // caller's status word (device) or nullptr
+};
+
+// Plan a subset call on the device (check, count, scan, run list), then the
+// segment kernel with a.nseg_dev / a.counter pointing into sa.ctl, then the
+// commit of the listed streams' end states (skipped after an error).
+hipError_t launch_subset(const SubsetArgs &sa, const SegArgs &a, uint32_t grid, uint32_t block, uint32_t store,
+                         uint32_t *state, hipStream_t st);
 
 // lds_min: dynamic LDS per workgroup at least this (caps residency).
 hipError_t launch_segments(const SegArgs &a, uint32_t grid, uint32_t block, uint32_t store, uint32_t lds_min,

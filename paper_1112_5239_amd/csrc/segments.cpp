@@ -351,12 +351,18 @@ void destroy_req_slots(cprng_t *h)
         if (r->d_buf) (void)hipFree(r->d_buf);
         if (r->h_stage) (void)hipHostFree(r->h_stage);
         if (r->ev_stage) (void)hipEventDestroy(r->ev_stage);
+        if (r->d_sub_ctl) (void)hipFree(r->d_sub_ctl);
+        if (r->d_sub_buf) (void)hipFree(r->d_sub_buf);
         delete r;
     }
     h->req_slots.clear();
     for (auto &kv : h->d_req_poly_tables) (void)hipFree(kv.second);
     h->d_req_poly_tables.clear();
     h->req_poly_kcap.clear();
+    for (auto &kv : h->d_sub_tables) (void)hipFree(kv.second);
+    h->d_sub_tables.clear();
+    if (h->d_sub_mark) (void)hipFree(h->d_sub_mark);
+    h->d_sub_mark = nullptr;
 }
 
 int ragged_with(cprng_t *h, uint32_t *out, const uint64_t *lengths, const uint64_t *offsets,
@@ -636,6 +642,7 @@ ReqSlot *find_slot(cprng_t *h, hipStream_t st, int *rc)
     }
     ReqSlot *r = new ReqSlot();
     r->stream = st;
+    r->index = (uint32_t)h->req_slots.size();
     if (hipMalloc(&r->d_counter, 64) != hipSuccess ||
         hipEventCreateWithFlags(&r->ev_stage, hipEventDisableTiming) != hipSuccess) {
         if (r->d_counter) (void)hipFree(r->d_counter);
@@ -773,6 +780,162 @@ extern "C" int cprng_generate_requests(cprng_t *h, const cprng_request_t *reqs, 
                               (uint32_t)ids[j].size(), h->ns, st);
     }
     if (e != hipSuccess) return hip_error(e, "request kernels");
+    if (h->timing) {
+        if (hipEventRecord(h->ev1, st) != hipSuccess) return set_error(CPRNG_E_HIP, "hipEventRecord");
+        h->ev_pending = true;
+    }
+    return CPRNG_OK;
+}
+
+namespace {
+
+// Chunking of subset calls: the handle's tuning over the batched default, in
+// a persistent store mode (the launch grid cannot follow a segment count
+// that only the device knows).
+SegCfg subset_cfg(const cprng_t *h)
+{
+    SegCfg c = kDefaultSeg;
+    if (h->tuning.chunk) c.chunk = h->tuning.chunk;
+    if (h->tuning.waves_per_cu) c.waves = h->tuning.waves_per_cu;
+    if (h->tuning.unroll) c.unroll = h->tuning.unroll;
+    if (h->tuning.block) c.block = h->tuning.block;
+    if (h->tuning.store) c.store = h->tuning.store == ST_DIRECT_NT ? (uint32_t)ST_DIRECT : h->tuning.store;
+    normalize(c);
+    if (!seg_persistent(c)) c.store = seg_kernel_store(c);
+    return c;
+}
+
+// Jump tables of subset calls for one chunk length, one allocation: rows
+// X^(k * chunk) mod q, then rows X^(k * 2^13 * chunk) mod q, k < 2^13, five
+// words each.
+int subset_tables(cprng_t *h, uint32_t chunk, const uint32_t **lo, const uint32_t **hi)
+{
+    const uint32_t rows = 1u << kSubsetLoBits;
+    auto it = h->d_sub_tables.find(chunk);
+    if (it == h->d_sub_tables.end()) {
+        std::vector<uint32_t> tab;
+        jump_table(chunk, rows, tab);
+        tab.resize((size_t)rows * 10u);
+        const JPoly step = jump_xpow((uint64_t)chunk << kSubsetLoBits);
+        JPoly r = jump_one();
+        for (uint32_t k = 0; k < rows; ++k) {
+            jump_pack(r, &tab[(size_t)(rows + k) * 5u]);
+            r = jump_mul(r, step);
+        }
+        uint32_t *d = nullptr;
+        if (hipMalloc(&d, tab.size() * sizeof(uint32_t)) != hipSuccess)
+            return set_error(CPRNG_E_NOMEM, "hipMalloc subset jump table");
+        if (hipMemcpy(d, tab.data(), tab.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(d);
+            return set_error(CPRNG_E_HIP, "hipMemcpy subset jump table");
+        }
+        it = h->d_sub_tables.emplace(chunk, d).first;
+    }
+    *lo = it->second;
+    *hi = it->second + (size_t)rows * 5u;
+    return CPRNG_OK;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Byte offsets in a slot's subset buffer for cap descriptors: segment counts,
+// block sums, run descriptors.
+void subset_layout(uint32_t cap, size_t *off_bsum, size_t *off_runs, size_t *total)
+{
+    *off_bsum = align_up((size_t)cap * 4u, 256);
+    *off_runs = align_up(*off_bsum + (size_t)((cap + 255u) / 256u) * 8u, 256);
+    *total = *off_runs + (size_t)cap * sizeof(RunDesc);
+}
+
+// The handle's stream marks and the slot's control block and buffers for
+// count descriptors.  Allocates only on a slot's first call and when count
+// exceeds every earlier call's.
+int subset_buffers(cprng_t *h, ReqSlot *slot, uint32_t count)
+{
+    if (!h->d_sub_mark) {
+        if (hipMalloc(&h->d_sub_mark, (size_t)h->ns * 8u) != hipSuccess)
+            return set_error(CPRNG_E_NOMEM, "hipMalloc subset marks");
+        if (hipMemset(h->d_sub_mark, 0, (size_t)h->ns * 8u) != hipSuccess)
+            return set_error(CPRNG_E_HIP, "hipMemset subset marks");
+    }
+    if (!slot->d_sub_ctl) {
+        SubsetCtl c;
+        std::memset(&c, 0, sizeof c);
+        c.epoch = ((unsigned long long)(slot->index + 1u) << 56) | 1ull;   // never 0, the marks' initial value
+        if (hipMalloc(&slot->d_sub_ctl, sizeof c) != hipSuccess)
+            return set_error(CPRNG_E_NOMEM, "hipMalloc subset control block");
+        if (hipMemcpy(slot->d_sub_ctl, &c, sizeof c, hipMemcpyHostToDevice) != hipSuccess)
+            return set_error(CPRNG_E_HIP, "hipMemcpy subset control block");
+    }
+    if (count > slot->sub_cap) {
+        if (slot->d_sub_buf) (void)hipFree(slot->d_sub_buf);   // hipFree waits for the device
+        slot->d_sub_buf = nullptr;
+        slot->sub_cap = 0;
+        const uint32_t cap = (uint32_t)std::min<uint64_t>(h->ns, std::max<uint64_t>(1024u, 2ull * count));
+        size_t ob, orr, total;
+        subset_layout(cap, &ob, &orr, &total);
+        if (hipMalloc(&slot->d_sub_buf, total) != hipSuccess) return set_error(CPRNG_E_NOMEM, "hipMalloc subset buffers");
+        slot->sub_cap = cap;
+    }
+    return CPRNG_OK;
+}
+
+}  // namespace
+
+extern "C" int cprng_generate_subset(cprng_t *h, const uint32_t *ids, const uint64_t *lens,
+                                     const uint64_t *out_offsets, uint32_t count, uint32_t *out_base,
+                                     int32_t *status, cprng_stream_t stream)
+{
+    if (!h) return set_error(CPRNG_E_INVAL, "NULL handle");
+    if (h->variant != CPRNG_V0_PLAIN)
+        return set_error(CPRNG_E_UNSUPPORTED, "subsets need the V0 variant (per-stream jump-ahead planned on the device)");
+    if (count == 0) return CPRNG_OK;
+    if (!ids || !lens || !out_offsets || !out_base) return set_error(CPRNG_E_INVAL, "NULL argument");
+    if ((uintptr_t)ids % 4u || (uintptr_t)lens % 8u || (uintptr_t)out_offsets % 8u || (uintptr_t)out_base % 4u ||
+        (uintptr_t)status % 4u)
+        return set_error(CPRNG_E_INVAL, "misaligned argument (ids, out_base, status: 4 bytes; lens, offsets: 8)");
+    if (count > h->ns) return set_error(CPRNG_E_INVAL, "more descriptors than streams (a stream id would repeat)");
+    DevGuard g(h->device);
+    int rc = ensure_common(h);
+    if (rc) return rc;
+    const SegCfg c = subset_cfg(h);
+    if (c.chunk % 64u || c.chunk < kSubsetMinChunk)
+        return set_error(CPRNG_E_INVAL, "subset calls need a chunk length of at least 2048, a multiple of 64");
+    const uint32_t *lo = nullptr, *hi = nullptr;
+    if ((rc = subset_tables(h, c.chunk, &lo, &hi))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    ReqSlot *slot = find_slot(h, st, &rc);
+    if (!slot) return rc;
+    if ((rc = subset_buffers(h, slot, count))) return rc;
+
+    size_t ob, orr, total;
+    subset_layout(slot->sub_cap, &ob, &orr, &total);
+    char *buf = (char *)slot->d_sub_buf;
+    SubsetArgs sa;
+    std::memset(&sa, 0, sizeof sa);
+    sa.ids = ids;
+    sa.lens = lens;
+    sa.offs = out_offsets;
+    sa.count = count;
+    sa.ns = h->ns;
+    sa.chunk = c.chunk;
+    sa.nblocks = (count + 255u) / 256u;
+    sa.out_base = (uint64_t)(uintptr_t)out_base;
+    sa.mark = h->d_sub_mark;
+    sa.ctl = slot->d_sub_ctl;
+    sa.segs = (uint32_t *)buf;
+    sa.bsum = (unsigned long long *)(buf + ob);
+    sa.runs = (RunDesc *)(buf + orr);
+    sa.status = status;
+    SegArgs a = seg_args(h, c, sa.runs, count, 0, 1u << kSubsetLoBits, lo, slot->d_sub_ctl->counter);
+    a.nseg_dev = &slot->d_sub_ctl->nseg;
+    a.polys_hi = hi;
+    a.lo_bits = kSubsetLoBits;
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1u, (uint64_t)h->n_cu * c.waves / (c.block / 64u));
+
+    if (h->timing && hipEventRecord(h->ev0, st) != hipSuccess) return set_error(CPRNG_E_HIP, "hipEventRecord");
+    const hipError_t e = launch_subset(sa, a, grid, c.block, seg_kernel_store(c), h->d_state, st);
+    if (e != hipSuccess) return hip_error(e, "subset kernels");
     if (h->timing) {
         if (hipEventRecord(h->ev1, st) != hipSuccess) return set_error(CPRNG_E_HIP, "hipEventRecord");
         h->ev_pending = true;

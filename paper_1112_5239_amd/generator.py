@@ -99,6 +99,13 @@ class Generator:
         """reqs: list of (stream_id, length, out_tensor_or_address)."""
         L.cprng_generate_requests(self.h, reqs, _stream(stream))
 
+    def generate_subset(self, ids, lens, out_offsets, out, status=None, stream=None):
+        """Device-described subset (cprng_generate_subset): ids (int32 tensor
+        viewed as uint32), lens and out_offsets (int64 tensors) on the device,
+        out the uint32 output base, status an optional one-element int32
+        device tensor."""
+        L.cprng_generate_subset(self.h, ids, lens, out_offsets, int(ids.numel()), out, status, _stream(stream))
+
     # -- state ----------------------------------------------------------------
     def state_words(self) -> int:
         return L.cprng_state_words(self.h)

@@ -152,3 +152,11 @@ def test_tuning_queries_and_replay_reject_null_before_device_work(L):
                                         keep.ctypes.data, res) == L.E_INVAL
     assert lib.cprng_autotune(None, None, 64, None) == L.E_INVAL
     assert lib.cprng_autotune_ragged(None, None, lengths.ctypes.data, None, None) == L.E_INVAL
+
+
+def test_subset_rejects_null_handle_before_device_work(L):
+    lib = L.lib()
+    z64 = np.zeros(1, dtype=np.uint64)
+    z32 = np.zeros(1, dtype=np.uint32)
+    assert lib.cprng_generate_subset(None, z32.ctypes.data, z64.ctypes.data, z64.ctypes.data, 1,
+                                     z32.ctypes.data, None, None) == L.E_INVAL

@@ -18,6 +18,9 @@ and in the launch configuration it uses (default tuning, automatic chunk length)
 - Batched uneven runs of the exchange variant (V2) in 128 groups of 32 with
   log-uniform group lengths: a 1% sample of groups plus the longest and shortest,
   over two calls, and their end states.
+- The plain variant's batched workload (4,096 streams, the same lengths) as a
+  device-described subset: a 1% sample plus the longest and shortest streams,
+  over two calls, and their end states.
 """
 import numpy as np
 import pytest
@@ -179,6 +182,42 @@ def test_batched_v2_groups_full_workload_auto_chunk(orc, G, torch, tuned):
                 assert bad.size == 0, f"call {call} group {gi} (length {L}): first mismatch {bad[:3].tolist()}"
         rows = np.concatenate([np.arange(int(gi) * Cg, (int(gi) + 1) * Cg) for gi in groups])
         assert np.array_equal(g.get_state()[rows], st[rows]), "end states differ"
+        del out
+    finally:
+        g.close()
+
+
+def test_batched_v0_device_subset_full_workload(orc, G, torch):
+    # The batched workload's 4,096 runs as a device-described subset
+    # (cprng_generate_subset, default tuning), as the benchmark's ragged leg
+    # times it: a 1% sample plus the longest and shortest streams, two calls.
+    from paper_1112_5239_amd import workloads
+    lengths = workloads.ragged_lengths()
+    ns = lengths.size
+    offs = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.uint64)
+    total = int(lengths.sum())
+    g = G.Generator(ns, "v0", seed=2)
+    try:
+        out = torch.empty(total, dtype=torch.int32, device="cuda")
+        ids = torch.arange(ns, dtype=torch.int32, device="cuda")
+        lens = torch.tensor(lengths.astype(np.int64), device="cuda")
+        t_offs = torch.cumsum(lens, 0) - lens
+        status = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+        pick = _stream_sample(lengths, 0.01, 103)
+        st = orc.seed(0, 2, 0, ns)
+        for call in range(2):
+            g.generate_subset(ids, lens, t_offs, out, status)
+            torch.cuda.synchronize()
+            assert int(status.item()) == 0
+            for s in pick:
+                o, L = int(offs[s]), int(lengths[s])
+                got = G.as_u32(out[o:o + L])
+                one = st[s:s + 1].copy()
+                want, _ = orc.generate(0, one, L)
+                st[s] = one[0]
+                bad = np.flatnonzero(got != want[0])
+                assert bad.size == 0, f"call {call} stream {s} (length {L}): first mismatch at {bad[:3].tolist()}"
+        assert np.array_equal(g.get_state()[pick], st[pick]), "end states differ"
         del out
     finally:
         g.close()
