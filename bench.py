@@ -56,7 +56,8 @@ LANES_FAST, LANES_SHIFT = 128, 64
 ALU_MIX = {
     "v0_consume": (233 / 16, 33 / 16),      # k_consume<0, u32, 16>
     "v2_consume": (265 / 16, 33 / 16),      # k_consume<2, u32, 16>
-    "v1_generate": (1257 / 32, 360 / 32),   # k_generate_ilv<1, u64, 32, 256, NT>: 28 xor + 11.25 64-bit
+    "v1_generate": (1081 / 32, 400 / 32),   # k_generate_ilv<1, u64, 32, 256, NT>: 14 xor + 7 xor3 + 9 64-bit
+                                            # shifts + 2.5 64-bit adds + 1 add3
     "v3_generate": (2181 / 16, 436 / 16),   # k_generate_ilv<3, u32, 16, 512, NT, LDS exchange>
     "v3_consume": (2281 / 16, 449 / 16),    # k_consume<3, u32, 16>
 }
