@@ -251,7 +251,8 @@ int cprng_generate_requests(cprng_t *h, const cprng_request_t *reqs, uint32_t co
  * must be distinct within a call.  status: optional device int32 that
  * receives, in stream order, 0 or CPRNG_E_INVAL when a descriptor is
  * invalid (id >= n_streams, repeated id, length > 2^37); an invalid call
- * writes no output and changes no state.  Calls on different HIP streams
+ * writes no output and changes no state.  A call with count 0 does nothing
+ * and leaves status untouched.  Calls on different HIP streams
  * must list disjoint streams.  ids, lens and out_offsets must stay valid
  * until the call has run.  Chunk length: tuning.chunk (at least 2048), else
  * 2048.  Errors (host side): E_INVAL (NULL or misaligned pointers, count >
