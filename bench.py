@@ -70,12 +70,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_sha():
+def headline_launch_key(cfg):
+    """The headline's resolved launch configuration as text (which template of
+    the kernel runs: tile, round, store mode, buffers, exchange, residency)."""
+    return ",".join(f"{k}={cfg[k]}" for k in ("block", "unroll", "store", "waves_per_cu",
+                                               "streams_per_lane", "exchange"))
+
+
+def kernel_source_sha(launch_key=""):
     """Hash of the sources the headline kernel (k_generate_ilv of the exchange
     variant) is built from: its template and launch code, the device helpers,
-    the variant's instantiation unit and the kernel-argument struct."""
+    the variant's instantiation unit and the kernel-argument struct, plus the
+    launch configuration that selects the template's instance."""
     csrc = os.path.join(ROOT, "paper_1112_5239_amd", "csrc")
     h = hashlib.sha256()
+    h.update(b"launch\0" + launch_key.encode())
     for name in ("device_common.inc", "gen_kernels.inc", "gen_v2.hip"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
@@ -86,9 +95,9 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_tag):
+def traffic_from_profile(kernel_tag, launch_key):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
-    taken on the current kernel source; else None."""
+    taken on the current kernel source and launch configuration; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}.txt")
     if not os.path.exists(path):
         return None
@@ -98,7 +107,7 @@ def traffic_from_profile(kernel_tag):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha") != kernel_source_sha():
+    if vals.get("kernel_source_sha") != kernel_source_sha(launch_key):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -606,6 +615,8 @@ def main():
     log(f"[bench] paper: {ms:.4f} ms/step ({kernel_ms:.4f} ms per launch), {value:.1f} Gnumbers/s, "
         f"{achieved:.0f} GB/s")
     extra["headline_launch_ms"] = [round(x, 4) for x in launches]
+    launch_key = headline_launch_key(g.resolved_tuning(n))
+    log(f"[bench] headline launch: {launch_key}")
     if args.copy_probe:
         run_copy_probe(torch, L)
     g.close()
@@ -643,7 +654,7 @@ def main():
                                   else "the first launches after idle"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profile("k_generate_ilv_v2_paper"),
+                     "traffic": traffic_from_profile("k_generate_ilv_v2_paper", launch_key),
                      "algorithmic_bytes_per_launch": alg_bytes, "kernel_ms": round(kernel_ms, 5)},
         "cpu_baseline": cpu,
         "extra": extra,
