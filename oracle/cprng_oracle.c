@@ -57,10 +57,10 @@
  *     xor of the two 32-bit halves of each 64-bit output, the convention
  *     Listing 1 applies to its 64-bit generators.
  *
- * Parity unpinned: the SplitMix64 multiplier constants (no known-answer value
- * is printed in the paper) and the order of the xor64 triple, (13,7,17)
- * rather than its mirror (17,7,13), which is also full period; everything
- * else is pinned by the test suite.
+ * Parity unpinned: the order of the xor64 triple, (13,7,17) rather than its
+ * mirror (17,7,13), which is also full period, and the order in which the
+ * seeding draws fill the state words; everything else is pinned by the test
+ * suite (SplitMix64 by its published outputs from state 0).
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared (no fast-math).
  */

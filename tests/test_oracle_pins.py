@@ -175,9 +175,19 @@ def test_xorshift64_13_17_5_reduces_to_alg2_on_low_word_prefix(orc):
 
 # --------------------------------------------------------------------------
 # SplitMix64 seeding (stands in for ISAAC, Section 6.1).  Pins: the increment
-# is the odd integer nearest 2^64/phi; the finaliser is a bijection.  The two
-# multiplier constants are parity unpinned (no printed known answer).
+# is the odd integer nearest 2^64/phi; the finaliser is a bijection; the first
+# outputs from state 0 equal SplitMix64's published known-answer sequence,
+# which fixes the finaliser's shifts and multipliers.
 # --------------------------------------------------------------------------
+def test_splitmix_known_answer_from_state_zero(orc):
+    # The first three outputs of SplitMix64 (Steele, Lea and Flood, OOPSLA
+    # 2014) started from state 0, as its reference implementation produces
+    # them and as implementations commonly check them.
+    want = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    assert [int(v) for v in orc.sm64_draws(0, 3)] == want
+
+
+
 def test_splitmix_gamma_is_golden_ratio(orc):
     getcontext().prec = 60
     phi = (1 + Decimal(5).sqrt()) / 2
