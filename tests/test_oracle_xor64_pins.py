@@ -3,8 +3,10 @@ as each thread's generator, the generator Section 7 names for its optimized
 versions) and the xor64 alternative for Listing 1's first generator (V1 with
 the F_XOR64 flag).
 
-The xor64 triple is pinned by the primitivity of the recurrence its output
-bits obey (a mistyped shift almost surely breaks it); the V4 wiring by a
+The xor64 triple is pinned by the first outputs of Marsaglia's own xor64
+example (which also fixes the order of the shifts against the full-period
+mirror triple) and by the primitivity of the recurrence its output bits obey
+(a mistyped shift almost surely breaks it); the V4 wiring by a
 brute-force lockstep simulation of Algorithm 4, the cancellation of equal
 combination arrays and GF(2) linearity; the V1 alternative by composing the
 three generators run alone.
@@ -21,6 +23,15 @@ V4 = 4
 def _xor64_words(orc, y0, n):
     out, _ = orc.gen_outputs(3, 64, [int(y0)], n)
     return out.astype(np.uint64)
+
+
+def test_xor64_marsaglia_example_outputs(orc):
+    # Marsaglia, "Xorshift RNGs" (2003): xor64 with shifts left 13, right 7,
+    # left 17 from the seed 88172645463325252, whose first outputs are
+    # 8748534153485358512, 3040900993826735515, 3453997556048239312; the
+    # mirror triple (17, 7, 13) gives other numbers from the first step.
+    out = _xor64_words(orc, 88172645463325252, 3)
+    assert [int(v) for v in out] == [8748534153485358512, 3040900993826735515, 3453997556048239312]
 
 
 def test_xor64_primitive_degree_64(orc):
