@@ -91,14 +91,31 @@ def test_alg2_xorshift32_full_period(orc):
     assert not hit_zero
 
 
+def test_xorshift32_marsaglia_example_outputs(orc):
+    # Marsaglia, "Xorshift RNGs" (2003): the 32-bit xorshift with shifts left
+    # 13, right 17, left 5 from its example seed 2463534242 gives
+    # 723471715, 2497366906, 2064144800 first.
+    out, _ = orc.gen_outputs(0, 32, [2463534242], 3)
+    assert [int(v) for v in out] == [723471715, 2497366906, 2064144800]
+
+
 # --------------------------------------------------------------------------
 # Marsaglia's xor128 and xorwow with 32-bit words (Section 6.2 uses xor128 with
-# 32-bit words): the output bit sequences satisfy a primitive recurrence of
-# full degree, which gives the published periods 2^128-1 and (2^160-1)2^32.
-# A wrongly remembered shift constant almost surely breaks primitivity.
+# 32-bit words): xor128 reproduces the first outputs of Marsaglia's published
+# example, and the output bit sequences satisfy a primitive recurrence of full
+# degree, which gives the published periods 2^128-1 and (2^160-1)2^32.  A
+# wrongly remembered shift constant almost surely breaks primitivity.
 # --------------------------------------------------------------------------
 def _bits(words, b):
     return [int((int(w) >> b) & 1) for w in words]
+
+
+def test_xor128_32_marsaglia_example_outputs(orc):
+    # Marsaglia's xor128 from the example seeds x, y, z, w = 123456789,
+    # 362436069, 521288629, 88675123 gives 3701687786, 458299110, 2500872618
+    # first.
+    out, _ = orc.gen_outputs(1, 32, [123456789, 362436069, 521288629, 88675123], 3)
+    assert [int(v) for v in out] == [3701687786, 458299110, 2500872618]
 
 
 def test_xor128_32_primitive_degree_128(orc):
