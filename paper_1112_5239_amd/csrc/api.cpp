@@ -173,6 +173,39 @@ int create_impl(const cprng_params_t *p, cprng_t **out)
     return CPRNG_OK;
 }
 
+// Stream-major generate with few streams.  The defaults of default_entry()
+// suit 2^18 streams and more; fewer streams leave CUs idle and each wave's
+// latency exposed.  Measured on MI355X at 1,024 outputs per stream: up to one
+// wave per CU, one-wave blocks storing their own quads beat the LDS tiles
+// (1,024 streams: V0 0.016 vs 0.033 ms, V1 0.063 vs 0.081, V2 0.040 vs
+// 0.063); up to four waves per CU, one-wave LDS tiles of 32 steps (V0 0.041
+// vs 0.079 ms, V2 0.064 vs 0.071 at 2^16 streams) and, for V1, direct stores
+// of 16 steps (0.094 vs 0.106 ms).  The BBS variant keeps its defaults.
+void small_shape_defaults(const cprng_t *h, LaunchCfg &c, TuneEntry &e)
+{
+    if (h->variant == CPRNG_V3_BBS || (h->flags & CPRNG_F_INTERLEAVED)) return;
+    const uint64_t ns = h->ns, cu = h->n_cu ? h->n_cu : 256u;
+    if (ns <= cu * 64u) {
+        c.block = 64; c.unroll = 32; c.store = ST_DIRECT;
+    } else if (ns <= cu * 256u) {
+        c.block = 64;
+        if (h->variant == CPRNG_V1_NAIVE3) { c.unroll = 16; c.store = ST_DIRECT; }
+        else { c.unroll = 32; c.store = ST_LDS; }
+    } else {
+        return;
+    }
+    e.block = c.block; e.unroll = c.unroll; e.store = c.store; e.waves = 0;
+}
+
+// The default entry of a stream-major generate call on this handle.
+TuneEntry default_generate_entry(const cprng_t *h)
+{
+    LaunchCfg c = default_cfg(h->variant, (h->flags & CPRNG_F_V1_W32) != 0, false);
+    TuneEntry e = default_entry(h->variant, false);
+    small_shape_defaults(h, c, e);
+    return e;
+}
+
 // Launch configuration of a generate / consume call: the library's defaults,
 // then the autotuner's entry for the shape class, then cprng_set_tuning's
 // fields.  defaults_only: the defaults alone.
@@ -229,6 +262,7 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume, bool defaults_only =
     }
     LaunchCfg c = default_cfg(h->variant, (h->flags & CPRNG_F_V1_W32) != 0, consume);
     TuneEntry e = default_entry(h->variant, consume);
+    if (!consume) small_shape_defaults(h, c, e);
     if (defaults_only) {
         c.lds_bytes = (c.store == ST_PIPE || c.store == ST_PIPE_NT) ? 0u : lds_for_waves(c.block, consume ? 0u : e.waves);
         return c;
@@ -272,7 +306,7 @@ std::pair<LaunchCfg, TuneEntry> default_generate(cprng_t *h, uint64_t n)
     e.store = c.store;
     e.slots = c.slots;
     e.exchange = c.exchange;
-    e.waves = (h->flags & CPRNG_F_INTERLEAVED) ? (h->n_cu ? c.grid / h->n_cu : 0u) : default_entry(h->variant, false).waves;
+    e.waves = (h->flags & CPRNG_F_INTERLEAVED) ? (h->n_cu ? c.grid / h->n_cu : 0u) : default_generate_entry(h).waves;
     return {c, e};
 }
 int timing_begin(cprng_t *h, hipStream_t st) { return begin_timing(h, st); }
@@ -576,7 +610,7 @@ int cprng_resolved_tuning(cprng_t *h, uint64_t n_per_stream, cprng_tuning_t *out
     else if (c.store == ST_PIPE || c.store == ST_PIPE_NT)
         out->waves_per_cu = h->n_cu ? c.grid / h->n_cu : 0;
     else
-        out->waves_per_cu = h->tuning.waves_per_cu ? h->tuning.waves_per_cu : (cached ? e.waves : default_entry(h->variant, false).waves);
+        out->waves_per_cu = h->tuning.waves_per_cu ? h->tuning.waves_per_cu : (cached ? e.waves : default_generate_entry(h).waves);
     if (source) *source = tuning_source(h, cached);
     return CPRNG_OK;
 }
