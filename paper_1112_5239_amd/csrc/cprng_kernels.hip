@@ -332,10 +332,14 @@ __global__ __launch_bounds__(64) void k_segments_tile(SegArgs a)
     }
 }
 
+// Copies the listed streams' end states back; with `reset` set, thread 0
+// also clears the 8 work-queue counters for the next launch on the stream
+// (after the segment kernel that used them has finished, in stream order).
 __global__ void k_commit(uint32_t *state, const uint32_t *state_next, const uint32_t *ids,
-                         uint32_t count, uint32_t ns)
+                         uint32_t count, uint32_t ns, uint32_t *reset)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (reset && i < 8u) reset[i] = 0u;
     if (i >= count) return;
     const uint64_t id = ids[i];
 #pragma unroll
@@ -643,10 +647,11 @@ hipError_t launch_subset(const SubsetArgs &sa, const SegArgs &a, uint32_t grid, 
 }
 
 hipError_t launch_commit(uint32_t *state, const uint32_t *state_next, const uint32_t *ids,
-                         uint32_t count, uint32_t ns, hipStream_t st)
+                         uint32_t count, uint32_t ns, hipStream_t st, uint32_t *reset_counters)
 {
-    if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_commit, dim3((count + 255) / 256), dim3(256), 0, st, state, state_next, ids, count, ns);
+    if (count == 0 && !reset_counters) return hipSuccess;
+    const uint32_t grid = count ? (count + 255) / 256 : 1u;
+    hipLaunchKernelGGL(k_commit, dim3(grid), dim3(256), 0, st, state, state_next, ids, count, ns, reset_counters);
     return hipGetLastError();
 }
 

@@ -87,7 +87,8 @@ hipError_t launch_ragged_v0(const cprng_t *h, const V0Launch &p, const RunDesc *
 // streams may overlap on the device, so each stream has its own).
 struct ReqSlot {
     hipStream_t stream = nullptr;
-    uint32_t *d_counter = nullptr;      // work-queue counter
+    uint32_t *d_counter = nullptr;      // work-queue counters
+    bool counters_clean = true;         // zero (cleared by the last launch's commit)
     void *d_buf = nullptr;              // run descriptors and commit ids
     void *h_stage = nullptr;            // pinned staging of d_buf
     size_t buf_cap = 0;

@@ -249,9 +249,10 @@ hipError_t launch_subset(const SubsetArgs &sa, const SegArgs &a, uint32_t grid, 
 // lds_min: dynamic LDS per workgroup at least this (caps residency).
 hipError_t launch_segments(const SegArgs &a, uint32_t grid, uint32_t block, uint32_t store, uint32_t lds_min,
                            hipStream_t st);
-// state[k * ns + ids[i]] = state_next[k * ns + ids[i]] for k < 5.
+// state[k * ns + ids[i]] = state_next[k * ns + ids[i]] for k < 5; with
+// reset_counters, also clears those 8 work-queue counters for the next launch.
 hipError_t launch_commit(uint32_t *state, const uint32_t *state_next, const uint32_t *ids,
-                         uint32_t count, uint32_t ns, hipStream_t st);
+                         uint32_t count, uint32_t ns, hipStream_t st, uint32_t *reset_counters = nullptr);
 hipError_t launch_zero_u32(uint32_t *p, uint32_t count, hipStream_t st);
 
 hipError_t launch_fill(uint32_t *dst, uint64_t n_words, uint32_t value, hipStream_t st);

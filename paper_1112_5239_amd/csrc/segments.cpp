@@ -622,13 +622,21 @@ int request_table(cprng_t *h, uint32_t chunk, uint64_t max_seg, const uint32_t *
     return CPRNG_OK;
 }
 
-// Chunk length of a request batch: the tuned chunk, halved (down to 1024)
-// while the batch would not give every SIMD two lanes of work.
+// Chunk length of a request batch: the tuned chunk, halved (down to 1,024)
+// while the batch would not give every SIMD two lanes of work, then (down
+// to 256) while it gives fewer than 4,096 lanes.  Such a batch is
+// latency-bound: each lane walks its jump and then its chunk serially, so
+// shorter chunks finish sooner (one request of 2^17 numbers: 56 -> 42 us
+// round trip), while larger batches would only add jumps (2^22 numbers:
+// 59 us at 1,024-output chunks, 62 us at 256).
+constexpr uint32_t kMinRequestChunk = 256;
+
 uint32_t request_chunk(const cprng_t *h, uint32_t chunk, uint64_t total)
 {
     if (h->tuning.chunk) return chunk;
     const uint64_t lanes_wanted = (uint64_t)h->n_cu * 4 * 64 * 2;
     while (chunk > 1024 && total / chunk < lanes_wanted) chunk /= 2;
+    while (chunk > kMinRequestChunk && total / chunk < 4096) chunk /= 2;
     return chunk;
 }
 
@@ -643,7 +651,9 @@ ReqSlot *find_slot(cprng_t *h, hipStream_t st, int *rc)
     ReqSlot *r = new ReqSlot();
     r->stream = st;
     r->index = (uint32_t)h->req_slots.size();
-    if (hipMalloc(&r->d_counter, 64) != hipSuccess ||
+    // The queue counters start at zero; each request launch's commit kernel
+    // clears them again for the next launch on this stream.
+    if (hipMalloc(&r->d_counter, 64) != hipSuccess || hipMemset(r->d_counter, 0, 64) != hipSuccess ||
         hipEventCreateWithFlags(&r->ev_stage, hipEventDisableTiming) != hipSuccess) {
         if (r->d_counter) (void)hipFree(r->d_counter);
         delete r;
@@ -773,11 +783,15 @@ extern "C" int cprng_generate_requests(cprng_t *h, const cprng_request_t *reqs, 
     for (size_t j = 0; j < launches.size() && e == hipSuccess; ++j) {
         const SegArgs a = seg_args(h, c, (const RunDesc *)(db + run_off[j]), (uint32_t)launches[j].runs.size(),
                                    launches[j].nseg, kcap, d_tab, slot->d_counter);
-        e = launch_zero_u32(slot->d_counter, 8, st);
+        // The counters are zero unless an earlier launch failed before its
+        // commit could clear them.
+        if (!slot->counters_clean) e = launch_zero_u32(slot->d_counter, 8, st);
+        slot->counters_clean = false;
         if (e == hipSuccess) e = launch_segments(a, persistent_grid(h, c, a.nseg), c.block, seg_kernel_store(c), seg_lds_min(c), st);
         if (e == hipSuccess)
             e = launch_commit(h->d_state, h->d_state_next, (const uint32_t *)(db + id_off[j]),
-                              (uint32_t)ids[j].size(), h->ns, st);
+                              (uint32_t)ids[j].size(), h->ns, st, slot->d_counter);
+        if (e == hipSuccess) slot->counters_clean = true;
     }
     if (e != hipSuccess) return hip_error(e, "request kernels");
     if (h->timing) {
@@ -955,7 +969,7 @@ int prepare_request_tables(cprng_t *h, uint64_t max_len)
         const uint32_t *d = nullptr;
         uint32_t kcap = 0;
         rc = request_table(h, chunk, segments_of(max_len, 0, chunk), &d, &kcap);
-        if (rc || chunk <= 1024 || h->tuning.chunk) return rc;
+        if (rc || chunk <= kMinRequestChunk || h->tuning.chunk) return rc;
     }
 }
 
