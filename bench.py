@@ -54,12 +54,12 @@ LANES_FAST, LANES_SHIFT = 128, 64
 # gfx950 code object (hipcc -S of gen_vN.hip; the unrolled loop of the
 # configuration that runs by default).
 ALU_MIX = {
-    "v0_consume": (217 / 16, 33 / 16),      # k_consume<0, u32, 16>
-    "v2_consume": (233 / 16, 33 / 16),      # k_consume<2, u32, 16>
+    "v0_consume": (201 / 16, 33 / 16),      # k_consume<0, u32, 16>
+    "v2_consume": (217 / 16, 33 / 16),      # k_consume<2, u32, 16>
     "v1_generate": (1081 / 32, 400 / 32),   # k_generate_ilv<1, u64, 32, 256, NT>: 14 xor + 7 xor3 + 9 64-bit
                                             # shifts + 2.5 64-bit adds + 1 add3
     "v3_generate": (2181 / 16, 436 / 16),   # k_generate_ilv<3, u32, 16, 512, NT, LDS exchange>
-    "v3_consume": (2281 / 16, 449 / 16),    # k_consume<3, u32, 16>
+    "v3_consume": (2265 / 16, 449 / 16),    # k_consume<3, u32, 16>
 }
 
 # kernels whose loop bodies are integer-only (no f32 instruction to pair with)

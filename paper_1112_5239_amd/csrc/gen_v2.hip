@@ -10,6 +10,7 @@ namespace {
 
 #include "device_common.inc"
 #include "gen_kernels.inc"
+#include "consume_kernels.inc"
 #include "chunk_kernels.inc"
 
 }  // namespace
