@@ -61,6 +61,37 @@ def test_v0_plain_1024x1024_all_store_modes(orc, G, store, unroll):
     _gen_check(orc, G, "v0", 0, 1024, 1024, sigma=0, tuning=dict(store=store, unroll=unroll, block=256))
 
 
+# The stream-major defaults depend on the stream count: one-wave blocks with
+# direct stores up to one wave per CU (16,384 streams on 256 CUs), one-wave
+# LDS tiles up to four (65,536), the large-shape defaults above.
+def _cu_count(torch):
+    return torch.cuda.get_device_properties(0).multi_processor_count
+
+
+@pytest.mark.parametrize("variant_name,variant", [("v0", 0), ("v1", 1), ("v2", 2)])
+@pytest.mark.parametrize("ns", [16384, 16448, 65536, 65600])
+def test_few_streams_default_bands(orc, G, torch, variant_name, variant, ns):
+    # Both sides of each band edge with the default configuration; n with a
+    # tail after the 32-step rounds.
+    _gen_check(orc, G, variant_name, variant, ns, 44, sigma=5, calls=2)
+
+
+def test_few_streams_defaults_resolved(G, torch):
+    if _cu_count(torch) != 256:
+        pytest.skip("the band edges are stated for 256 compute units")
+    cases = [(1024, "v0", (64, 32, 1)), (16384, "v2", (64, 32, 1)), (16384, "v1", (64, 32, 1)),
+             (16448, "v0", (64, 32, 2)), (65536, "v2", (64, 32, 2)), (65536, "v1", (64, 16, 1)),
+             (65600, "v0", (128, 128, 4)), (65600, "v1", (256, 64, 4)), (65600, "v2", (256, 32, 2))]
+    for ns, name, want in cases:
+        g = G.Generator(ns, name, seed=0)
+        try:
+            cfg = g.resolved_tuning(1024)
+            assert cfg["source"] == "default", (ns, name, cfg)
+            assert (cfg["block"], cfg["unroll"], cfg["store"]) == want, (ns, name, cfg)
+        finally:
+            g.close()
+
+
 @pytest.mark.parametrize("unroll,block,waves,slots", [(64, 64, 2, 1), (128, 128, 4, 1), (256, 64, 0, 1),
                                                       (32, 192, 6, 1), (64, 128, 0, 2), (32, 64, 4, 4),
                                                       (128, 64, 0, 4), (16, 256, 0, 2)])
