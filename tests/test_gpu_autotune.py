@@ -136,7 +136,8 @@ def test_autotune_cache_round_trip_and_parity(tmp_path):
     # a fresh process reads the file and uses the same configurations
     used = _child("use", cache)
     assert used == tuned
-    # the interleaved pick is an interleaved kernel
-    assert tuned["gen_v2_ilv"]["store"] in (9, 10, 11, 12)
+    # the interleaved pick is an interleaved kernel: the per-lane dword
+    # kernel (the default at this stream count), the tiles or the quad lanes
+    assert tuned["gen_v2_ilv"]["store"] in (5, 9, 10, 11, 12)
     assert tuned["ragged_v1"]["streams_per_lane"] in (1, 2, 4)
     assert tuned["ragged_v1"]["unroll"] in (32, 64, 128)

@@ -232,6 +232,30 @@ def _ilv_check(orc, G, variant_name, variant, ns, n, sigma, tuning=None, calls=2
         g.close()
 
 
+@pytest.mark.parametrize("variant_name,variant", [("v0", 0), ("v1", 1), ("v2", 2)])
+@pytest.mark.parametrize("ns", [65536, 65600])
+def test_interleaved_few_streams_default_band(orc, G, torch, variant_name, variant, ns):
+    # Up to 65,536 streams (on 256 CUs) the interleaved default is the
+    # per-lane dword kernel, above it the tiles: both sides of the edge.
+    _ilv_check(orc, G, variant_name, variant, ns, 44, sigma=6)
+
+
+def test_interleaved_few_streams_resolved(G, torch):
+    if torch.cuda.get_device_properties(0).multi_processor_count != 256:
+        pytest.skip("the band edge is stated for 256 compute units")
+    cases = [(1024, "v0", (64, 32, 5)), (65536, "v2", (64, 32, 5)), (65536, "v1", (64, 32, 5)),
+             (65536, "v4", (64, 32, 5)), (65600, "v0", (1024, 16, 10)), (65600, "v2", (1024, 16, 10)),
+             (65600, "v1", (256, 32, 10)), (65536, "v3", (512, 16, 10))]
+    for ns, name, want in cases:
+        g = G.Generator(ns, name, seed=0, interleaved=True)
+        try:
+            cfg = g.resolved_tuning(1024)
+            assert cfg["source"] == "default", (ns, name, cfg)
+            assert (cfg["block"], cfg["unroll"], cfg["store"]) == want, (ns, name, cfg)
+        finally:
+            g.close()
+
+
 @pytest.mark.parametrize("store", [2, 4, 1])
 @pytest.mark.parametrize("block,unroll", [(256, 64), (512, 32), (1024, 16), (1024, 8), (256, 8)])
 def test_interleaved_tiles(orc, G, store, block, unroll):
