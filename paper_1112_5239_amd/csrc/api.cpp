@@ -178,19 +178,20 @@ int create_impl(const cprng_params_t *p, cprng_t **out)
 // latency exposed.  Measured on MI355X at 1,024 outputs per stream: up to one
 // wave per CU, one-wave blocks storing their own quads beat the LDS tiles
 // (1,024 streams: V0 0.016 vs 0.033 ms, V1 0.063 vs 0.081, V2 0.040 vs
-// 0.063); up to four waves per CU, one-wave LDS tiles of 32 steps (V0 0.041
-// vs 0.079 ms, V2 0.064 vs 0.071 at 2^16 streams) and, for V1, direct stores
-// of 16 steps (0.094 vs 0.106 ms).  The BBS variant keeps its defaults.
+// 0.063); beyond that, one-wave LDS tiles of 32 steps for V0 up to six waves
+// per CU (65,600 streams: 0.042 vs 0.082 ms; even at 98,304) and for V2/V4
+// up to four (65,536: V2 0.064 vs 0.071 ms), and for V1 the direct stores up
+// to five (65,600: 0.135 vs 0.145 ms; even at 81,920, slower by 98,304).  The
+// BBS variant keeps its defaults.
 void small_shape_defaults(const cprng_t *h, LaunchCfg &c, TuneEntry &e)
 {
     if (h->variant == CPRNG_V3_BBS || (h->flags & CPRNG_F_INTERLEAVED)) return;
     const uint64_t ns = h->ns, cu = h->n_cu ? h->n_cu : 256u;
-    if (ns <= cu * 64u) {
+    const bool v0 = h->variant == CPRNG_V0_PLAIN, v1 = h->variant == CPRNG_V1_NAIVE3;
+    if (ns <= cu * 64u || (v1 && ns <= cu * 320u)) {
         c.block = 64; c.unroll = 32; c.store = ST_DIRECT;
-    } else if (ns <= cu * 256u) {
-        c.block = 64;
-        if (h->variant == CPRNG_V1_NAIVE3) { c.unroll = 16; c.store = ST_DIRECT; }
-        else { c.unroll = 32; c.store = ST_LDS; }
+    } else if (ns <= cu * (v0 ? 384u : 256u) && !v1) {
+        c.block = 64; c.unroll = 32; c.store = ST_LDS;
     } else {
         return;
     }
@@ -235,12 +236,16 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume, bool defaults_only =
             c.slots = 1;
             c.exchange = XCH_LDS;
         }
-        // Up to four waves' worth of streams per CU (65,536 on 256 CUs) the
-        // tiles leave most CUs idle; per-lane dword stores in one-wave blocks
-        // of 32 steps are faster (1,024 streams: V0 0.022 vs 0.068 ms, V2
-        // 0.055 vs 0.111, V1 0.067 vs 0.080; 65,536: V0 0.041 vs 0.071 ms),
-        // the tiles again from 2^18 streams.  BBS keeps its tiles.
-        if (h->variant != CPRNG_V3_BBS && (uint64_t)h->ns <= (uint64_t)(h->n_cu ? h->n_cu : 256u) * 256u) {
+        // With few streams the tiles leave most CUs idle; per-lane dword
+        // stores in one-wave blocks of 32 steps are faster: V0 up to five
+        // waves' worth of streams per CU (1,024 streams: 0.022 vs 0.068 ms;
+        // 65,600: 0.044 vs 0.070; slower by 98,304), V1, V2 and V4 up to
+        // eight (1,024: V2 0.055 vs 0.111 ms, V1 0.067 vs 0.080; 131,072: V2
+        // 0.114 vs 0.123, V1 0.187 vs 0.192; slower by 196,608).  BBS keeps
+        // its tiles.
+        const uint64_t ilv_cu = h->n_cu ? h->n_cu : 256u;
+        if (h->variant != CPRNG_V3_BBS &&
+            (uint64_t)h->ns <= ilv_cu * (h->variant == CPRNG_V0_PLAIN ? 320u : 512u)) {
             c.block = 64;
             c.unroll = 32;
             c.store = ST_INTERLEAVED;

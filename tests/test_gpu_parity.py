@@ -62,14 +62,15 @@ def test_v0_plain_1024x1024_all_store_modes(orc, G, store, unroll):
 
 
 # The stream-major defaults depend on the stream count: one-wave blocks with
-# direct stores up to one wave per CU (16,384 streams on 256 CUs), one-wave
-# LDS tiles up to four (65,536), the large-shape defaults above.
+# direct stores up to one wave per CU (16,384 streams on 256 CUs; V1 up to five,
+# 81,920), one-wave LDS tiles above that (V0 up to six waves per CU, V2 up to
+# four, 65,536), the large-shape defaults beyond.
 def _cu_count(torch):
     return torch.cuda.get_device_properties(0).multi_processor_count
 
 
 @pytest.mark.parametrize("variant_name,variant", [("v0", 0), ("v1", 1), ("v2", 2)])
-@pytest.mark.parametrize("ns", [16384, 16448, 65536, 65600])
+@pytest.mark.parametrize("ns", [16384, 16448, 65536, 65600, 81920, 81952, 98304, 98336])
 def test_few_streams_default_bands(orc, G, torch, variant_name, variant, ns):
     # Both sides of each band edge with the default configuration; n with a
     # tail after the 32-step rounds.
@@ -80,8 +81,9 @@ def test_few_streams_defaults_resolved(G, torch):
     if _cu_count(torch) != 256:
         pytest.skip("the band edges are stated for 256 compute units")
     cases = [(1024, "v0", (64, 32, 1)), (16384, "v2", (64, 32, 1)), (16384, "v1", (64, 32, 1)),
-             (16448, "v0", (64, 32, 2)), (65536, "v2", (64, 32, 2)), (65536, "v1", (64, 16, 1)),
-             (65600, "v0", (128, 128, 4)), (65600, "v1", (256, 64, 4)), (65600, "v2", (256, 32, 2))]
+             (16448, "v0", (64, 32, 2)), (65536, "v2", (64, 32, 2)), (65600, "v2", (256, 32, 2)),
+             (98304, "v0", (64, 32, 2)), (98336, "v0", (128, 128, 4)),
+             (81920, "v1", (64, 32, 1)), (81952, "v1", (256, 64, 4))]
     for ns, name, want in cases:
         g = G.Generator(ns, name, seed=0)
         try:
@@ -233,19 +235,20 @@ def _ilv_check(orc, G, variant_name, variant, ns, n, sigma, tuning=None, calls=2
 
 
 @pytest.mark.parametrize("variant_name,variant", [("v0", 0), ("v1", 1), ("v2", 2)])
-@pytest.mark.parametrize("ns", [65536, 65600])
+@pytest.mark.parametrize("ns", [81920, 81952, 131072, 131104])
 def test_interleaved_few_streams_default_band(orc, G, torch, variant_name, variant, ns):
-    # Up to 65,536 streams (on 256 CUs) the interleaved default is the
-    # per-lane dword kernel, above it the tiles: both sides of the edge.
+    # With few streams the interleaved default is the per-lane dword kernel
+    # (V0 up to 81,920 streams on 256 CUs, V1 and V2 up to 131,072), above it
+    # the tiles: both sides of each edge.
     _ilv_check(orc, G, variant_name, variant, ns, 44, sigma=6)
 
 
 def test_interleaved_few_streams_resolved(G, torch):
     if torch.cuda.get_device_properties(0).multi_processor_count != 256:
         pytest.skip("the band edge is stated for 256 compute units")
-    cases = [(1024, "v0", (64, 32, 5)), (65536, "v2", (64, 32, 5)), (65536, "v1", (64, 32, 5)),
-             (65536, "v4", (64, 32, 5)), (65600, "v0", (1024, 16, 10)), (65600, "v2", (1024, 16, 10)),
-             (65600, "v1", (256, 32, 10)), (65536, "v3", (512, 16, 10))]
+    cases = [(1024, "v0", (64, 32, 5)), (81920, "v0", (64, 32, 5)), (81952, "v0", (1024, 16, 10)),
+             (131072, "v2", (64, 32, 5)), (131072, "v1", (64, 32, 5)), (131072, "v4", (64, 32, 5)),
+             (131104, "v2", (1024, 16, 10)), (131104, "v1", (256, 32, 10)), (65536, "v3", (512, 16, 10))]
     for ns, name, want in cases:
         g = G.Generator(ns, name, seed=0, interleaved=True)
         try:
