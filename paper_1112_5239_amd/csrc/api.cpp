@@ -242,8 +242,10 @@ LaunchCfg resolve_cfg(cprng_t *h, uint64_t n, bool consume, bool defaults_only =
         // 65,600: 0.044 vs 0.070; slower by 98,304), V1, V2 and V4 up to
         // eight (1,024: V2 0.055 vs 0.111 ms, V1 0.067 vs 0.080; 131,072: V2
         // 0.114 vs 0.123, V1 0.187 vs 0.192; slower by 196,608).  BBS keeps
-        // its tiles.
+        // its tiles, of 256 streams up to four waves' worth per CU (1,024
+        // streams: 0.274 vs 0.308 ms; 65,536: 0.294 vs 0.325; equal beyond).
         const uint64_t ilv_cu = h->n_cu ? h->n_cu : 256u;
+        if (h->variant == CPRNG_V3_BBS && (uint64_t)h->ns <= ilv_cu * 256u) c.block = 256;
         if (h->variant != CPRNG_V3_BBS &&
             (uint64_t)h->ns <= ilv_cu * (h->variant == CPRNG_V0_PLAIN ? 320u : 512u)) {
             c.block = 64;

@@ -248,7 +248,8 @@ def test_interleaved_few_streams_resolved(G, torch):
         pytest.skip("the band edge is stated for 256 compute units")
     cases = [(1024, "v0", (64, 32, 5)), (81920, "v0", (64, 32, 5)), (81952, "v0", (1024, 16, 10)),
              (131072, "v2", (64, 32, 5)), (131072, "v1", (64, 32, 5)), (131072, "v4", (64, 32, 5)),
-             (131104, "v2", (1024, 16, 10)), (131104, "v1", (256, 32, 10)), (65536, "v3", (512, 16, 10))]
+             (131104, "v2", (1024, 16, 10)), (131104, "v1", (256, 32, 10)), (65536, "v3", (256, 16, 10)),
+             (65568, "v3", (512, 16, 10))]
     for ns, name, want in cases:
         g = G.Generator(ns, name, seed=0, interleaved=True)
         try:
