@@ -329,7 +329,7 @@ def run_ragged_v1(torch, G, args, ref_gn):
 
 def run_small(torch, G, args):
     """The small plain configuration: 1,024 streams x 1,024 outputs (4 MiB),
-    seed 0, V0 and V1, stream-major: a launch-bound size (16 waves)."""
+    seed 0, V0 and V1, stream-major: 16 waves, a latency-bound size."""
     res = {"workload": "1024 streams x 1024 uint32 (4 MiB), seed 0, stream-major"}
     for variant in ("v0", "v1"):
         g = G.Generator(1024, variant, seed=0)
