@@ -223,9 +223,8 @@ __global__ __launch_bounds__(256) void k_segments(SegArgs a)
 // 256-byte aligned after the run's head (0..63 outputs stored singly by
 // segment 0), so full rounds write whole lines.
 template <int K, bool NT>
-__global__ __launch_bounds__(64) void k_segments_tile(SegArgs a)
+__device__ __forceinline__ void segments_tile(SegArgs a, uint32_t *lds)
 {
-    HIP_DYNAMIC_SHARED(uint32_t, lds);
     constexpr int QPR = K / 4;               // quads per row
     constexpr int RPI = 64 / QPR;            // rows per store instruction
     static_assert(QPR <= 64 && 64 % QPR == 0, "K must divide 256");
@@ -330,6 +329,39 @@ __global__ __launch_bounds__(64) void k_segments_tile(SegArgs a)
             st[4 * ns] = x;
         }
     }
+}
+
+template <int K, bool NT>
+__global__ __launch_bounds__(64) void k_segments_tile(SegArgs a)
+{
+    HIP_DYNAMIC_SHARED(uint32_t, lds);
+    segments_tile<K, NT>(a, lds);
+}
+
+// The same with the run descriptors in the kernel arguments (small request
+// batches): they are read through the kernel-argument segment, so no upload
+// precedes the launch.
+template <int K, bool NT>
+__global__ __launch_bounds__(64) void k_segments_tile_inline(SegInline s)
+{
+    HIP_DYNAMIC_SHARED(uint32_t, lds);
+    const SegInline *p = (const SegInline *)__builtin_amdgcn_kernarg_segment_ptr();
+    SegArgs a = p->a;
+    a.runs = p->runs;
+    segments_tile<K, NT>(a, lds);
+}
+
+// Commit of an inline batch (ids in the kernel arguments, at most 64), which
+// also clears the batch's work-queue counters for the next launch.
+__global__ __launch_bounds__(64) void k_commit_inline(SegInline s, uint32_t *state)
+{
+    const SegInline *p = (const SegInline *)__builtin_amdgcn_kernarg_segment_ptr();
+    const uint32_t i = threadIdx.x;
+    if (i < 8u) p->a.counter[i] = 0u;
+    if (i >= p->n_ids) return;
+    const uint64_t id = p->ids[i], ns = p->a.ns;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) state[k * ns + id] = p->a.state_next[k * ns + id];
 }
 
 // Copies the listed streams' end states back; with `reset` set, thread 0
@@ -643,6 +675,35 @@ hipError_t launch_subset(const SubsetArgs &sa, const SegArgs &a, uint32_t grid, 
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_segments(a, grid, block, store, 0, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_subset_commit, dim3(sa.nblocks), dim3(256), 0, st, sa, state, a.state_next);
+    return hipGetLastError();
+}
+
+hipError_t launch_segments_inline(const SegInline &si, uint32_t grid, uint32_t store, hipStream_t st)
+{
+    if (grid == 0 || si.n_ids > kInlineRuns || si.a.nrun > kInlineRuns || (store != ST_LDS && store != ST_LDS_NT))
+        return hipErrorInvalidValue;
+    const bool nt = store == ST_LDS_NT;
+    const size_t lds = (size_t)64 * si.a.unroll * 4 + 64 * 12;
+#define SEG_TILE_INLINE(K)                                                                                   \
+    do {                                                                                                     \
+        if (nt) hipLaunchKernelGGL((k_segments_tile_inline<K, true>), dim3(grid), dim3(64), lds, st, si);    \
+        else hipLaunchKernelGGL((k_segments_tile_inline<K, false>), dim3(grid), dim3(64), lds, st, si);      \
+    } while (0)
+    switch (si.a.unroll) {
+    case 32: SEG_TILE_INLINE(32); break;
+    case 64: SEG_TILE_INLINE(64); break;
+    case 128: SEG_TILE_INLINE(128); break;
+    case 256: SEG_TILE_INLINE(256); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef SEG_TILE_INLINE
+    return hipGetLastError();
+}
+
+hipError_t launch_commit_inline(const SegInline &si, uint32_t *state, hipStream_t st)
+{
+    if (si.n_ids > kInlineRuns) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_commit_inline, dim3(1), dim3(64), 0, st, si, state);
     return hipGetLastError();
 }
 

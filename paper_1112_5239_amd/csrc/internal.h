@@ -208,6 +208,21 @@ struct SegArgs {
     uint32_t lo_bits;
 };
 
+// Request batches small enough to travel in the kernel arguments: up to
+// kInlineRuns runs and commit ids, read by the kernels through their
+// kernel-argument segment, so no descriptor upload precedes the launch.
+constexpr uint32_t kInlineRuns = 64;
+struct SegInline {
+    SegArgs a;                    // a.runs is ignored: the kernels use runs[]
+    RunDesc runs[kInlineRuns];
+    uint32_t ids[kInlineRuns];    // streams whose end states the commit copies back
+    uint32_t n_ids;
+};
+// Tiled segment kernel (store ST_LDS / ST_LDS_NT, persistent) on an inline batch.
+hipError_t launch_segments_inline(const SegInline &si, uint32_t grid, uint32_t store, hipStream_t st);
+// Commit of an inline batch; also clears its 8 work-queue counters (si.a.counter).
+hipError_t launch_commit_inline(const SegInline &si, uint32_t *state, hipStream_t st);
+
 // Stream subsets described in device memory (cprng_generate_subset).
 constexpr uint64_t kSubsetMaxLen = 1ull << 37;   // outputs per descriptor
 constexpr uint32_t kSubsetLoBits = 13;           // jump table: 2 x 2^13 rows

@@ -742,6 +742,38 @@ extern "C" int cprng_generate_requests(cprng_t *h, const cprng_request_t *reqs, 
     hipStream_t st = (hipStream_t)stream;
     ReqSlot *slot = find_slot(h, st, &rc);
     if (!slot) return rc;
+
+    // Small batches (every launch at most kInlineRuns runs, tiled persistent
+    // stores) carry their runs and commit ids in the kernel arguments: no
+    // upload, no wait for the staging buffer.
+    bool inline_ok = seg_persistent(c) && (seg_kernel_store(c) == ST_LDS || seg_kernel_store(c) == ST_LDS_NT);
+    for (size_t j = 0; j < launches.size() && inline_ok; ++j)
+        inline_ok = launches[j].runs.size() <= kInlineRuns && ids[j].size() <= kInlineRuns;
+    if (inline_ok) {
+        if (h->timing && hipEventRecord(h->ev0, st) != hipSuccess) return set_error(CPRNG_E_HIP, "hipEventRecord");
+        hipError_t e = hipSuccess;
+        for (size_t j = 0; j < launches.size() && e == hipSuccess; ++j) {
+            SegInline si;
+            std::memset(&si, 0, sizeof si);
+            si.a = seg_args(h, c, nullptr, (uint32_t)launches[j].runs.size(), launches[j].nseg, kcap, d_tab,
+                            slot->d_counter);
+            std::memcpy(si.runs, launches[j].runs.data(), launches[j].runs.size() * sizeof(RunDesc));
+            std::memcpy(si.ids, ids[j].data(), ids[j].size() * sizeof(uint32_t));
+            si.n_ids = (uint32_t)ids[j].size();
+            if (!slot->counters_clean) e = launch_zero_u32(slot->d_counter, 8, st);
+            slot->counters_clean = false;
+            if (e == hipSuccess) e = launch_segments_inline(si, persistent_grid(h, c, si.a.nseg), seg_kernel_store(c), st);
+            if (e == hipSuccess) e = launch_commit_inline(si, h->d_state, st);
+            if (e == hipSuccess) slot->counters_clean = true;
+        }
+        if (e != hipSuccess) return hip_error(e, "request kernels");
+        if (h->timing) {
+            if (hipEventRecord(h->ev1, st) != hipSuccess) return set_error(CPRNG_E_HIP, "hipEventRecord");
+            h->ev_pending = true;
+        }
+        return CPRNG_OK;
+    }
+
     // Stage every launch's runs and ids in one pinned buffer and copy it with
     // one transfer.  The previous call on this stream may still be running:
     // wait until its transfer has left the staging buffer; on the device the

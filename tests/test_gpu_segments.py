@@ -190,3 +190,29 @@ def test_requests_large_single_request(orc, G, torch):
         assert np.array_equal(G.as_u32(b), want[0])
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("n_req", [1, 64, 65, 100])
+def test_requests_inline_and_staged_batches(orc, G, torch, n_req):
+    # Up to 64 runs per launch the batch travels in the kernel arguments,
+    # above that through the staged upload; three calls in a row (the queue
+    # counters carry over between launches), lengths across several chunks.
+    ns = 128
+    g = G.Generator(ns, "v0", seed=17)
+    try:
+        rng = np.random.default_rng(n_req)
+        st = orc.seed(0, 17, 0, ns)
+        for call in range(3):
+            streams = rng.permutation(ns)[:n_req]
+            lengths = rng.integers(1, 20000, n_req)
+            bufs = [torch.zeros(int(L) + 4, dtype=torch.int32, device="cuda") for L in lengths]
+            g.generate_requests([(int(s), int(L), b.data_ptr() + 4) for s, L, b in zip(streams, lengths, bufs)])
+            torch.cuda.synchronize()
+            for s, L, b in zip(streams, lengths, bufs):
+                want, _ = orc.generate(0, st[s:s + 1], int(L))
+                got = G.as_u32(b)
+                assert np.array_equal(got[1:1 + L], want[0]), f"call {call} stream {s} (length {L})"
+                assert got[0] == 0 and not got[1 + L:].any()
+        assert np.array_equal(g.get_state(), st)
+    finally:
+        g.close()
