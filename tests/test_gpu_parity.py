@@ -188,6 +188,42 @@ def test_ragged_tail_lengths(orc, G, variant_name, variant, n):
 
 
 @pytest.mark.parametrize("variant_name,variant", [("v0", 0), ("v1", 1), ("v2", 2)])
+@pytest.mark.parametrize("unroll,store,exchange", [(32, 2, 2), (64, 4, 1), (128, 4, 2), (32, 4, 3),
+                                                   (64, 2, 3), (128, 2, 1)])
+def test_rows_off_lines(orc, G, torch, variant_name, variant, unroll, store, exchange):
+    # Stream-major rows that start off 128-byte lines (n not a multiple of 32,
+    # or a 16-byte aligned base at every phase of a line) take line-aligned
+    # pieces; rows shorter than a round, a partial last wave, several calls.
+    # Words around the output must stay untouched.
+    ns, sigma, fill = (1056 if variant == 2 else 1000), 31, 0x5A5A5A5A
+    g = G.Generator(ns, variant_name, seed=sigma)
+    try:
+        kw = dict(store=store, unroll=unroll, block=256)
+        if variant == 2:
+            kw["exchange"] = exchange
+        g.set_tuning(**kw)
+        st = _oracle_states(orc, variant, sigma, ns)
+        combs = orc.comb_tables(32) if variant == 2 else None
+        buf = torch.full((ns * 1060 + 96,), fill, dtype=torch.int32, device="cuda")
+        assert buf.data_ptr() % 16 == 0
+        phase0 = (buf.data_ptr() // 4) % 32
+        for n, phase in ((1000, 0), (1024, 4), (1024, 28), (4, 0), (28, 12), (100, 8), (1060, 20), (132, 0)):
+            off = (phase - phase0) % 32
+            g.generate(n, out=buf[off:off + ns * n])
+            torch.cuda.synchronize()
+            want, _ = orc.generate(variant, st, n, comb=combs)
+            host = G.as_u32(buf)
+            got = host[off:off + ns * n].reshape(ns, n)
+            bad = np.argwhere(got != want)
+            assert bad.size == 0, f"n={n}, line phase {phase}: first mismatch at {bad[:3].tolist()}"
+            assert (host[:off] == fill).all() and (host[off + ns * n:] == fill).all(), f"n={n}: wrote outside"
+            buf.fill_(fill)
+        assert np.array_equal(g.get_state(), st), "end state differs"
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("variant_name,variant", [("v0", 0), ("v1", 1), ("v2", 2)])
 def test_continuation_across_calls(orc, G, variant_name, variant):
     _gen_check(orc, G, variant_name, variant, 256, 64, sigma=4, calls=3)
 
