@@ -136,8 +136,10 @@ void cprng_destroy(cprng_t *h);
 /* ------------------------------------------------------------------------ */
 
 /* Generate n_per_stream outputs for every stream into out (device,
- * n_streams * n_per_stream uint32, 4-byte aligned; 16-byte alignment and
- * n_per_stream % 4 == 0 select the fast store path).  Each output is the new
+ * n_streams * n_per_stream uint32, 4-byte aligned).  In the stream-major
+ * layout, rows that start off 128-byte lines (n_per_stream % 32 != 0 or a
+ * base not 128-byte aligned) are stored in line-aligned pieces through LDS
+ * tiles whatever the store mode asked.  Each output is the new
  * state x after one chaotic iteration x <- x xor S (Section 4.2), with S as
  * the variant defines it; the state is written back at the end, as the GPU
  * kernels of Section 6 do.  n_per_stream == 0 is a no-op.

@@ -395,8 +395,12 @@ int generate_with(cprng_t *h, uint32_t *out, uint64_t n, hipStream_t st, LaunchC
         }
     } else {
         if (c.block > 256) c.block = 256;
+        // Rows off the 128-byte lines take the LDS tiles, whose launch then
+        // stores line-aligned pieces: the per-lane quads need n % 4 == 0 and a
+        // 16-byte aligned base, and the pipelined tiles would split lines.
         const bool aligned = ((uintptr_t)out % 16u) == 0 && (n % 4u) == 0;
-        if (!aligned) c.store = ST_GENERIC;
+        const bool on_lines = ((uintptr_t)out % 128u) == 0 && (n % 32u) == 0;
+        if (!aligned || (!on_lines && (c.store == ST_PIPE || c.store == ST_PIPE_NT))) c.store = ST_LDS_NT;
     }
     if (c.store == ST_LDS || c.store == ST_LDS_NT) {
         // LDS tiles hold K >= 16 words per row; block/64 waves x 64 rows x K

@@ -32,7 +32,6 @@ enum StoreMode : int {
     ST_DIRECT_NT = 3,     // as ST_DIRECT with non-temporal stores
     ST_LDS_NT = 4,        // as ST_LDS with non-temporal stores
     ST_INTERLEAVED = 5,   // out[i * n_streams + s], one dword per lane
-    ST_GENERIC = 6,       // any alignment / length: one dword per output
     ST_PIPE = 7,          // persistent waves, double-buffered LDS tiles, stores overlapped
     ST_PIPE_NT = 8,       // as ST_PIPE with non-temporal stores
     ST_ILV_TILE = 9,      // interleaved layout through a K x block LDS tile, 16-byte stores

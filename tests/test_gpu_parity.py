@@ -112,17 +112,19 @@ def test_lds_tiles_and_occupancy_caps(orc, G, unroll, block, waves, slots):
 def test_pipelined_persistent_modes(orc, G, store, unroll):
     # One persistent wave per CU over ~40k streams: each workgroup takes
     # several 64-stream blocks in turn, the last block is partial, and
-    # n = 1000 leaves a tail after the pipelined rounds.
+    # n = 1056 (rows on 128-byte lines) leaves a tail after the pipelined
+    # rounds of 64 and 128.
     for name, variant in (("v0", 0), ("v2", 2), ("v1", 1)):
         ns = 40032 if variant == 2 else 40037
-        _gen_check(orc, G, name, variant, ns, 1000, sigma=21,
+        _gen_check(orc, G, name, variant, ns, 1056, sigma=21,
                    tuning=dict(store=store, unroll=unroll, waves_per_cu=1))
 
 
 @pytest.mark.parametrize("exchange", [1, 2, 3])
-@pytest.mark.parametrize("n", [4, 1024, 1000])
+@pytest.mark.parametrize("n", [32, 1024, 1056, 1000])
 def test_pipelined_v2_exchange_modes(orc, G, exchange, n):
-    # n = 4: no full round (per-lane path only); 1024: rounds only.
+    # n = 32: shorter than a round of 64, or one round of 32; 1024: rounds only;
+    # 1056: rounds and a tail; 1000: rows off the lines (LDS tiles instead).
     _gen_check(orc, G, "v2", 2, 20480, n, sigma=22, calls=2,
                tuning=dict(store=7, unroll=64 if exchange != 2 else 32, waves_per_cu=2, exchange=exchange))
 
@@ -189,12 +191,13 @@ def test_ragged_tail_lengths(orc, G, variant_name, variant, n):
 
 @pytest.mark.parametrize("variant_name,variant", [("v0", 0), ("v1", 1), ("v2", 2)])
 @pytest.mark.parametrize("unroll,store,exchange", [(32, 2, 2), (64, 4, 1), (128, 4, 2), (32, 4, 3),
-                                                   (64, 2, 3), (128, 2, 1)])
+                                                   (64, 2, 3), (128, 2, 1), (32, 1, 1), (64, 7, 2)])
 def test_rows_off_lines(orc, G, torch, variant_name, variant, unroll, store, exchange):
-    # Stream-major rows that start off 128-byte lines (n not a multiple of 32,
-    # or a 16-byte aligned base at every phase of a line) take line-aligned
-    # pieces; rows shorter than a round, a partial last wave, several calls.
-    # Words around the output must stay untouched.
+    # Stream-major rows that start off 128-byte lines (n not a multiple of 32
+    # or of 4, a base at any 4-byte phase of a line) take line-aligned pieces
+    # whatever the store mode asked (LDS tiles, per-lane quads, pipelined);
+    # rows shorter than a round, a partial last wave, several calls.  Words
+    # around the output must stay untouched.
     ns, sigma, fill = (1056 if variant == 2 else 1000), 31, 0x5A5A5A5A
     g = G.Generator(ns, variant_name, seed=sigma)
     try:
@@ -207,7 +210,8 @@ def test_rows_off_lines(orc, G, torch, variant_name, variant, unroll, store, exc
         buf = torch.full((ns * 1060 + 96,), fill, dtype=torch.int32, device="cuda")
         assert buf.data_ptr() % 16 == 0
         phase0 = (buf.data_ptr() // 4) % 32
-        for n, phase in ((1000, 0), (1024, 4), (1024, 28), (4, 0), (28, 12), (100, 8), (1060, 20), (132, 0)):
+        for n, phase in ((1000, 0), (1024, 4), (1024, 28), (4, 0), (28, 12), (100, 8), (1060, 20), (132, 0),
+                         (1001, 1), (1003, 30), (7, 5), (1, 3), (1026, 2), (1024, 17), (33, 0), (64, 31)):
             off = (phase - phase0) % 32
             g.generate(n, out=buf[off:off + ns * n])
             torch.cuda.synchronize()
@@ -371,8 +375,10 @@ def _sample_groups(ns, frac=0.01, group=32, seed=20111223):
     return np.unique(np.concatenate([np.arange(64) // group, groups]))
 
 
-def test_v2_paper_shape_sampled(orc, G, torch):
-    ns, n = 1 << 20, 1024
+@pytest.mark.parametrize("n", [1024, 1000])
+def test_v2_paper_shape_sampled(orc, G, torch, n):
+    # n = 1000: rows off the 128-byte lines (line-aligned pieces through a ring).
+    ns = 1 << 20
     g = G.Generator(ns, "v2", seed=1)
     try:
         out = g.generate(n)
@@ -391,9 +397,10 @@ def test_v2_paper_shape_sampled(orc, G, torch):
         g.close()
 
 
+@pytest.mark.parametrize("n", [1024, 1000])
 @pytest.mark.parametrize("variant_name,variant", [("v0", 0), ("v1", 1)])
-def test_plain_paper_shape_sampled(orc, G, torch, variant_name, variant):
-    ns, n = 1 << 20, 1024
+def test_plain_paper_shape_sampled(orc, G, torch, variant_name, variant, n):
+    ns = 1 << 20
     g = G.Generator(ns, variant_name, seed=1)
     try:
         out = g.generate(n)
