@@ -243,6 +243,24 @@ def run_plain(torch, G, variant, args, interleaved=False):
             "frac_hbm_peak": round(byts / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def run_rows_off_lines(torch, G, args):
+    """Stream-major rows that start off 128-byte lines (n = 1000: 16-byte
+    aligned rows; n = 1001: 4-byte aligned), stored in line-aligned pieces."""
+    ns = 1 << 20
+    res = {"workload": "2^20 streams, stream-major, default launch, rows of 1000 and 1001 words"}
+    for variant, words in (("v0", 5), ("v2", 6)):
+        g = G.Generator(ns, variant, seed=1)
+        for n in (1000, 1001):
+            out = torch.empty((ns, n), dtype=torch.int32, device="cuda")
+            ms, _ = timed(torch, lambda: g.generate(n, out=out), max(5, args.steps // 2), 40)
+            del out
+            byts = ns * n * 4 + ns * words * 8
+            res[f"{variant}_n{n}"] = {"ms": round(ms, 4), "hbm_gbs": round(byts / (ms / 1e3) / 1e9, 1),
+                                      "frac_hbm_peak": round(byts / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        g.close()
+    return res
+
+
 def _tune_ragged(g, lengths, out, args):
     """Run the batched-launch autotuner unless disabled; returns its record."""
     t0 = time.perf_counter()
@@ -577,6 +595,8 @@ def main():
                 if f"{variant}_generate" in ALU_MIX:
                     extra[key]["roofline"] = alu_roofline(extra[key]["gnumbers_per_s"], f"{variant}_generate")
                 log(f"[bench] {key}: {extra[key]}")
+        extra["rows_off_lines"] = run_rows_off_lines(torch, G, args)
+        log(f"[bench] rows off lines: {extra['rows_off_lines']}")
         extra["ragged"] = run_ragged(torch, G, args, extra["v0_stream_major"]["gnumbers_per_s"])
         log(f"[bench] ragged: {extra['ragged']}")
         extra["ragged_groups_v2"] = run_ragged_groups(torch, G, args, extra["v2_stream_major"]["gnumbers_per_s"])
