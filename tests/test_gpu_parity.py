@@ -435,6 +435,24 @@ def test_consume_counts_small(orc, G, variant_name, variant):
         g.close()
 
 
+@pytest.mark.parametrize("exchange", [1, 2])
+@pytest.mark.parametrize("unroll", [8, 16, 32])
+def test_consume_exchange_modes(orc, G, exchange, unroll):
+    # Cross-lane reads or the per-wave LDS word buffer; a partial last wave
+    # (160 streams) and pairs after the last full round (n = 4098).
+    ns, n = 160, 4098
+    g = G.Generator(ns, "v2", seed=5)
+    try:
+        g.set_tuning(exchange=exchange, unroll=unroll)
+        st = _oracle_states(orc, 2, 5, ns)
+        for _ in range(2):
+            got = g.consume_qc(n).cpu().numpy().astype(np.uint64)
+            assert np.array_equal(got, orc.consume_qc(2, st, n))
+        assert np.array_equal(g.get_state(), st)
+    finally:
+        g.close()
+
+
 def test_consume_paper_scale_sampled(orc, G, torch):
     # 2^36 numbers: 2^20 streams x 2^16, exchange variant, seed 3.
     ns, n = 1 << 20, 1 << 16
