@@ -83,7 +83,7 @@ def test_few_streams_defaults_resolved(G, torch):
     cases = [(1024, "v0", (64, 32, 1)), (16384, "v2", (64, 32, 1)), (16384, "v1", (64, 32, 1)),
              (16448, "v0", (64, 32, 2)), (65536, "v2", (64, 32, 2)), (65600, "v2", (256, 32, 2)),
              (98304, "v0", (64, 32, 2)), (98336, "v0", (128, 128, 4)),
-             (81920, "v1", (64, 32, 1)), (81952, "v1", (256, 64, 4))]
+             (81920, "v1", (64, 32, 1)), (81952, "v1", (256, 32, 4))]
     for ns, name, want in cases:
         g = G.Generator(ns, name, seed=0)
         try:
