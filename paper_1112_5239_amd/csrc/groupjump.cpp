@@ -546,13 +546,15 @@ const V1Polys &v1_polys_of(const cprng_t *h)
 // of the chunk kernel's resident waves.  Its time follows whole passes (a
 // last pass that is mostly empty costs a whole chunk's time); the exchange
 // variants want their chunks in one pass (the exchange reads' latency needs
-// many waves; fewer, longer runs in flight store better), V1 in two (its
-// aggregate pass wants the waves).  The 3% slack keeps a workgroup the
-// dispatcher places late from opening another pass.
+// many waves; fewer, longer runs in flight store better), V1 in six (its
+// aggregate pass wants the waves, and shorter chunks even out the lanes'
+// work by more than their extra jumps cost: 4,096 runs log-uniform in
+// 1e3..1e7 took 8.1 ms at six passes against 8.6 at two).  The 3% slack
+// keeps a workgroup the dispatcher places late from opening another pass.
 uint64_t auto_chunk(const cprng_t *h, const uint64_t *lengths, const ChunkCfg &c, uint64_t jump_len)
 {
     if (is_v1(h)) {
-        const uint64_t cap = 2u * (uint64_t)h->n_cu * chunk_resident_waves(c, true) * 64u * 31u / 32u;
+        const uint64_t cap = 6u * (uint64_t)h->n_cu * chunk_resident_waves(c, true) * 64u * 31u / 32u;
         return fit_chunk(16ull * jump_len, cap, [&](uint64_t ch) {
             uint64_t n = 0;
             for (uint32_t s = 0; s < h->ns; ++s) n += (lengths[s] + ch - 1) / ch;
@@ -1008,7 +1010,6 @@ int autotune_chunked(cprng_t *h, uint32_t *out, const uint64_t *lengths, const u
         for (uint32_t W : {1u, 4u})
             for (int pi = 0; pi < n_parts; ++pi)
                 for (int scale = 0; scale < 3; ++scale) {
-                    if (scale == 1 && is_v1(h)) continue;     // V1: automatic and twice that
                     if (!is_v1(h) && K == 128 && W == 4) continue; // group rings of K = 128: one wave per workgroup
                     ChunkCfg c;
                     c.round = K;
