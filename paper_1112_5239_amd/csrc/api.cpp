@@ -181,14 +181,15 @@ int create_impl(const cprng_params_t *p, cprng_t **out)
 // 0.063); beyond that, one-wave LDS tiles of 32 steps for V0 up to six waves
 // per CU (65,600 streams: 0.042 vs 0.082 ms; even at 98,304) and for V2/V4
 // up to four (65,536: V2 0.064 vs 0.071 ms), and for V1 the direct stores up
-// to five (65,600: 0.135 vs 0.145 ms; even at 81,920, slower by 98,304).  The
-// BBS variant keeps its defaults.
+// to six (98,304: 0.150 vs 0.160 ms against the large-shape default of rounds
+// of 32 with no residency cap; slower by 131,072).  The BBS variant keeps its
+// defaults.
 void small_shape_defaults(const cprng_t *h, LaunchCfg &c, TuneEntry &e)
 {
     if (h->variant == CPRNG_V3_BBS || (h->flags & CPRNG_F_INTERLEAVED)) return;
     const uint64_t ns = h->ns, cu = h->n_cu ? h->n_cu : 256u;
     const bool v0 = h->variant == CPRNG_V0_PLAIN, v1 = h->variant == CPRNG_V1_NAIVE3;
-    if (ns <= cu * 64u || (v1 && ns <= cu * 320u)) {
+    if (ns <= cu * 64u || (v1 && ns <= cu * 384u)) {
         c.block = 64; c.unroll = 32; c.store = ST_DIRECT;
     } else if (ns <= cu * (v0 ? 384u : 256u) && !v1) {
         c.block = 64; c.unroll = 32; c.store = ST_LDS;

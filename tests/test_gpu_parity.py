@@ -62,8 +62,8 @@ def test_v0_plain_1024x1024_all_store_modes(orc, G, store, unroll):
 
 
 # The stream-major defaults depend on the stream count: one-wave blocks with
-# direct stores up to one wave per CU (16,384 streams on 256 CUs; V1 up to five,
-# 81,920), one-wave LDS tiles above that (V0 up to six waves per CU, V2 up to
+# direct stores up to one wave per CU (16,384 streams on 256 CUs; V1 up to six,
+# 98,304), one-wave LDS tiles above that (V0 up to six waves per CU, V2 up to
 # four, 65,536), the large-shape defaults beyond.
 def _cu_count(torch):
     return torch.cuda.get_device_properties(0).multi_processor_count
@@ -83,7 +83,7 @@ def test_few_streams_defaults_resolved(G, torch):
     cases = [(1024, "v0", (64, 32, 1)), (16384, "v2", (64, 32, 1)), (16384, "v1", (64, 32, 1)),
              (16448, "v0", (64, 32, 2)), (65536, "v2", (64, 32, 2)), (65600, "v2", (256, 32, 2)),
              (98304, "v0", (64, 32, 2)), (98336, "v0", (128, 128, 4)),
-             (81920, "v1", (64, 32, 1)), (81952, "v1", (256, 32, 4))]
+             (98304, "v1", (64, 32, 1)), (98336, "v1", (256, 32, 4))]
     for ns, name, want in cases:
         g = G.Generator(ns, name, seed=0)
         try:
